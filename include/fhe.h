@@ -1,0 +1,228 @@
+/*
+ * fhe.h -- C ABI of the gfx950 BFV multiply+relinearize and p-ary bridge library.
+ *
+ * Scheme: BFV (Fan-Vercauteren 2012, the BFV citation of the paper's
+ * introduction) in residue-number-system form.  The paper runs BFV through
+ * SEAL and fixes nothing about its internals; the operations below compute the
+ * textbook FV12 results exactly, so every output word is uniquely defined:
+ *
+ *   multiply      C_j = round(t D_j / q) mod q, D the exact integer tensor of the
+ *                 centred lifts (D0 = A0 B0, D1 = A0 B1 + A1 B0, D2 = A1 B1);
+ *   relinearize   c'_l = C_l + sum_i [C2]_{q_i} rlk_i[l]  (mod q), one digit per
+ *                 RNS prime, rlk_i = (-(a_i s + e_i) + eps_i s^2, a_i);
+ *   bridge        the paper's conversion SecureMod -> SecureUint (Section 3.2.3,
+ *                 its equation with Fermat equality tests 1 - (x - c)^(t-1), its
+ *                 pow listing for the power): eq_c for every c in [0, t), then
+ *                 bit j = sum over c in [1, t) with bit j of c set of eq_c.
+ *
+ * Data layout (all words uint64, little endian, canonical residues in [0, q_i)):
+ *   polynomial   [k][n]        limb-major: limb i is n contiguous coefficients
+ *   ciphertext   [2][k][n]     (c0, c1);   a batch is [count][2][k][n]
+ *   public key   [2][k][n]     coefficient form
+ *   relin key    internal, fhe_rlk_words() words, produced only by fhe_keygen or
+ *                fhe_rlk_import (transform domain, resident on the device)
+ *   plaintext    [n] coefficients in [0, t) (host)
+ *
+ * Ownership: the caller allocates every buffer (device buffers with its own
+ * allocator, e.g. torch); the library never keeps a pointer after a call
+ * returns.  Device-side tables belong to the context.  Workspace ("ws") is
+ * caller-provided device memory of at least fhe_workspace_bytes() bytes.
+ *
+ * Streams: every call enqueues its kernels on `stream` (NULL = default stream)
+ * and returns without synchronising, except the calls that return host data
+ * (fhe_decrypt) which synchronise the stream.  Argument and shape errors are
+ * returned synchronously before anything is enqueued; launch failures return
+ * FHE_EDEVICE.  A context is not thread safe: one context per host thread.
+ *
+ * Aliasing: `out` may be exactly `a` or `b` (in-place); any other overlap
+ * between outputs and inputs is undefined.
+ *
+ * Inputs must be canonical residues.  With the environment variable
+ * FHE_VALIDATE=1 the elementwise, multiply and bridge calls check this first
+ * and return FHE_ENONCANON.
+ */
+#ifndef FHE_H
+#define FHE_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FHE_OK = 0,
+    FHE_EINVAL = -1,       /* null pointer, bad count, bad op code, overlap */
+    FHE_EPARAM = -2,       /* parameter set rejected by fhe_ctx_create */
+    FHE_ENOMEM = -3,       /* device allocation of context tables failed */
+    FHE_EDEVICE = -4,      /* HIP error (launch failure, bad device) */
+    FHE_ESHAPE = -5,       /* size arguments inconsistent with the context */
+    FHE_ENONCANON = -6,    /* FHE_VALIDATE: an input word is not < its prime */
+    FHE_EUNSUPPORTED = -7, /* operation not defined for this parameter set */
+    FHE_EWORKSPACE = -8    /* workspace smaller than fhe_workspace_bytes() */
+} fhe_status;
+
+enum { FHE_ENC_SLOTS = 0, FHE_ENC_COEFF = 1 };
+
+/* op codes for fhe_workspace_bytes */
+enum {
+    FHE_OP_MUL_RELIN = 1,
+    FHE_OP_SQUARE_RELIN = 2,
+    FHE_OP_BRIDGE = 3,
+    FHE_OP_KEYGEN = 4,
+    FHE_OP_ENCRYPT = 5,
+    FHE_OP_DECRYPT = 6,
+    FHE_OP_RLK_IMPORT = 7
+};
+
+typedef struct fhe_ctx fhe_ctx;
+
+typedef struct {
+    uint32_t n;        /* ring degree, power of two in [16, 16384] */
+    uint32_t k;        /* number of RNS primes of q, 1..16 */
+    uint64_t t;        /* plaintext modulus, 2 <= t < 2^62, gcd(t, q) = 1 */
+    const uint64_t *q; /* host array of k distinct primes, q_i = 1 mod 2n, q_i < 2^62 */
+    uint32_t encoding; /* FHE_ENC_SLOTS (needs t prime, t = 1 mod 2n) or FHE_ENC_COEFF */
+} fhe_params;
+
+/* Validate parameters and build the context's device tables on `hip_device`.
+ * Rejects (FHE_EPARAM) n not a power of two in [16, 16384], k outside 1..16,
+ * composite / repeated / too large q_i, q_i != 1 mod 2n, gcd(t, q) != 1, and
+ * slot encoding without a prime t = 1 mod 2n.  Parameter checks run before any
+ * device call.  *out is set only on FHE_OK. */
+fhe_status fhe_ctx_create(const fhe_params *params, int hip_device, fhe_ctx **out);
+void fhe_ctx_destroy(fhe_ctx *ctx);
+
+size_t fhe_ct_words(const fhe_ctx *ctx);  /* 2 k n */
+size_t fhe_pk_words(const fhe_ctx *ctx);  /* 2 k n */
+size_t fhe_rlk_words(const fhe_ctx *ctx); /* 2 k^2 n (internal transform domain) */
+/* Number of auxiliary primes the exact multiply extends q with (internal). */
+uint32_t fhe_aux_primes(const fhe_ctx *ctx);
+
+/* Device workspace, in bytes, for `op` on `count` items (ciphertext pairs for
+ * multiply, inputs for the bridge, ciphertexts for encrypt/decrypt). */
+size_t fhe_workspace_bytes(const fhe_ctx *ctx, int op, size_t count);
+
+/* Cap on the number of products one multiply launch sequence processes; larger
+ * counts run in chunks (workspace is sized for min(count, cap)).  0 restores
+ * the default (about 8 GiB of workspace). */
+fhe_status fhe_set_batch_limit(fhe_ctx *ctx, size_t max_items);
+
+/* ---------------------------------------------------------------- keys --- *
+ * Key generation from explicit randomness (host arrays):
+ *   s      int8[n]          secret key, entries in {-1, 0, 1}
+ *   pk_a   uint64[k][n]     uniform residues (public-key mask)
+ *   pk_e   int32[n]         public-key error
+ *   rlk_a  uint64[k][k][n]  mask of relinearization digit i
+ *   rlk_e  int32[k][n]      error of relinearization digit i
+ * Writes pk (device, [2][k][n], coefficient form: pk0 = -(a s + e), pk1 = a) and
+ * rlk (device, internal form).  ws: FHE_OP_KEYGEN bytes. */
+fhe_status fhe_keygen(fhe_ctx *ctx, const int8_t *s, const uint64_t *pk_a, const int32_t *pk_e,
+                      const uint64_t *rlk_a, const int32_t *rlk_e, uint64_t *pk_dev,
+                      uint64_t *rlk_dev, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Convert a relinearization key given in coefficient form, device
+ * uint64[k digits][2][k][n] (rlk_i = (b_i, a_i)), into the internal form used by
+ * fhe_mul_relin.  ws: FHE_OP_RLK_IMPORT bytes. */
+fhe_status fhe_rlk_import(fhe_ctx *ctx, const uint64_t *rlk_coeff_dev, uint64_t *rlk_dev,
+                          void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------ encoding --- *
+ * Host-side plaintext encoding of n values in [0, t).  Slots: m with
+ * m(psi_t^(2j+1)) = vals[j] mod t, psi_t = g^((t-1)/2n) for g the smallest
+ * primitive root of t (3 for t = 65537).  Coefficient: m = vals. */
+fhe_status fhe_encode(const fhe_ctx *ctx, const uint64_t *vals, uint64_t *pt);
+fhe_status fhe_decode(const fhe_ctx *ctx, const uint64_t *pt, uint64_t *vals);
+
+/* ------------------------------------------------------ enc / dec -------- *
+ * ct[j] = ([pk0 u_j + e_j[0] + Delta m_j]_q, [pk1 u_j + e_j[1]]_q), Delta = floor(q/t).
+ *   pt   host uint64[count][n] plaintext polynomials, coefficients < t
+ *   u    host int8[count][n] ternary; e host int32[count][2][n]
+ *   ct   device uint64[count][2][k][n]. ws: FHE_OP_ENCRYPT bytes. */
+fhe_status fhe_encrypt(fhe_ctx *ctx, const uint64_t *pk_dev, const uint64_t *pt, const int8_t *u,
+                       const int32_t *e, uint64_t *ct_dev, size_t count, void *ws,
+                       size_t ws_bytes, hipStream_t stream);
+
+/* pt[j] = [round(t [c0 + c1 s]_q / q)]_t per coefficient (exact).  s host
+ * int8[n]; pt host uint64[count][n].  Synchronises `stream`.
+ * ws: FHE_OP_DECRYPT bytes. */
+fhe_status fhe_decrypt(fhe_ctx *ctx, const int8_t *s, const uint64_t *ct_dev, uint64_t *pt,
+                       size_t count, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* --------------------------------------------------------- elementwise --- *
+ * Batches of `count` ciphertexts, device pointers, modulo each q_i.
+ * add_plain_const / sub_plain_const add / subtract Delta*c to the constant
+ * coefficient of c0 (the encoding of the constant polynomial c, 0 <= c < t). */
+fhe_status fhe_add(fhe_ctx *ctx, const uint64_t *a, const uint64_t *b, uint64_t *out, size_t count,
+                   hipStream_t stream);
+fhe_status fhe_sub(fhe_ctx *ctx, const uint64_t *a, const uint64_t *b, uint64_t *out, size_t count,
+                   hipStream_t stream);
+fhe_status fhe_neg(fhe_ctx *ctx, const uint64_t *a, uint64_t *out, size_t count, hipStream_t stream);
+fhe_status fhe_add_plain_const(fhe_ctx *ctx, const uint64_t *a, uint64_t c, uint64_t *out,
+                               size_t count, hipStream_t stream);
+fhe_status fhe_sub_plain_const(fhe_ctx *ctx, const uint64_t *a, uint64_t c, uint64_t *out,
+                               size_t count, hipStream_t stream);
+
+/* ----------------------------------------------------------- hot path ---- *
+ * out[j] = relinearize(multiply(a[j], b[j])) for j < count, the FV12 product
+ * and one-digit-per-prime key switching (see the top of this file).
+ * a, b, out: device [count][2][k][n]; rlk from fhe_keygen / fhe_rlk_import.
+ * a == b (same pointer) selects the squaring kernels (same result).
+ * count == 0 is a no-op.  ws: FHE_OP_MUL_RELIN (or FHE_OP_SQUARE_RELIN when
+ * a == b) bytes for count. */
+fhe_status fhe_mul_relin(fhe_ctx *ctx, const uint64_t *rlk_dev, const uint64_t *a,
+                         const uint64_t *b, uint64_t *out, size_t count, void *ws,
+                         size_t ws_bytes, hipStream_t stream);
+
+/* The paper's SecureMod -> SecureUint conversion for prime t (Section 3.2.3):
+ * for each input x[j] (device [count][2][k][n]) and each c in [0, t):
+ *   y = x - c (sub_plain_const), y = y^(t-1) by repeated squaring
+ *   (mul_relin, t-1 a power of two: log2(t-1) squarings), eq_c = 1 - y;
+ * bits[j][b] = sum over c in [1, t) with bit b of c set of eq_c, b < nbits.
+ *   bits  device [count][nbits][2][k][n]
+ *   eq    device [count][t][2][k][n], or NULL to skip writing the eq_c
+ * Requires coefficient encoding, t prime, t - 1 a power of two, and
+ * 2^nbits >= t (else FHE_EUNSUPPORTED / FHE_EINVAL).  Inputs should encrypt
+ * constant polynomials (the equality test is coefficient-wise only for
+ * those); the words are defined for any input.  ws: FHE_OP_BRIDGE bytes. */
+fhe_status fhe_bridge_to_bits(fhe_ctx *ctx, const uint64_t *rlk_dev, const uint64_t *x,
+                              uint32_t nbits, uint64_t *bits, uint64_t *eq, size_t count,
+                              void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* The paper's SecureUint -> SecureMod cast (Section 3.2.1, Horner):
+ * out[j] = sum_b 2^b bits[j][b], evaluated as r = bit_{nbits-1}; r = r + r + bit_b.
+ * bits device [count][nbits][2][k][n]; out device [count][2][k][n]. */
+fhe_status fhe_bits_to_mod(fhe_ctx *ctx, const uint64_t *bits, uint32_t nbits, uint64_t *out,
+                           size_t count, hipStream_t stream);
+
+/* ---------------------------------------------------- kernel-level test -- *
+ * Negacyclic transform of `count` polynomials [count][k][n] in place, limb i
+ * modulo q_i with psi_i = x^((q_i-1)/2n) for the smallest x >= 2 giving
+ * psi_i^n = -1.  Forward: position bitrev(j) receives sum_i a_i psi^(i(2j+1)).
+ * Inverse (inverse != 0) undoes it.  Outputs canonical. */
+fhe_status fhe_ntt(fhe_ctx *ctx, int inverse, uint64_t *polys, size_t count, hipStream_t stream);
+
+/* ------------------------------------------------------------- timing ---- *
+ * When enabled, every kernel launch is bracketed by HIP events on its stream
+ * and its duration is accumulated per kernel kind (costs one event pair per
+ * launch; off by default).  fhe_kernel_stats synchronises the events and
+ * returns the total milliseconds and launch count of kernel kind `kind`
+ * (see fhe_kernel_name; kinds are 0 .. fhe_kernel_kinds()-1). */
+fhe_status fhe_set_timing(fhe_ctx *ctx, int enable);
+int fhe_kernel_kinds(void);
+const char *fhe_kernel_name(int kind);
+fhe_status fhe_kernel_stats(fhe_ctx *ctx, int kind, double *total_ms, uint64_t *launches);
+fhe_status fhe_reset_kernel_stats(fhe_ctx *ctx);
+
+/* Number of coefficients that took the exact (multi-word) path in the base
+ * conversions since the context was created (diagnostic; synchronises). */
+fhe_status fhe_fallback_count(fhe_ctx *ctx, uint64_t *count);
+
+const char *fhe_status_str(fhe_status status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FHE_H */

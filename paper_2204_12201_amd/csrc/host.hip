@@ -1,0 +1,990 @@
+// Host side of the C ABI (include/fhe.h): parameter checks, constant tables,
+// workspace layout and the launch sequences of every entry point.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
+#include "fhe.h"
+#include "kernels.hpp"
+#include "modarith.hpp"
+#include "ntt_core.hpp"
+#include "tables.hpp"
+
+namespace {
+
+// ------------------------------------------------------------ host math ----
+
+uint64_t hmul(uint64_t a, uint64_t b, uint64_t m) { return (uint64_t)((u128)a * b % m); }
+
+uint64_t hpow(uint64_t b, uint64_t e, uint64_t m) {
+    uint64_t r = 1 % m;
+    b %= m;
+    while (e) {
+        if (e & 1) r = hmul(r, b, m);
+        b = hmul(b, b, m);
+        e >>= 1;
+    }
+    return r;
+}
+
+uint64_t hgcd(uint64_t a, uint64_t b) {
+    while (b) {
+        uint64_t t = a % b;
+        a = b;
+        b = t;
+    }
+    return a;
+}
+
+// Inverse of a modulo m (gcd(a, m) = 1), extended Euclid in signed 128-bit.
+uint64_t hinv(uint64_t a, uint64_t m) {
+    __int128 t = 0, nt = 1, r = m, nr = a % m;
+    while (nr != 0) {
+        __int128 qq = r / nr, tmp;
+        tmp = t - qq * nt; t = nt; nt = tmp;
+        tmp = r - qq * nr; r = nr; nr = tmp;
+    }
+    if (t < 0) t += m;
+    return (uint64_t)t;
+}
+
+bool is_prime_u64(uint64_t n) {
+    static const uint64_t bases[] = {2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37};
+    if (n < 2) return false;
+    for (uint64_t p : bases)
+        if (n % p == 0) return n == p;
+    uint64_t d = n - 1;
+    int s = 0;
+    while ((d & 1) == 0) { d >>= 1; s++; }
+    for (uint64_t a : bases) {
+        uint64_t x = hpow(a, d, n);
+        if (x == 1 || x == n - 1) continue;
+        bool comp = true;
+        for (int r = 1; r < s; r++) {
+            x = hmul(x, x, n);
+            if (x == n - 1) { comp = false; break; }
+        }
+        if (comp) return false;
+    }
+    return true;
+}
+
+uint64_t shoup(uint64_t w, uint64_t q) { return (uint64_t)(((u128)w << 64) / q); }
+uint64_t mont(uint64_t x, uint64_t q) { return (uint64_t)(((u128)(x % q) << 64) % q); }
+
+uint64_t neg_inv64(uint64_t q) {  // -q^-1 mod 2^64 (q odd), Newton iteration
+    uint64_t x = q;  // q * q = 1 mod 8
+    for (int i = 0; i < 6; i++) x *= 2 - q * x;
+    return (uint64_t)0 - x;
+}
+
+// psi = x^((q-1)/2n) for the smallest x >= 2 with psi^n = -1 mod q.
+uint64_t find_psi(uint64_t q, uint32_t n) {
+    for (uint64_t x = 2;; x++) {
+        uint64_t psi = hpow(x, (q - 1) / (2 * (uint64_t)n), q);
+        if (hpow(psi, n, q) == q - 1) return psi;
+    }
+}
+
+uint32_t bitrev(uint32_t x, int L) {
+    uint32_t r = 0;
+    for (int i = 0; i < L; i++) r |= ((x >> i) & 1u) << (L - 1 - i);
+    return r;
+}
+
+// Smallest primitive root of the prime t (trial-division factorisation of t-1).
+bool primitive_root(uint64_t t, uint64_t *g) {
+    std::vector<uint64_t> f;
+    uint64_t m = t - 1;
+    for (uint64_t p = 2; p * p <= m && p < (1ull << 22); p++) {
+        if (m % p == 0) {
+            f.push_back(p);
+            while (m % p == 0) m /= p;
+        }
+    }
+    if (m > 1) {
+        if (!is_prime_u64(m)) return false;
+        f.push_back(m);
+    }
+    for (uint64_t x = 2; x < t; x++) {
+        bool ok = true;
+        for (uint64_t p : f)
+            if (hpow(x, (t - 1) / p, t) == 1) { ok = false; break; }
+        if (ok) { *g = x; return true; }
+    }
+    return false;
+}
+
+// (M - 1) / 2 modulo m for M the product of `basis`, M odd: ((M mod 2m) - 1) / 2.
+uint64_t half_mod(const std::vector<uint64_t> &basis, uint64_t m) {
+    uint64_t m2 = 2 * m;
+    uint64_t r = 1 % m2;
+    for (uint64_t b : basis) r = hmul(r, b % m2, m2);
+    return ((r + m2 - 1) % m2) / 2;
+}
+
+uint64_t prod_mod(const std::vector<uint64_t> &basis, uint64_t m, int skip = -1) {
+    uint64_t r = 1 % m;
+    for (size_t i = 0; i < basis.size(); i++)
+        if ((int)i != skip) r = hmul(r, basis[i] % m, m);
+    return r;
+}
+
+void build_mrc(MrcConst &M, const std::vector<uint64_t> &basis, const std::vector<uint64_t> &targets) {
+    std::memset(&M, 0, sizeof(M));
+    const int K = (int)basis.size();
+    M.K = (uint32_t)K;
+    M.ntarget = (uint32_t)targets.size();
+    for (int b = 0; b < K; b++) {
+        M.m[b] = basis[b];
+        M.one_p[b] = shoup(1, basis[b]);
+        for (int a = 0; a < b; a++) {
+            M.inv[a][b] = hinv(basis[a] % basis[b], basis[b]);
+            M.inv_p[a][b] = shoup(M.inv[a][b], basis[b]);
+        }
+    }
+    // mixed-radix digits of (M - 1)/2 from its residues (m_b - 1)/2
+    uint64_t d[FHE_MAXB];
+    for (int b = 0; b < K; b++) {
+        const uint64_t mb = basis[b];
+        uint64_t v = (mb - 1) / 2;
+        for (int a = 0; a < b; a++) {
+            v = (v + mb - d[a] % mb) % mb;
+            v = hmul(v, M.inv[a][b], mb);
+        }
+        d[b] = v;
+        M.half_digit[b] = v;
+    }
+    for (size_t j = 0; j < targets.size(); j++) {
+        const uint64_t p = targets[j];
+        M.target[j] = p;
+        M.tgt_one_p[j] = shoup(1, p);
+        for (int b = 0; b < K; b++) {
+            M.m_mod_t[b][j] = basis[b] % p;
+            M.m_mod_t_p[b][j] = shoup(M.m_mod_t[b][j], p);
+        }
+        M.M_mod_t[j] = prod_mod(basis, p);
+    }
+}
+
+// ------------------------------------------------------------------ events --
+
+struct EvPair {
+    hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct fhe_ctx {
+    int device = 0;
+    uint32_t n = 0, L = 0, k = 0, kp = 0, K = 0, encoding = 0;
+    uint64_t t = 0;
+    std::vector<uint64_t> primes;  // Q then P
+    // slot encoding (host)
+    std::vector<uint64_t> enc_tw, enc_itw;
+    uint64_t t_ninv = 0;
+    // device allocations
+    void *d_pc = nullptr, *d_tw = nullptr, *d_itw = nullptr, *d_cc = nullptr;
+    void *d_mrc_q = nullptr, *d_mrc_p = nullptr, *d_counters = nullptr;
+    DevCtx dev{};
+    size_t batch_limit = 0, default_limit = 0;
+    bool validate = false;
+    bool timing = false;
+    std::vector<EvPair> pending[KK_COUNT];
+    std::vector<hipEvent_t> free_events;
+    double total_ms[KK_COUNT] = {};
+    uint64_t launches[KK_COUNT] = {};
+};
+
+namespace {
+
+const char *kKernelNames[KK_COUNT] = {"lift_q2p",     "fwd_ext",  "tensor_intt", "scale_round",
+                                      "relin_digits", "relin_ip", "ntt_rows",    "elementwise",
+                                      "bridge",       "misc"};
+
+hipEvent_t take_event(fhe_ctx *c) {
+    if (!c->free_events.empty()) {
+        hipEvent_t e = c->free_events.back();
+        c->free_events.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Launch through f(), bracketed by events when timing is enabled.
+template <typename F>
+fhe_status run(fhe_ctx *c, int kind, hipStream_t s, F &&f) {
+    EvPair ev{nullptr, nullptr};
+    if (c->timing) {
+        ev.a = take_event(c);
+        ev.b = take_event(c);
+        if (ev.a) hipEventRecord(ev.a, s);
+    }
+    hipError_t e = f();
+    if (c->timing) {
+        if (ev.b) hipEventRecord(ev.b, s);
+        if (ev.a && ev.b) c->pending[kind].push_back(ev);
+        c->launches[kind] += 1;
+    }
+    return e == hipSuccess ? FHE_OK : FHE_EDEVICE;
+}
+
+#define FHE_TRY(expr)                         \
+    do {                                      \
+        fhe_status _st = (expr);              \
+        if (_st != FHE_OK) return _st;        \
+    } while (0)
+
+#define FHE_HIP(expr)                                      \
+    do {                                                   \
+        if ((expr) != hipSuccess) return FHE_EDEVICE;      \
+    } while (0)
+
+size_t ct_words(const fhe_ctx *c) { return 2 * (size_t)c->k * c->n; }
+
+size_t item_words_mul(const fhe_ctx *c, bool square) {
+    const size_t npoly = square ? 2 : 4;
+    size_t regionA = (npoly + 3) * c->K;  // E then Dt; Dhat reuses it when it fits
+    size_t dhat = (size_t)c->k * c->k;
+    if (dhat > regionA) regionA = dhat;
+    return (regionA + c->k) * c->n;
+}
+
+size_t bridge_group(const fhe_ctx *c) {
+    size_t g = c->batch_limit / c->t;
+    return g ? g : 1;
+}
+
+bool overlaps(const void *a, const void *b, size_t bytes) {
+    const char *x = (const char *)a, *y = (const char *)b;
+    return x < y + bytes && y < x + bytes;
+}
+
+bool overlaps2(const void *a, size_t abytes, const void *b, size_t bbytes) {
+    const char *x = (const char *)a, *y = (const char *)b;
+    return x < y + bbytes && y < x + abytes;
+}
+
+fhe_status check_canonical(fhe_ctx *c, const uint64_t *a, size_t nrows, int kmod, int off,
+                           hipStream_t s) {
+    if (!c->validate || nrows == 0) return FHE_OK;
+    unsigned int *flag = (unsigned int *)c->d_counters + 2;
+    FHE_HIP(hipMemsetAsync(flag, 0, sizeof(unsigned int), s));
+    FHE_HIP(launch_validate(c->dev, a, nrows, kmod, off, flag, s));
+    unsigned int h = 0;
+    FHE_HIP(hipMemcpyAsync(&h, flag, sizeof(h), hipMemcpyDeviceToHost, s));
+    FHE_HIP(hipStreamSynchronize(s));
+    return h ? FHE_ENONCANON : FHE_OK;
+}
+
+// The product pipeline on `count` items with workspace for min(count, limit).
+fhe_status mul_relin_impl(fhe_ctx *c, const uint64_t *rlk, const uint64_t *a, const uint64_t *b,
+                          uint64_t *out, size_t count, void *ws, hipStream_t s) {
+    const bool square = (a == b);
+    const int npoly = square ? 2 : 4;
+    const size_t n = c->n, K = c->K, k = c->k, ctw = ct_words(c);
+    const size_t chunk = c->batch_limit;
+    for (size_t off = 0; off < count; off += chunk) {
+        const size_t items = count - off < chunk ? count - off : chunk;
+        const uint64_t *ai = a + off * ctw;
+        const uint64_t *bi = b + off * ctw;
+        uint64_t *oi = out + off * ctw;
+        uint64_t *E = (uint64_t *)ws;
+        uint64_t *Dt = E + items * npoly * K * n;
+        size_t regionA = (npoly + 3) * K;
+        if ((size_t)k * k > regionA) regionA = k * k;
+        uint64_t *C2 = E + items * regionA * n;
+        uint64_t *Dhat = E;  // E and Dt are dead once C2 is formed
+        const DevCtx &d = c->dev;
+        FHE_TRY(run(c, KK_LIFT, s, [&] { return launch_lift(d, ai, bi, E, npoly, items, s); }));
+        FHE_TRY(run(c, KK_FWD_EXT, s, [&] { return launch_fwd_ext(d, ai, bi, E, npoly, items, s); }));
+        FHE_TRY(run(c, KK_TENSOR_INTT, s, [&] { return launch_tensor_intt(d, E, Dt, square, items, s); }));
+        FHE_TRY(run(c, KK_SCALE, s, [&] { return launch_scale(d, Dt, oi, C2, items, s); }));
+        FHE_TRY(run(c, KK_RELIN_DIGITS, s, [&] { return launch_relin_digits(d, C2, Dhat, items, s); }));
+        FHE_TRY(run(c, KK_RELIN_IP, s, [&] { return launch_relin_ip(d, Dhat, rlk, oi, items, s); }));
+    }
+    return FHE_OK;
+}
+
+fhe_status alloc_copy(void **dst, const void *src, size_t bytes) {
+    if (hipMalloc(dst, bytes) != hipSuccess) {
+        *dst = nullptr;
+        return FHE_ENOMEM;
+    }
+    if (hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice) != hipSuccess) return FHE_EDEVICE;
+    return FHE_OK;
+}
+
+void release(fhe_ctx *c) {
+    void *ptrs[] = {c->d_pc, c->d_tw, c->d_itw, c->d_cc, c->d_mrc_q, c->d_mrc_p, c->d_counters};
+    for (void *p : ptrs)
+        if (p) hipFree(p);
+    for (int i = 0; i < KK_COUNT; i++)
+        for (auto &e : c->pending[i]) {
+            hipEventDestroy(e.a);
+            hipEventDestroy(e.b);
+        }
+    for (auto e : c->free_events) hipEventDestroy(e);
+}
+
+// Host slot transforms modulo t (merged-psi Cooley-Tukey / Gentleman-Sande).
+void host_fwd_mod_t(std::vector<uint64_t> &a, const std::vector<uint64_t> &tw, uint64_t t) {
+    const size_t n = a.size();
+    size_t len = n;
+    for (size_t m = 1; m < n; m <<= 1) {
+        len >>= 1;
+        for (size_t i = 0; i < m; i++) {
+            const size_t j1 = 2 * i * len;
+            const uint64_t S = tw[m + i];
+            for (size_t j = j1; j < j1 + len; j++) {
+                const uint64_t U = a[j], V = hmul(a[j + len], S, t);
+                a[j] = (U + V) % t;
+                a[j + len] = (U + t - V) % t;
+            }
+        }
+    }
+}
+
+void host_inv_mod_t(std::vector<uint64_t> &a, const std::vector<uint64_t> &itw, uint64_t t,
+                    uint64_t ninv) {
+    const size_t n = a.size();
+    size_t len = 1;
+    for (size_t m = n; m > 1; m >>= 1) {
+        size_t j1 = 0;
+        const size_t h = m >> 1;
+        for (size_t i = 0; i < h; i++) {
+            const uint64_t S = itw[h + i];
+            for (size_t j = j1; j < j1 + len; j++) {
+                const uint64_t U = a[j], V = a[j + len];
+                a[j] = (U + V) % t;
+                a[j + len] = hmul((U + t - V) % t, S, t);
+            }
+            j1 += 2 * len;
+        }
+        len <<= 1;
+    }
+    for (auto &v : a) v = hmul(v, ninv, t);
+}
+
+}  // namespace
+
+// =================================================================== ABI ====
+
+extern "C" {
+
+const char *fhe_status_str(fhe_status s) {
+    switch (s) {
+        case FHE_OK: return "ok";
+        case FHE_EINVAL: return "invalid argument";
+        case FHE_EPARAM: return "parameter set rejected";
+        case FHE_ENOMEM: return "device allocation failed";
+        case FHE_EDEVICE: return "HIP error";
+        case FHE_ESHAPE: return "shape mismatch";
+        case FHE_ENONCANON: return "non-canonical input word";
+        case FHE_EUNSUPPORTED: return "operation not supported for these parameters";
+        case FHE_EWORKSPACE: return "workspace too small";
+    }
+    return "unknown status";
+}
+
+fhe_status fhe_ctx_create(const fhe_params *p, int hip_device, fhe_ctx **out) {
+    if (!p || !out || !p->q) return FHE_EINVAL;
+    const uint32_t n = p->n, k = p->k;
+    if (n < 16 || n > 16384 || (n & (n - 1))) return FHE_EPARAM;
+    if (k < 1 || k > (uint32_t)FHE_MAXK) return FHE_EPARAM;
+    if (p->t < 2 || p->t >= (1ull << 62)) return FHE_EPARAM;
+    if (p->encoding != FHE_ENC_SLOTS && p->encoding != FHE_ENC_COEFF) return FHE_EPARAM;
+    std::vector<uint64_t> qs(p->q, p->q + k);
+    double log2q = 0;
+    for (uint32_t i = 0; i < k; i++) {
+        const uint64_t qi = qs[i];
+        if (qi < 3 || qi >= (1ull << 62) || qi % (2ull * n) != 1 || !is_prime_u64(qi)) return FHE_EPARAM;
+        for (uint32_t j = 0; j < i; j++)
+            if (qs[j] == qi) return FHE_EPARAM;
+        if (hgcd(p->t, qi) != 1) return FHE_EPARAM;
+        log2q += std::log2((double)qi);
+    }
+    if (p->encoding == FHE_ENC_SLOTS && (!is_prime_u64(p->t) || p->t % (2ull * n) != 1)) return FHE_EPARAM;
+
+    // Auxiliary primes: the largest primes below 2^61 that are 1 mod 2n and not
+    // in Q, until P > 4 t n q (the scaled tensor is then unique modulo P).
+    std::vector<uint64_t> ps;
+    const double need = std::log2((double)p->t) + std::log2((double)n) + log2q + 2.0;
+    double have = 0;
+    const uint64_t step = 2ull * n;
+    uint64_t cand = ((1ull << 61) - 2) / step * step + 1;
+    while (have < need) {
+        if (ps.size() >= (size_t)FHE_MAXKP || cand < (1ull << 59)) return FHE_EPARAM;
+        bool inq = false;
+        for (uint64_t qi : qs) inq |= (qi == cand);
+        if (!inq && is_prime_u64(cand) && hgcd(p->t, cand) == 1) {
+            ps.push_back(cand);
+            have += std::log2((double)cand);
+        }
+        cand -= step;
+    }
+
+    fhe_ctx *c = new fhe_ctx();
+    c->n = n;
+    c->k = k;
+    c->kp = (uint32_t)ps.size();
+    c->K = c->k + c->kp;
+    c->t = p->t;
+    c->encoding = p->encoding;
+    c->device = hip_device;
+    for (int L = 0; L < 32; L++)
+        if ((1u << L) == n) c->L = L;
+    c->primes = qs;
+    c->primes.insert(c->primes.end(), ps.begin(), ps.end());
+    const char *v = std::getenv("FHE_VALIDATE");
+    c->validate = v && v[0] == '1';
+
+    // slot transform tables (host)
+    if (c->encoding == FHE_ENC_SLOTS) {
+        uint64_t g = 0;
+        if (!primitive_root(c->t, &g)) {
+            delete c;
+            return FHE_EPARAM;
+        }
+        const uint64_t psi = hpow(g, (c->t - 1) / (2 * (uint64_t)n), c->t);
+        const uint64_t ipsi = hinv(psi, c->t);
+        c->enc_tw.resize(n);
+        c->enc_itw.resize(n);
+        for (uint32_t i = 0; i < n; i++) {
+            c->enc_tw[i] = hpow(psi, bitrev(i, c->L), c->t);
+            c->enc_itw[i] = hpow(ipsi, bitrev(i, c->L), c->t);
+        }
+        c->t_ninv = hinv(n % c->t, c->t);
+    }
+
+    // ---- device tables ----
+    std::vector<PrimeConst> pc(c->K);
+    std::vector<Tw> tw((size_t)c->K * n), itw((size_t)c->K * n);
+    for (uint32_t l = 0; l < c->K; l++) {
+        const uint64_t q = c->primes[l];
+        PrimeConst &P = pc[l];
+        std::memset(&P, 0, sizeof(P));
+        P.q = q;
+        P.qinv_neg = neg_inv64(q);
+        P.one_p = shoup(1, q);
+        P.ninv = hinv(n % q, q);
+        P.ninv_p = shoup(P.ninv, q);
+        P.ninvm = mont(P.ninv, q);
+        P.ninvm_p = shoup(P.ninvm, q);
+        const uint64_t psi = find_psi(q, n), ipsi = hinv(psi, q);
+        std::vector<uint64_t> pw(n), ipw(n);
+        pw[0] = 1;
+        ipw[0] = 1;
+        for (uint32_t i = 1; i < n; i++) {
+            pw[i] = hmul(pw[i - 1], psi, q);
+            ipw[i] = hmul(ipw[i - 1], ipsi, q);
+        }
+        for (uint32_t i = 0; i < n; i++) {
+            const uint32_t r = bitrev(i, c->L);
+            tw[(size_t)l * n + i] = Tw{pw[r], shoup(pw[r], q)};
+            itw[(size_t)l * n + i] = Tw{ipw[r], shoup(ipw[r], q)};
+        }
+    }
+
+    ConvConst *cc = new ConvConst();
+    std::memset(cc, 0, sizeof(ConvConst));
+    cc->k = k;
+    cc->kp = c->kp;
+    cc->t = c->t;
+    const uint64_t t = c->t;
+    for (uint32_t i = 0; i < k; i++) {
+        const uint64_t qi = qs[i];
+        const uint64_t qhat_i = prod_mod(qs, qi, (int)i);
+        const uint64_t qhinv = hinv(qhat_i, qi);
+        cc->qhinv[i] = qhinv;
+        cc->qhinv_p[i] = shoup(qhinv, qi);
+        cc->inv_q[i] = 1.0 / (double)qi;
+        const uint64_t tq = t % qi;
+        cc->tqhinv[i] = hmul(tq, qhinv, qi);
+        cc->tqhinv_p[i] = shoup(cc->tqhinv[i], qi);
+        const uint64_t hq = (qi - 1) / 2;  // (q - 1)/2 = -1/2 modulo q_i
+        cc->hqhinv[i] = hmul(hq, qhinv, qi);
+        cc->h_q[i] = hq;
+        cc->t_q[i] = tq;
+        cc->t_qs[i] = shoup(tq, qi);
+        // Delta = floor(q/t) = (q - [q]_t)/t = -[q]_t t^-1 modulo q_i
+        const uint64_t q_mod_t = prod_mod(qs, t);
+        const uint64_t dq = hmul((qi - q_mod_t % qi) % qi, hinv(tq, qi), qi);
+        cc->delta_q[i] = dq;
+        cc->delta_qs[i] = shoup(dq, qi);
+        for (uint32_t j = 0; j < c->kp; j++) {
+            const uint64_t pj = ps[j];
+            cc->qhat_pm[i][j] = mont(prod_mod(qs, pj, (int)i), pj);
+            const uint64_t qiinv = hinv(qi % pj, pj);
+            cc->nqinv_pm[i][j] = mont((pj - qiinv) % pj, pj);
+        }
+    }
+    for (uint32_t j = 0; j < c->kp; j++) {
+        const uint64_t pj = ps[j];
+        const uint64_t qmod = prod_mod(qs, pj);
+        for (uint32_t beta = 0; beta <= k; beta++) cc->beta_q_p[beta][j] = hmul(beta, qmod, pj);
+        const uint64_t qinv = hinv(qmod, pj);
+        const uint64_t hp = half_mod(qs, pj);
+        cc->tqinv_p[j] = hmul(t % pj, qinv, pj);
+        cc->tqinv_ps[j] = shoup(cc->tqinv_p[j], pj);
+        cc->hqinv_p[j] = hmul(hp, qinv, pj);
+        cc->h_p[j] = hp;
+        cc->t_p[j] = t % pj;
+        cc->t_ps[j] = shoup(t % pj, pj);
+        cc->qinv_p[j] = qinv;
+        cc->qinv_ps[j] = shoup(qinv, pj);
+        const uint64_t phat = prod_mod(ps, pj, (int)j);
+        cc->phinv[j] = hinv(phat, pj);
+        cc->phinv_p[j] = shoup(cc->phinv[j], pj);
+        cc->inv_p[j] = 1.0 / (double)pj;
+        for (uint32_t i = 0; i < k; i++) cc->phat_qm[j][i] = mont(prod_mod(ps, qs[i], (int)j), qs[i]);
+    }
+    for (uint32_t i = 0; i < k; i++) {
+        const uint64_t pmod = prod_mod(ps, qs[i]);
+        for (uint32_t beta = 0; beta <= c->kp; beta++) cc->beta_p_q[beta][i] = hmul(beta, pmod, qs[i]);
+    }
+    cc->h_t = half_mod(qs, t);
+    cc->qinv_t = hinv(prod_mod(qs, t), t);
+    cc->qinv_ts = shoup(cc->qinv_t, t);
+    cc->t_one_p = shoup(1, t);
+
+    MrcConst *mq = new MrcConst(), *mp = new MrcConst();
+    std::vector<uint64_t> tq_targets(ps);
+    tq_targets.push_back(t);
+    build_mrc(*mq, qs, tq_targets);
+    build_mrc(*mp, ps, qs);
+
+    fhe_status st = FHE_OK;
+    if (hipSetDevice(hip_device) != hipSuccess) st = FHE_EDEVICE;
+    if (st == FHE_OK) st = alloc_copy(&c->d_pc, pc.data(), pc.size() * sizeof(PrimeConst));
+    if (st == FHE_OK) st = alloc_copy(&c->d_tw, tw.data(), tw.size() * sizeof(Tw));
+    if (st == FHE_OK) st = alloc_copy(&c->d_itw, itw.data(), itw.size() * sizeof(Tw));
+    if (st == FHE_OK) st = alloc_copy(&c->d_cc, cc, sizeof(ConvConst));
+    if (st == FHE_OK) st = alloc_copy(&c->d_mrc_q, mq, sizeof(MrcConst));
+    if (st == FHE_OK) st = alloc_copy(&c->d_mrc_p, mp, sizeof(MrcConst));
+    if (st == FHE_OK) {
+        uint64_t zeros[4] = {0, 0, 0, 0};
+        st = alloc_copy(&c->d_counters, zeros, sizeof(zeros));
+    }
+    delete cc;
+    delete mq;
+    delete mp;
+    if (st != FHE_OK) {
+        release(c);
+        delete c;
+        return st;
+    }
+    DevCtx &d = c->dev;
+    d.n = (int)n;
+    d.L = (int)c->L;
+    d.k = (int)k;
+    d.kp = (int)c->kp;
+    d.K = (int)c->K;
+    d.t = c->t;
+    d.pc = (const PrimeConst *)c->d_pc;
+    d.tw = (const Tw *)c->d_tw;
+    d.itw = (const Tw *)c->d_itw;
+    d.cc = (const ConvConst *)c->d_cc;
+    d.mrc_q = (const MrcConst *)c->d_mrc_q;
+    d.mrc_p = (const MrcConst *)c->d_mrc_p;
+    d.fallback = (unsigned long long *)c->d_counters;
+    // default chunk: about 8 GiB of product workspace
+    size_t per = item_words_mul(c, false) * 8;
+    c->default_limit = ((size_t)8 << 30) / per;
+    if (c->default_limit < 1) c->default_limit = 1;
+    if (c->default_limit > 65535) c->default_limit = 65535;
+    c->batch_limit = c->default_limit;
+    *out = c;
+    return FHE_OK;
+}
+
+void fhe_ctx_destroy(fhe_ctx *c) {
+    if (!c) return;
+    hipDeviceSynchronize();
+    release(c);
+    delete c;
+}
+
+size_t fhe_ct_words(const fhe_ctx *c) { return c ? ct_words(c) : 0; }
+size_t fhe_pk_words(const fhe_ctx *c) { return c ? ct_words(c) : 0; }
+size_t fhe_rlk_words(const fhe_ctx *c) { return c ? 2 * (size_t)c->k * c->k * c->n : 0; }
+uint32_t fhe_aux_primes(const fhe_ctx *c) { return c ? c->kp : 0; }
+
+size_t fhe_workspace_bytes(const fhe_ctx *c, int op, size_t count) {
+    if (!c) return 0;
+    const size_t n = c->n, k = c->k;
+    const size_t lim = c->batch_limit;
+    switch (op) {
+        case FHE_OP_MUL_RELIN:
+        case FHE_OP_SQUARE_RELIN: {
+            const size_t items = count < lim ? count : lim;
+            return items * item_words_mul(c, op == FHE_OP_SQUARE_RELIN) * 8;
+        }
+        case FHE_OP_BRIDGE: {
+            size_t g = bridge_group(c);
+            if (count < g) g = count;
+            const size_t chains = g * c->t;
+            return (chains * ct_words(c) + chains * item_words_mul(c, true)) * 8;
+        }
+        case FHE_OP_KEYGEN:
+            return (6 * k * n) * 8 + n + 4 * n + k * n * 8 + 4 * n + 64;
+        case FHE_OP_ENCRYPT:
+            return (2 * k * n + count * k * n + count * 2 * k * n + count * n) * 8 + count * n +
+                   count * 2 * n * 4 + 256;
+        case FHE_OP_DECRYPT:
+            return (k * n + 2 * count * k * n + count * n) * 8 + n + 256;
+        case FHE_OP_RLK_IMPORT:
+            return 0;
+    }
+    return 0;
+}
+
+fhe_status fhe_set_batch_limit(fhe_ctx *c, size_t max_items) {
+    if (!c) return FHE_EINVAL;
+    c->batch_limit = max_items ? (max_items > 65535 ? 65535 : max_items) : c->default_limit;
+    return FHE_OK;
+}
+
+// ------------------------------------------------------------------ keys ----
+
+fhe_status fhe_keygen(fhe_ctx *c, const int8_t *s, const uint64_t *pk_a, const int32_t *pk_e,
+                      const uint64_t *rlk_a, const int32_t *rlk_e, uint64_t *pk_dev, uint64_t *rlk_dev,
+                      void *ws, size_t ws_bytes, hipStream_t st) {
+    if (!c || !s || !pk_a || !pk_e || !rlk_a || !rlk_e || !pk_dev || !rlk_dev || !ws) return FHE_EINVAL;
+    if (ws_bytes < fhe_workspace_bytes(c, FHE_OP_KEYGEN, 1)) return FHE_EWORKSPACE;
+    const size_t n = c->n, k = c->k, kn = k * n;
+    uint64_t *S = (uint64_t *)ws, *A = S + kn, *prod = A + kn, *Er = prod + kn, *S2 = Er + kn,
+             *tmp = S2 + kn;
+    int8_t *s_dev = (int8_t *)(tmp + kn);
+    int32_t *e_dev = (int32_t *)(s_dev + ((n + 63) & ~(size_t)63));
+    const DevCtx &d = c->dev;
+    FHE_HIP(hipMemcpyAsync(s_dev, s, n, hipMemcpyHostToDevice, st));
+    FHE_TRY(run(c, KK_MISC, st, [&] { return launch_small_to_rns(d, s_dev, 1, S, 1, st); }));
+    FHE_TRY(run(c, KK_NTT_ROWS, st, [&] { return launch_ntt_rows(d, S, k, k, 0, NTT_FWD, st); }));
+    // pk0 = -(a s + e), pk1 = a
+    FHE_HIP(hipMemcpyAsync(A, pk_a, kn * 8, hipMemcpyHostToDevice, st));
+    FHE_HIP(hipMemcpyAsync(pk_dev + kn, pk_a, kn * 8, hipMemcpyHostToDevice, st));
+    FHE_TRY(run(c, KK_NTT_ROWS, st, [&] { return launch_ntt_rows(d, A, k, k, 0, NTT_FWD, st); }));
+    FHE_TRY(run(c, KK_MISC, st, [&] { return launch_pointwise_mont(d, A, S, prod, k, 0, st); }));
+    FHE_TRY(run(c, KK_NTT_ROWS, st, [&] { return launch_ntt_rows(d, prod, k, k, 0, NTT_INV_MONT, st); }));
+    FHE_HIP(hipMemcpyAsync(e_dev, pk_e, n * 4, hipMemcpyHostToDevice, st));
+    FHE_TRY(run(c, KK_MISC, st, [&] { return launch_small_to_rns(d, e_dev, 0, Er, 1, st); }));
+    FHE_TRY(run(c, KK_MISC, st, [&] { return launch_key_b(d, prod, Er, nullptr, -1, pk_dev, st); }));
+    // s^2 (coefficient form)
+    FHE_TRY(run(c, KK_MISC, st, [&] { return launch_pointwise_mont(d, S, S, S2, k, 0, st); }));
+    FHE_TRY(run(c, KK_NTT_ROWS, st, [&] { return launch_ntt_rows(d, S2, k, k, 0, NTT_INV_MONT, st); }));
+    // rlk_i = (-(a_i s + e_i) + eps_i s^2, a_i), built in coefficient form in rlk_dev
+    for (size_t i = 0; i < k; i++) {
+        uint64_t *b_i = rlk_dev + (i * 2 + 0) * kn;
+        uint64_t *a_i = rlk_dev + (i * 2 + 1) * kn;
+        FHE_HIP(hipMemcpyAsync(A, rlk_a + i * kn, kn * 8, hipMemcpyHostToDevice, st));
+        FHE_HIP(hipMemcpyAsync(a_i, rlk_a + i * kn, kn * 8, hipMemcpyHostToDevice, st));
+        FHE_TRY(run(c, KK_NTT_ROWS, st, [&] { return launch_ntt_rows(d, A, k, k, 0, NTT_FWD, st); }));
+        FHE_TRY(run(c, KK_MISC, st, [&] { return launch_pointwise_mont(d, A, S, prod, k, 0, st); }));
+        FHE_TRY(run(c, KK_NTT_ROWS, st, [&] { return launch_ntt_rows(d, prod, k, k, 0, NTT_INV_MONT, st); }));
+        FHE_HIP(hipMemcpyAsync(e_dev, rlk_e + i * n, n * 4, hipMemcpyHostToDevice, st));
+        FHE_TRY(run(c, KK_MISC, st, [&] { return launch_small_to_rns(d, e_dev, 0, Er, 1, st); }));
+        FHE_TRY(run(c, KK_MISC, st, [&] { return launch_key_b(d, prod, Er, S2, (int)i, b_i, st); }));
+        // the staging buffers are reused next iteration: wait for this one
+        FHE_HIP(hipStreamSynchronize(st));
+    }
+    FHE_TRY(run(c, KK_NTT_ROWS, st,
+                [&] { return launch_ntt_rows(d, rlk_dev, 2 * k * k, k, 0, NTT_FWD_NINVM, st); }));
+    FHE_HIP(hipStreamSynchronize(st));
+    return FHE_OK;
+}
+
+fhe_status fhe_rlk_import(fhe_ctx *c, const uint64_t *rlk_coeff, uint64_t *rlk_dev, void *ws,
+                          size_t ws_bytes, hipStream_t st) {
+    (void)ws;
+    (void)ws_bytes;
+    if (!c || !rlk_coeff || !rlk_dev) return FHE_EINVAL;
+    const size_t words = fhe_rlk_words(c);
+    if (rlk_coeff != rlk_dev) {
+        if (overlaps(rlk_coeff, rlk_dev, words * 8)) return FHE_EINVAL;
+        FHE_HIP(hipMemcpyAsync(rlk_dev, rlk_coeff, words * 8, hipMemcpyDeviceToDevice, st));
+    }
+    FHE_TRY(check_canonical(c, rlk_dev, 2 * (size_t)c->k * c->k, c->k, 0, st));
+    return run(c, KK_NTT_ROWS, st, [&] {
+        return launch_ntt_rows(c->dev, rlk_dev, 2 * (size_t)c->k * c->k, c->k, 0, NTT_FWD_NINVM, st);
+    });
+}
+
+// -------------------------------------------------------------- encoding ----
+
+fhe_status fhe_encode(const fhe_ctx *c, const uint64_t *vals, uint64_t *pt) {
+    if (!c || !vals || !pt) return FHE_EINVAL;
+    const size_t n = c->n;
+    if (c->encoding == FHE_ENC_COEFF) {
+        for (size_t i = 0; i < n; i++) pt[i] = vals[i] % c->t;
+        return FHE_OK;
+    }
+    std::vector<uint64_t> a(n);
+    for (size_t j = 0; j < n; j++) a[bitrev((uint32_t)j, c->L)] = vals[j] % c->t;
+    host_inv_mod_t(a, c->enc_itw, c->t, c->t_ninv);
+    std::memcpy(pt, a.data(), n * 8);
+    return FHE_OK;
+}
+
+fhe_status fhe_decode(const fhe_ctx *c, const uint64_t *pt, uint64_t *vals) {
+    if (!c || !vals || !pt) return FHE_EINVAL;
+    const size_t n = c->n;
+    if (c->encoding == FHE_ENC_COEFF) {
+        for (size_t i = 0; i < n; i++) vals[i] = pt[i] % c->t;
+        return FHE_OK;
+    }
+    std::vector<uint64_t> a(pt, pt + n);
+    for (auto &v : a) v %= c->t;
+    host_fwd_mod_t(a, c->enc_tw, c->t);
+    for (size_t j = 0; j < n; j++) vals[j] = a[bitrev((uint32_t)j, c->L)];
+    return FHE_OK;
+}
+
+// ------------------------------------------------------------- enc / dec ----
+
+fhe_status fhe_encrypt(fhe_ctx *c, const uint64_t *pk_dev, const uint64_t *pt, const int8_t *u,
+                       const int32_t *e, uint64_t *ct_dev, size_t count, void *ws, size_t ws_bytes,
+                       hipStream_t st) {
+    if (!c) return FHE_EINVAL;
+    if (count == 0) return FHE_OK;
+    if (!pk_dev || !pt || !u || !e || !ct_dev || !ws) return FHE_EINVAL;
+    if (ws_bytes < fhe_workspace_bytes(c, FHE_OP_ENCRYPT, count)) return FHE_EWORKSPACE;
+    for (size_t i = 0; i < count * c->n; i++)
+        if (pt[i] >= c->t) return FHE_EINVAL;
+    const size_t n = c->n, k = c->k, kn = k * n;
+    uint64_t *PK = (uint64_t *)ws, *U = PK + 2 * kn, *prod = U + count * kn, *pt_dev = prod + 2 * count * kn;
+    int8_t *u_dev = (int8_t *)(pt_dev + count * n);
+    int32_t *e_dev = (int32_t *)(u_dev + ((count * n + 63) & ~(size_t)63));
+    const DevCtx &d = c->dev;
+    FHE_HIP(hipMemcpyAsync(PK, pk_dev, 2 * kn * 8, hipMemcpyDeviceToDevice, st));
+    FHE_TRY(run(c, KK_NTT_ROWS, st, [&] { return launch_ntt_rows(d, PK, 2 * k, k, 0, NTT_FWD, st); }));
+    FHE_HIP(hipMemcpyAsync(u_dev, u, count * n, hipMemcpyHostToDevice, st));
+    FHE_TRY(run(c, KK_MISC, st, [&] { return launch_small_to_rns(d, u_dev, 1, U, count, st); }));
+    FHE_TRY(run(c, KK_NTT_ROWS, st, [&] { return launch_ntt_rows(d, U, count * k, k, 0, NTT_FWD, st); }));
+    for (int p = 0; p < 2; p++) {
+        uint64_t *dst = prod + p * count * kn;
+        FHE_TRY(run(c, KK_MISC, st,
+                    [&] { return launch_pointwise_mont(d, U, PK + p * kn, dst, count * k, 1, st); }));
+    }
+    FHE_TRY(run(c, KK_NTT_ROWS, st,
+                [&] { return launch_ntt_rows(d, prod, 2 * count * k, k, 0, NTT_INV_MONT, st); }));
+    FHE_HIP(hipMemcpyAsync(e_dev, e, count * 2 * n * 4, hipMemcpyHostToDevice, st));
+    FHE_HIP(hipMemcpyAsync(pt_dev, pt, count * n * 8, hipMemcpyHostToDevice, st));
+    FHE_TRY(run(c, KK_MISC, st, [&] { return launch_encrypt_finish(d, prod, e_dev, pt_dev, ct_dev, count, st); }));
+    FHE_HIP(hipStreamSynchronize(st));
+    return FHE_OK;
+}
+
+fhe_status fhe_decrypt(fhe_ctx *c, const int8_t *s, const uint64_t *ct_dev, uint64_t *pt, size_t count,
+                       void *ws, size_t ws_bytes, hipStream_t st) {
+    if (!c) return FHE_EINVAL;
+    if (count == 0) return FHE_OK;
+    if (!s || !ct_dev || !pt || !ws) return FHE_EINVAL;
+    if (ws_bytes < fhe_workspace_bytes(c, FHE_OP_DECRYPT, count)) return FHE_EWORKSPACE;
+    const size_t n = c->n, k = c->k, kn = k * n;
+    uint64_t *S = (uint64_t *)ws, *C1 = S + kn, *X = C1 + count * kn, *pt_dev = X + count * kn;
+    int8_t *s_dev = (int8_t *)(pt_dev + count * n);
+    const DevCtx &d = c->dev;
+    FHE_HIP(hipMemcpyAsync(s_dev, s, n, hipMemcpyHostToDevice, st));
+    FHE_TRY(run(c, KK_MISC, st, [&] { return launch_small_to_rns(d, s_dev, 1, S, 1, st); }));
+    FHE_TRY(run(c, KK_NTT_ROWS, st, [&] { return launch_ntt_rows(d, S, k, k, 0, NTT_FWD, st); }));
+    // C1 <- c1 of every ciphertext, X <- c1 s
+    FHE_HIP(hipMemcpy2DAsync(C1, kn * 8, ct_dev + kn, 2 * kn * 8, kn * 8, count, hipMemcpyDeviceToDevice, st));
+    FHE_TRY(run(c, KK_NTT_ROWS, st, [&] { return launch_ntt_rows(d, C1, count * k, k, 0, NTT_FWD, st); }));
+    FHE_TRY(run(c, KK_MISC, st, [&] { return launch_pointwise_mont(d, C1, S, X, count * k, 1, st); }));
+    FHE_TRY(run(c, KK_NTT_ROWS, st, [&] { return launch_ntt_rows(d, X, count * k, k, 0, NTT_INV_MONT, st); }));
+    // X <- X + c0
+    FHE_HIP(hipMemcpy2DAsync(C1, kn * 8, ct_dev, 2 * kn * 8, kn * 8, count, hipMemcpyDeviceToDevice, st));
+    FHE_TRY(run(c, KK_ELEMENTWISE, st, [&] { return launch_addsub(d, X, C1, X, count * k, 0, st); }));
+    FHE_TRY(run(c, KK_MISC, st, [&] { return launch_decrypt_scale(d, X, pt_dev, count, st); }));
+    FHE_HIP(hipMemcpyAsync(pt, pt_dev, count * n * 8, hipMemcpyDeviceToHost, st));
+    FHE_HIP(hipStreamSynchronize(st));
+    return FHE_OK;
+}
+
+// ----------------------------------------------------------- elementwise ----
+
+static fhe_status addsub_common(fhe_ctx *c, const uint64_t *a, const uint64_t *b, uint64_t *out,
+                                size_t count, int op, hipStream_t st) {
+    if (!c) return FHE_EINVAL;
+    if (count == 0) return FHE_OK;
+    if (!a || !out || (op != 2 && !b)) return FHE_EINVAL;
+    const size_t bytes = count * ct_words(c) * 8;
+    if (out != a && overlaps(out, a, bytes)) return FHE_EINVAL;
+    if (op != 2 && out != b && overlaps(out, b, bytes)) return FHE_EINVAL;
+    FHE_TRY(check_canonical(c, a, count * 2 * c->k, c->k, 0, st));
+    if (op != 2) FHE_TRY(check_canonical(c, b, count * 2 * c->k, c->k, 0, st));
+    return run(c, KK_ELEMENTWISE, st,
+               [&] { return launch_addsub(c->dev, a, b, out, count * 2 * c->k, op, st); });
+}
+
+fhe_status fhe_add(fhe_ctx *c, const uint64_t *a, const uint64_t *b, uint64_t *out, size_t count,
+                   hipStream_t st) {
+    return addsub_common(c, a, b, out, count, 0, st);
+}
+
+fhe_status fhe_sub(fhe_ctx *c, const uint64_t *a, const uint64_t *b, uint64_t *out, size_t count,
+                   hipStream_t st) {
+    return addsub_common(c, a, b, out, count, 1, st);
+}
+
+fhe_status fhe_neg(fhe_ctx *c, const uint64_t *a, uint64_t *out, size_t count, hipStream_t st) {
+    return addsub_common(c, a, nullptr, out, count, 2, st);
+}
+
+static fhe_status plain_common(fhe_ctx *c, const uint64_t *a, uint64_t cval, uint64_t *out,
+                               size_t count, int sign, hipStream_t st) {
+    if (!c) return FHE_EINVAL;
+    if (count == 0) return FHE_OK;
+    if (!a || !out) return FHE_EINVAL;
+    if (cval >= c->t) return FHE_EINVAL;
+    const size_t bytes = count * ct_words(c) * 8;
+    if (out != a && overlaps(out, a, bytes)) return FHE_EINVAL;
+    FHE_TRY(check_canonical(c, a, count * 2 * c->k, c->k, 0, st));
+    return run(c, KK_ELEMENTWISE, st,
+               [&] { return launch_plain_const(c->dev, a, out, count, cval, sign, st); });
+}
+
+fhe_status fhe_add_plain_const(fhe_ctx *c, const uint64_t *a, uint64_t cval, uint64_t *out,
+                               size_t count, hipStream_t st) {
+    return plain_common(c, a, cval, out, count, +1, st);
+}
+
+fhe_status fhe_sub_plain_const(fhe_ctx *c, const uint64_t *a, uint64_t cval, uint64_t *out,
+                               size_t count, hipStream_t st) {
+    return plain_common(c, a, cval, out, count, -1, st);
+}
+
+// -------------------------------------------------------------- hot path ----
+
+fhe_status fhe_mul_relin(fhe_ctx *c, const uint64_t *rlk, const uint64_t *a, const uint64_t *b,
+                         uint64_t *out, size_t count, void *ws, size_t ws_bytes, hipStream_t st) {
+    if (!c) return FHE_EINVAL;
+    if (count == 0) return FHE_OK;
+    if (!rlk || !a || !b || !out || !ws) return FHE_EINVAL;
+    const size_t bytes = count * ct_words(c) * 8;
+    if (out != a && overlaps(out, a, bytes)) return FHE_EINVAL;
+    if (out != b && overlaps(out, b, bytes)) return FHE_EINVAL;
+    const bool square = (a == b);
+    if (ws_bytes < fhe_workspace_bytes(c, square ? FHE_OP_SQUARE_RELIN : FHE_OP_MUL_RELIN, count))
+        return FHE_EWORKSPACE;
+    FHE_TRY(check_canonical(c, a, count * 2 * c->k, c->k, 0, st));
+    if (!square) FHE_TRY(check_canonical(c, b, count * 2 * c->k, c->k, 0, st));
+    return mul_relin_impl(c, rlk, a, b, out, count, ws, st);
+}
+
+fhe_status fhe_bridge_to_bits(fhe_ctx *c, const uint64_t *rlk, const uint64_t *x, uint32_t nbits,
+                              uint64_t *bits, uint64_t *eq, size_t count, void *ws, size_t ws_bytes,
+                              hipStream_t st) {
+    if (!c) return FHE_EINVAL;
+    if (c->encoding != FHE_ENC_COEFF || !is_prime_u64(c->t) || c->t < 3 ||
+        ((c->t - 1) & (c->t - 2)) != 0 || c->t > 65537)
+        return FHE_EUNSUPPORTED;
+    if (nbits == 0 || nbits > 20 || (1ull << nbits) < c->t) return FHE_EINVAL;
+    if (count == 0) return FHE_OK;
+    if (!rlk || !x || !bits || !ws) return FHE_EINVAL;
+    if (ws_bytes < fhe_workspace_bytes(c, FHE_OP_BRIDGE, count)) return FHE_EWORKSPACE;
+    const size_t ctw = ct_words(c);
+    if (overlaps2(bits, count * nbits * ctw * 8, x, count * ctw * 8)) return FHE_EINVAL;
+    if (eq && (overlaps2(eq, count * c->t * ctw * 8, x, count * ctw * 8) ||
+               overlaps2(eq, count * c->t * ctw * 8, bits, count * nbits * ctw * 8)))
+        return FHE_EINVAL;
+    FHE_TRY(check_canonical(c, x, count * 2 * c->k, c->k, 0, st));
+    const int T = (int)c->t;
+    int squarings = 0;
+    while ((1ull << squarings) < c->t - 1) squarings++;
+    const size_t G = bridge_group(c);
+    const size_t gmax = count < G ? count : G;
+    uint64_t *y = (uint64_t *)ws;
+    void *ws2 = y + gmax * T * ctw;
+    const DevCtx &d = c->dev;
+    for (size_t g0 = 0; g0 < count; g0 += G) {
+        const size_t gc = count - g0 < G ? count - g0 : G;
+        const size_t chains = gc * T;
+        FHE_TRY(run(c, KK_BRIDGE, st, [&] { return launch_bridge_init(d, x + g0 * ctw, y, gc, T, st); }));
+        for (int sq = 0; sq < squarings; sq++) FHE_TRY(mul_relin_impl(c, rlk, y, y, y, chains, ws2, st));
+        uint64_t *eqp = eq ? eq + g0 * T * ctw : nullptr;
+        FHE_TRY(run(c, KK_BRIDGE, st, [&] {
+            return launch_bridge_combine(d, y, bits + g0 * nbits * ctw, eqp, gc, T, (int)nbits, st);
+        }));
+    }
+    return FHE_OK;
+}
+
+fhe_status fhe_bits_to_mod(fhe_ctx *c, const uint64_t *bits, uint32_t nbits, uint64_t *out,
+                           size_t count, hipStream_t st) {
+    if (!c) return FHE_EINVAL;
+    if (nbits == 0) return FHE_EINVAL;
+    if (count == 0) return FHE_OK;
+    if (!bits || !out) return FHE_EINVAL;
+    if (overlaps2(out, count * ct_words(c) * 8, bits, count * nbits * ct_words(c) * 8)) return FHE_EINVAL;
+    return run(c, KK_ELEMENTWISE, st,
+               [&] { return launch_horner(c->dev, bits, (int)nbits, out, count, st); });
+}
+
+fhe_status fhe_ntt(fhe_ctx *c, int inverse, uint64_t *polys, size_t count, hipStream_t st) {
+    if (!c) return FHE_EINVAL;
+    if (count == 0) return FHE_OK;
+    if (!polys) return FHE_EINVAL;
+    FHE_TRY(check_canonical(c, polys, count * c->k, c->k, 0, st));
+    return run(c, KK_NTT_ROWS, st, [&] {
+        return launch_ntt_rows(c->dev, polys, count * c->k, c->k, 0, inverse ? NTT_INV : NTT_FWD, st);
+    });
+}
+
+// ---------------------------------------------------------------- timing ----
+
+fhe_status fhe_set_timing(fhe_ctx *c, int enable) {
+    if (!c) return FHE_EINVAL;
+    c->timing = enable != 0;
+    return FHE_OK;
+}
+
+int fhe_kernel_kinds(void) { return KK_COUNT; }
+
+const char *fhe_kernel_name(int kind) {
+    return (kind >= 0 && kind < KK_COUNT) ? kKernelNames[kind] : "unknown";
+}
+
+fhe_status fhe_kernel_stats(fhe_ctx *c, int kind, double *total_ms, uint64_t *launches) {
+    if (!c || kind < 0 || kind >= KK_COUNT || !total_ms || !launches) return FHE_EINVAL;
+    for (auto &ev : c->pending[kind]) {
+        if (hipEventSynchronize(ev.b) != hipSuccess) return FHE_EDEVICE;
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, ev.a, ev.b) != hipSuccess) return FHE_EDEVICE;
+        c->total_ms[kind] += ms;
+        c->free_events.push_back(ev.a);
+        c->free_events.push_back(ev.b);
+    }
+    c->pending[kind].clear();
+    *total_ms = c->total_ms[kind];
+    *launches = c->launches[kind];
+    return FHE_OK;
+}
+
+fhe_status fhe_reset_kernel_stats(fhe_ctx *c) {
+    if (!c) return FHE_EINVAL;
+    for (int i = 0; i < KK_COUNT; i++) {
+        double ms;
+        uint64_t l;
+        fhe_status s = fhe_kernel_stats(c, i, &ms, &l);
+        if (s != FHE_OK) return s;
+        c->total_ms[i] = 0;
+        c->launches[i] = 0;
+    }
+    return FHE_OK;
+}
+
+fhe_status fhe_fallback_count(fhe_ctx *c, uint64_t *count) {
+    if (!c || !count) return FHE_EINVAL;
+    FHE_HIP(hipDeviceSynchronize());
+    FHE_HIP(hipMemcpy(count, c->d_counters, 8, hipMemcpyDeviceToHost));
+    return FHE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,95 @@
+// Kernel launch interface shared by the host code and the kernel files.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "tables.hpp"
+
+struct Tw;
+
+// Everything a kernel needs to know about the context, passed by value.
+struct DevCtx {
+    int n, L, k, kp, K;
+    uint64_t t;
+    const PrimeConst *pc;   // [K]
+    const Tw *tw;           // [K][n] forward twiddles psi^bitrev(i)
+    const Tw *itw;          // [K][n] inverse twiddles psi^-bitrev(i)
+    const ConvConst *cc;
+    const MrcConst *mrc_q;  // basis Q -> targets P (and t in the last slot)
+    const MrcConst *mrc_p;  // basis P -> targets Q
+    unsigned long long *fallback;  // count of coefficients that took the exact path
+};
+
+// Kernel kinds (timing and profiling names).
+enum KernelKind {
+    KK_LIFT = 0,
+    KK_FWD_EXT,
+    KK_TENSOR_INTT,
+    KK_SCALE,
+    KK_RELIN_DIGITS,
+    KK_RELIN_IP,
+    KK_NTT_ROWS,
+    KK_ELEMENTWISE,
+    KK_BRIDGE,
+    KK_MISC,
+    KK_COUNT
+};
+
+// Row transform modes of launch_ntt_rows.
+enum NttMode {
+    NTT_FWD = 0,         // natural -> bit-reversed positions, canonical
+    NTT_INV = 1,         // inverse, times n^-1, canonical
+    NTT_INV_MONT = 2,    // inverse, times n^-1 2^64 (after Montgomery products)
+    NTT_FWD_NINVM = 3    // forward, then times n^-1 2^64 (relinearization key form)
+};
+
+// ---- transforms (kernels_ntt.hip) ----
+hipError_t launch_ntt_rows(const DevCtx &c, uint64_t *data, size_t nrows, int kmod, int limb_off,
+                           int mode, hipStream_t s);
+// Forward transforms of the extended inputs: rows (item, poly, limb) with the
+// Q limbs read from a (polys 0,1) / b (polys 2,3) and the P limbs read from E.
+hipError_t launch_fwd_ext(const DevCtx &c, const uint64_t *a, const uint64_t *b, uint64_t *E,
+                          int npoly, size_t items, hipStream_t s);
+hipError_t launch_tensor_intt(const DevCtx &c, const uint64_t *E, uint64_t *Dt, bool square,
+                              size_t items, hipStream_t s);
+hipError_t launch_relin_digits(const DevCtx &c, const uint64_t *C2, uint64_t *Dhat, size_t items,
+                               hipStream_t s);
+hipError_t launch_relin_ip(const DevCtx &c, const uint64_t *Dhat, const uint64_t *rlk, uint64_t *out,
+                           size_t items, hipStream_t s);
+
+// ---- base conversions and elementwise (kernels_conv.hip) ----
+hipError_t launch_lift(const DevCtx &c, const uint64_t *a, const uint64_t *b, uint64_t *E, int npoly,
+                       size_t items, hipStream_t s);
+hipError_t launch_scale(const DevCtx &c, const uint64_t *Dt, uint64_t *out, uint64_t *C2,
+                        size_t items, hipStream_t s);
+hipError_t launch_decrypt_scale(const DevCtx &c, const uint64_t *X, uint64_t *pt, size_t count,
+                                hipStream_t s);
+// op: 0 add, 1 sub, 2 neg (b unused)
+hipError_t launch_addsub(const DevCtx &c, const uint64_t *a, const uint64_t *b, uint64_t *out,
+                         size_t nrows, int op, hipStream_t s);
+// out = a with c0's constant coefficient +/- Delta*cval (sign: +1 / -1)
+hipError_t launch_plain_const(const DevCtx &c, const uint64_t *a, uint64_t *out, size_t count,
+                              uint64_t cval, int sign, hipStream_t s);
+// small signed integers (int8 when is8, else int32) -> residues, rows [count][k][n]
+hipError_t launch_small_to_rns(const DevCtx &c, const void *v, int is8, uint64_t *out, size_t count,
+                               hipStream_t s);
+// out = a * b * 2^-64 (canonical), rows with limb = row % k; bcast: b has k rows only
+hipError_t launch_pointwise_mont(const DevCtx &c, const uint64_t *a, const uint64_t *b, uint64_t *out,
+                                 size_t nrows, int bcast, hipStream_t s);
+// out_j = -(prod_j + e_j) + [j == digit] s2_j  (digit < 0: no s^2 term)
+hipError_t launch_key_b(const DevCtx &c, const uint64_t *prod, const uint64_t *e_rns,
+                        const uint64_t *s2, int digit, uint64_t *out, hipStream_t s);
+// ct[j] = (prod[0][j] + e[j][0] + Delta m_j, prod[1][j] + e[j][1]); prod [2][count][k][n]
+hipError_t launch_encrypt_finish(const DevCtx &c, const uint64_t *prod, const int32_t *e,
+                                 const uint64_t *pt, uint64_t *ct, size_t count, hipStream_t s);
+// y[j*tcount + c] = x[j] - Delta*c (constant coefficient of c0)
+hipError_t launch_bridge_init(const DevCtx &c, const uint64_t *x, uint64_t *y, size_t count,
+                              int tcount, hipStream_t s);
+hipError_t launch_bridge_combine(const DevCtx &c, const uint64_t *y, uint64_t *bits, uint64_t *eq,
+                                 size_t count, int tcount, int nbits, hipStream_t s);
+hipError_t launch_horner(const DevCtx &c, const uint64_t *bits, int nbits, uint64_t *out,
+                         size_t count, hipStream_t s);
+// flag[0] |= 1 if some word of rows [nrows][n] (limb = row % kmod + off) is >= its prime
+hipError_t launch_validate(const DevCtx &c, const uint64_t *a, size_t nrows, int kmod, int off,
+                           unsigned int *flag, hipStream_t s);

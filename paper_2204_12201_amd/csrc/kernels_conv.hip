@@ -1,0 +1,605 @@
+// Exact base conversions (lift, scale-and-round, P -> Q), decryption scaling,
+// elementwise ciphertext operations and the bridge glue.
+//
+// Base conversions follow the "fast conversion with exact overflow count"
+// pattern: for a value X known by residues x_i in basis {m_i},
+//   y_i = [x_i (M/m_i)^-1]_{m_i},   sum_i y_i M/m_i = X + v M,  v = floor(sum y_i/m_i),
+// so X modulo another prime p is sum_i y_i [M/m_i]_p - v [M]_p.  The overflow v
+// (or, for the centred lift, round(sum y_i / m_i)) is read off a double
+// precision estimate of sum y_i / m_i; when that estimate is within
+// FHE_EST_MARGIN of the decision boundary the coefficient is recomputed
+// exactly by mixed-radix (Garner) conversion instead, so every output word is
+// the exact one.
+#include "kernels.hpp"
+#include "modarith.hpp"
+
+namespace {
+
+// ---------------------------------------------------------------- exact path --
+
+// Garner digits d of X (residues r in basis M): X = sum_b d_b prod_{a<b} m_a.
+template <int MB>
+__device__ __forceinline__ void mrc_digits(const MrcConst &M, const uint64_t (&r)[MB],
+                                           uint64_t (&d)[MB]) {
+    const int K = (int)M.K;
+#pragma unroll
+    for (int b = 0; b < MB; b++) {
+        d[b] = 0;
+        if (b < K) {
+            const uint64_t mb = M.m[b];
+            uint64_t v = r[b];
+#pragma unroll
+            for (int a = 0; a < MB; a++) {
+                if (a < b) {
+                    const uint64_t da = mul_shoup(d[a], 1, M.one_p[b], mb);
+                    v = sub_mod(v, da, mb);
+                    v = mul_shoup(v, M.inv[a][b], M.inv_p[a][b], mb);
+                }
+            }
+            d[b] = v;
+        }
+    }
+}
+
+// X > (M - 1) / 2 ?  (lexicographic on the digits, most significant first)
+template <int MB>
+__device__ __forceinline__ bool mrc_gt_half(const MrcConst &M, const uint64_t (&d)[MB]) {
+    int res = 0;
+#pragma unroll
+    for (int b = MB - 1; b >= 0; b--) {
+        if (b < (int)M.K && res == 0) {
+            const uint64_t h = M.half_digit[b];
+            res = d[b] > h ? 1 : (d[b] < h ? -1 : 0);
+        }
+    }
+    return res == 1;
+}
+
+// X mod target j by Horner on the digits: acc = acc * m_b + d_b, b = K-1 .. 0.
+template <int MB>
+__device__ __forceinline__ uint64_t mrc_eval(const MrcConst &M, const uint64_t (&d)[MB], int j) {
+    const uint64_t p = M.target[j], op = M.tgt_one_p[j];
+    uint64_t acc = 0;
+#pragma unroll
+    for (int b = MB - 1; b >= 0; b--) {
+        if (b < (int)M.K) {
+            acc = mul_shoup(acc, M.m_mod_t[b][j], M.m_mod_t_p[b][j], p);
+            acc = add_mod(acc, mul_shoup(d[b], 1, op, p), p);
+        }
+    }
+    return acc;
+}
+
+// ---------------------------------------------------------------- lift ------
+
+// Extended rows of the inputs: for every coefficient of poly `blockIdx.y` of
+// item `blockIdx.z`, the centred lift x~ in (-q/2, q/2) written modulo each
+// P prime into E[item][poly][k + j].
+template <int MK, int MKP>
+__global__ __launch_bounds__(256) void k_lift(DevCtx c, const uint64_t *__restrict__ a,
+                                              const uint64_t *__restrict__ b,
+                                              uint64_t *__restrict__ E, int npoly) {
+    const int n = c.n, k = c.k, kp = c.kp, K = c.K;
+    const int coef = blockIdx.x * 256 + threadIdx.x;
+    if (coef >= n) return;
+    const int poly = blockIdx.y;
+    const size_t item = blockIdx.z;
+    const uint64_t *src = poly < 2 ? a + (item * 2 + poly) * (size_t)k * n
+                                   : b + (item * 2 + poly - 2) * (size_t)k * n;
+    uint64_t *dst = E + ((item * npoly + poly) * K + k) * (size_t)n;
+    const ConvConst &cc = *c.cc;
+
+    uint64_t x[MK], y[MK];
+    double e = 0.0;
+#pragma unroll
+    for (int i = 0; i < MK; i++) {
+        x[i] = 0;
+        y[i] = 0;
+        if (i < k) {
+            const uint64_t qi = c.pc[i].q;
+            x[i] = src[(size_t)i * n + coef];
+            y[i] = mul_shoup(x[i], cc.qhinv[i], cc.qhinv_p[i], qi);
+            e = fma((double)y[i], cc.inv_q[i], e);
+        }
+    }
+    // |e - sum y_i/q_i| <= (2.01 K + 1.01 K^2) 2^-53 < 2^-44 for K <= 20.
+    const double fl = floor(e), d = e - fl;
+    if (fabs(d - 0.5) >= FHE_EST_MARGIN) {
+        const int beta = (int)fl + (d > 0.5 ? 1 : 0);
+#pragma unroll
+        for (int j = 0; j < MKP; j++) {
+            if (j < kp) {
+                const PrimeConst &P = c.pc[k + j];
+                Acc128 acc;
+                acc_init(acc);
+#pragma unroll
+                for (int i = 0; i < MK; i++)
+                    if (i < k) acc_mac(acc, y[i], cc.qhat_pm[i][j]);
+                uint64_t r = acc_reduce_mont(acc, P.q, P.qinv_neg, P.one_p);
+                dst[(size_t)j * n + coef] = sub_mod(r, cc.beta_q_p[beta][j], P.q);
+            }
+        }
+    } else {
+        atomicAdd(c.fallback, 1ull);
+        const MrcConst &M = *c.mrc_q;
+        uint64_t dg[MK];
+        mrc_digits<MK>(M, x, dg);
+        const bool gt = mrc_gt_half<MK>(M, dg);
+#pragma unroll
+        for (int j = 0; j < MKP; j++) {
+            if (j < kp) {
+                const uint64_t pj = c.pc[k + j].q;
+                uint64_t r = mrc_eval<MK>(M, dg, j);
+                if (gt) r = sub_mod(r, M.M_mod_t[j], pj);
+                dst[(size_t)j * n + coef] = r;
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------- scale and round ----
+
+// C = round(t D / q) = floor((t D + h) / q), h = (q - 1)/2, for D given by its
+// residues in Q and P (rows Dt[item][comp][0..K)), written in basis Q.
+// Step 1 (in P):   C_{p_j} = [t q^-1 D_{p_j} + h q^-1 + v - sum_i y_i q_i^-1]_{p_j},
+//                  y_i = [(t D_{q_i} + h) qhat_i^-1]_{q_i}, v = floor(sum_i y_i / q_i).
+// Step 2 (P -> Q): centred conversion of C, which satisfies |C| < P/2.
+template <int MK, int MKP>
+__global__ __launch_bounds__(256) void k_scale(DevCtx c, const uint64_t *__restrict__ Dt,
+                                               uint64_t *__restrict__ out,
+                                               uint64_t *__restrict__ C2) {
+    const int n = c.n, k = c.k, kp = c.kp, K = c.K;
+    const int coef = blockIdx.x * 256 + threadIdx.x;
+    if (coef >= n) return;
+    const int comp = blockIdx.y;
+    const size_t item = blockIdx.z;
+    const uint64_t *src = Dt + (item * 3 + comp) * (size_t)K * n;
+    uint64_t *dst = comp < 2 ? out + (item * 2 + comp) * (size_t)k * n : C2 + item * (size_t)k * n;
+    const ConvConst &cc = *c.cc;
+
+    uint64_t y[MK];
+    double e = 0.0;
+#pragma unroll
+    for (int i = 0; i < MK; i++) {
+        y[i] = 0;
+        if (i < k) {
+            const uint64_t qi = c.pc[i].q;
+            const uint64_t dq = src[(size_t)i * n + coef];
+            y[i] = add_mod(mul_shoup(dq, cc.tqhinv[i], cc.tqhinv_p[i], qi), cc.hqhinv[i], qi);
+            e = fma((double)y[i], cc.inv_q[i], e);
+        }
+    }
+    const double fl = floor(e), d = e - fl;
+    bool exact = (d < FHE_EST_MARGIN) || (d > 1.0 - FHE_EST_MARGIN);
+    const uint64_t v = (uint64_t)fl;
+
+    uint64_t z[MKP];
+    double e2 = 0.0;
+#pragma unroll
+    for (int j = 0; j < MKP; j++) {
+        z[j] = 0;
+        if (j < kp) {
+            const PrimeConst &P = c.pc[k + j];
+            Acc128 acc;
+            acc_init(acc);
+#pragma unroll
+            for (int i = 0; i < MK; i++)
+                if (i < k) acc_mac(acc, y[i], cc.nqinv_pm[i][j]);
+            uint64_t r = acc_reduce_mont(acc, P.q, P.qinv_neg, P.one_p);
+            const uint64_t dp = src[(size_t)(k + j) * n + coef];
+            r = add_mod(r, mul_shoup(dp, cc.tqinv_p[j], cc.tqinv_ps[j], P.q), P.q);
+            r = add_mod(r, cc.hqinv_p[j], P.q);
+            r = add_mod(r, v, P.q);  // v <= k < p_j
+            z[j] = mul_shoup(r, cc.phinv[j], cc.phinv_p[j], P.q);
+            e2 = fma((double)z[j], cc.inv_p[j], e2);
+        }
+    }
+    const double fl2 = floor(e2), d2 = e2 - fl2;
+    exact = exact || (fabs(d2 - 0.5) < FHE_EST_MARGIN);
+    if (!exact) {
+        const int beta = (int)fl2 + (d2 > 0.5 ? 1 : 0);
+#pragma unroll
+        for (int i = 0; i < MK; i++) {
+            if (i < k) {
+                const PrimeConst &Q = c.pc[i];
+                Acc128 acc;
+                acc_init(acc);
+#pragma unroll
+                for (int j = 0; j < MKP; j++)
+                    if (j < kp) acc_mac(acc, z[j], cc.phat_qm[j][i]);
+                uint64_t r = acc_reduce_mont(acc, Q.q, Q.qinv_neg, Q.one_p);
+                dst[(size_t)i * n + coef] = sub_mod(r, cc.beta_p_q[beta][i], Q.q);
+            }
+        }
+        return;
+    }
+    // Exact path: Y = t D + h; [Y]_q by Garner over Q; C_p = (Y_p - [Y]_q) q^-1;
+    // then the centred value of C by Garner over P.
+    atomicAdd(c.fallback, 1ull);
+    const MrcConst &MQ = *c.mrc_q;
+    const MrcConst &MP = *c.mrc_p;
+    uint64_t yq[MK], dq[MK];
+#pragma unroll
+    for (int i = 0; i < MK; i++) {
+        yq[i] = 0;
+        if (i < k) {
+            const uint64_t qi = c.pc[i].q;
+            const uint64_t dv = src[(size_t)i * n + coef];
+            yq[i] = add_mod(mul_shoup(dv, cc.t_q[i], cc.t_qs[i], qi), cc.h_q[i], qi);
+        }
+    }
+    mrc_digits<MK>(MQ, yq, dq);
+    uint64_t cp[MKP], dp[MKP];
+#pragma unroll
+    for (int j = 0; j < MKP; j++) {
+        cp[j] = 0;
+        if (j < kp) {
+            const uint64_t pj = c.pc[k + j].q;
+            const uint64_t dv = src[(size_t)(k + j) * n + coef];
+            const uint64_t ypj = add_mod(mul_shoup(dv, cc.t_p[j], cc.t_ps[j], pj), cc.h_p[j], pj);
+            const uint64_t xpj = mrc_eval<MK>(MQ, dq, j);
+            cp[j] = mul_shoup(sub_mod(ypj, xpj, pj), cc.qinv_p[j], cc.qinv_ps[j], pj);
+        }
+    }
+    mrc_digits<MKP>(MP, cp, dp);
+    const bool gt = mrc_gt_half<MKP>(MP, dp);
+#pragma unroll
+    for (int i = 0; i < MK; i++) {
+        if (i < k) {
+            const uint64_t qi = c.pc[i].q;
+            uint64_t r = mrc_eval<MKP>(MP, dp, i);
+            if (gt) r = sub_mod(r, MP.M_mod_t[i], qi);
+            dst[(size_t)i * n + coef] = r;
+        }
+    }
+}
+
+// -------------------------------------------------------- decryption ------
+
+// pt = floor((t X + h) / q) mod t = (h - [t X + h]_q) q^-1 mod t, X = [c0 + c1 s]_q.
+template <int MK>
+__global__ __launch_bounds__(256) void k_decrypt_scale(DevCtx c, const uint64_t *__restrict__ X,
+                                                       uint64_t *__restrict__ pt) {
+    const int n = c.n, k = c.k, kp = c.kp;
+    const int coef = blockIdx.x * 256 + threadIdx.x;
+    if (coef >= n) return;
+    const size_t item = blockIdx.y;
+    const ConvConst &cc = *c.cc;
+    const MrcConst &MQ = *c.mrc_q;
+    uint64_t y[MK], d[MK];
+#pragma unroll
+    for (int i = 0; i < MK; i++) {
+        y[i] = 0;
+        if (i < k) {
+            const uint64_t qi = c.pc[i].q;
+            const uint64_t xv = X[(item * k + i) * (size_t)n + coef];
+            y[i] = add_mod(mul_shoup(xv, cc.t_q[i], cc.t_qs[i], qi), cc.h_q[i], qi);
+        }
+    }
+    mrc_digits<MK>(MQ, y, d);
+    const uint64_t t = c.t;
+    const uint64_t yt = mrc_eval<MK>(MQ, d, kp);  // target slot kp is t
+    pt[item * n + coef] = mul_shoup(sub_mod(cc.h_t, yt, t), cc.qinv_t, cc.qinv_ts, t);
+}
+
+// ------------------------------------------------------- elementwise ------
+
+__global__ void k_addsub(DevCtx c, const uint64_t *__restrict__ a, const uint64_t *__restrict__ b,
+                         uint64_t *__restrict__ out, size_t words, int op) {
+    const size_t n = c.n;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < words;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const int limb = (int)((i / n) % c.k);
+        const uint64_t q = c.pc[limb].q;
+        const uint64_t x = a[i];
+        uint64_t r;
+        if (op == 0) r = add_mod(x, b[i], q);
+        else if (op == 1) r = sub_mod(x, b[i], q);
+        else r = x == 0 ? 0 : q - x;
+        out[i] = r;
+    }
+}
+
+// out = a, except c0's constant coefficient +/- Delta * cval.
+__global__ void k_plain_const(DevCtx c, const uint64_t *__restrict__ a, uint64_t *__restrict__ out,
+                              size_t words, uint64_t cval, int sign) {
+    const size_t n = c.n, k = c.k;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < words;
+         i += (size_t)gridDim.x * blockDim.x) {
+        uint64_t x = a[i];
+        const size_t coef = i % n, row = i / n;
+        const size_t limb = row % k, poly = (row / k) % 2;
+        if (coef == 0 && poly == 0) {
+            const uint64_t q = c.pc[limb].q;
+            const uint64_t dc = mul_shoup(cval % q, c.cc->delta_q[limb], c.cc->delta_qs[limb], q);
+            x = sign > 0 ? add_mod(x, dc, q) : sub_mod(x, dc, q);
+        }
+        out[i] = x;
+    }
+}
+
+__global__ void k_small_to_rns(DevCtx c, const void *__restrict__ v, int is8,
+                               uint64_t *__restrict__ out, size_t count) {
+    const size_t n = c.n, k = c.k;
+    const size_t total = count * k * n;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const size_t coef = i % n, limb = (i / n) % k, item = i / (n * k);
+        const int64_t s = is8 ? (int64_t)((const int8_t *)v)[item * n + coef]
+                              : (int64_t)((const int32_t *)v)[item * n + coef];
+        const uint64_t q = c.pc[limb].q;
+        out[i] = s >= 0 ? (uint64_t)s % q : (q - ((uint64_t)(-s) % q)) % q;
+    }
+}
+
+__global__ void k_pointwise_mont(DevCtx c, const uint64_t *__restrict__ a,
+                                 const uint64_t *__restrict__ b, uint64_t *__restrict__ out,
+                                 size_t words, int bcast) {
+    const size_t n = c.n, k = c.k;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < words;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const size_t limb = (i / n) % k;
+        const PrimeConst &P = c.pc[limb];
+        const uint64_t bv = bcast ? b[limb * n + i % n] : b[i];
+        out[i] = csub(mont_mul_lazy(a[i], bv, P.q, P.qinv_neg), P.q);
+    }
+}
+
+__global__ void k_key_b(DevCtx c, const uint64_t *__restrict__ prod, const uint64_t *__restrict__ e,
+                        const uint64_t *__restrict__ s2, int digit, uint64_t *__restrict__ out) {
+    const size_t n = c.n, k = c.k;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < k * n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const size_t limb = i / n;
+        const uint64_t q = c.pc[limb].q;
+        uint64_t r = add_mod(prod[i], e[i], q);
+        r = r == 0 ? 0 : q - r;
+        if ((int)limb == digit) r = add_mod(r, s2[i], q);
+        out[i] = r;
+    }
+}
+
+// ct[j] = (prod[0][j] + e[j][0] + Delta m_j, prod[1][j] + e[j][1]); prod is [2][count][k][n].
+__global__ void k_encrypt_finish(DevCtx c, const uint64_t *__restrict__ prod,
+                                 const int32_t *__restrict__ e, const uint64_t *__restrict__ pt,
+                                 uint64_t *__restrict__ ct, size_t count) {
+    const size_t n = c.n, k = c.k;
+    const size_t total = count * 2 * k * n;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const size_t coef = i % n, limb = (i / n) % k, poly = (i / (n * k)) % 2,
+                     item = i / (2 * n * k);
+        const uint64_t q = c.pc[limb].q;
+        const int64_t ev = e[(item * 2 + poly) * n + coef];
+        const uint64_t er = ev >= 0 ? (uint64_t)ev % q : (q - ((uint64_t)(-ev) % q)) % q;
+        uint64_t r = add_mod(prod[((poly * count + item) * k + limb) * n + coef], er, q);
+        if (poly == 0) {
+            const uint64_t m = pt[item * n + coef] % q;
+            r = add_mod(r, mul_shoup(m, c.cc->delta_q[limb], c.cc->delta_qs[limb], q), q);
+        }
+        ct[i] = r;
+    }
+}
+
+// y[j*T + c] = x[j] with Delta*c subtracted from c0's constant coefficient.
+__global__ void k_bridge_init(DevCtx c, const uint64_t *__restrict__ x, uint64_t *__restrict__ y,
+                              size_t count, int tcount) {
+    const size_t n = c.n, k = c.k, ctw = 2 * k * n;
+    const size_t total = count * tcount * ctw;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const size_t w = i % ctw, chain = i / ctw;
+        const size_t j = chain / tcount, cc = chain % tcount;
+        uint64_t v = x[j * ctw + w];
+        const size_t coef = w % n, row = w / n;
+        if (coef == 0 && row < k) {
+            const uint64_t q = c.pc[row].q;
+            const uint64_t dc = mul_shoup(cc % q, c.cc->delta_q[row], c.cc->delta_qs[row], q);
+            v = sub_mod(v, dc, q);
+        }
+        y[i] = v;
+    }
+}
+
+// eq_c = Delta [coefficient 0 of c0] - y_c;  bits_b = sum_{c in [1,T), bit b of c} eq_c.
+constexpr int FHE_MAXNB = 20;
+__global__ __launch_bounds__(256) void k_bridge_combine(DevCtx c, const uint64_t *__restrict__ y,
+                                                        uint64_t *__restrict__ bits,
+                                                        uint64_t *__restrict__ eq, int tcount,
+                                                        int nbits) {
+    const int n = c.n, k = c.k;
+    const int coef = blockIdx.x * 256 + threadIdx.x;
+    if (coef >= n) return;
+    const int row = blockIdx.y;  // poly * k + limb
+    const int limb = row % k, poly = row / k;
+    const size_t j = blockIdx.z;
+    const size_t ctw = 2 * (size_t)k * n;
+    const uint64_t q = c.pc[limb].q;
+    const uint64_t one = (poly == 0 && coef == 0) ? c.cc->delta_q[limb] : 0;
+    uint64_t acc[FHE_MAXNB];
+#pragma unroll
+    for (int b = 0; b < FHE_MAXNB; b++) acc[b] = 0;
+    const size_t off = (size_t)row * n + coef;
+    for (int cc = 0; cc < tcount; cc++) {
+        const uint64_t yv = y[(j * tcount + cc) * ctw + off];
+        const uint64_t ev = sub_mod(one, yv, q);
+        if (eq) eq[(j * tcount + cc) * ctw + off] = ev;
+#pragma unroll
+        for (int b = 0; b < FHE_MAXNB; b++)
+            if (b < nbits && ((cc >> b) & 1)) acc[b] = add_mod(acc[b], ev, q);
+    }
+#pragma unroll
+    for (int b = 0; b < FHE_MAXNB; b++)
+        if (b < nbits) bits[(j * nbits + b) * ctw + off] = acc[b];
+}
+
+// out = sum_b 2^b bits_b by Horner: r = bits_{nb-1}; r = r + r + bits_b.
+__global__ void k_horner(DevCtx c, const uint64_t *__restrict__ bits, int nbits,
+                         uint64_t *__restrict__ out, size_t count) {
+    const size_t n = c.n, k = c.k, ctw = 2 * k * n;
+    const size_t total = count * ctw;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const size_t w = i % ctw, j = i / ctw;
+        const uint64_t q = c.pc[(w / n) % k].q;
+        uint64_t r = bits[(j * nbits + nbits - 1) * ctw + w];
+        for (int b = nbits - 2; b >= 0; b--) {
+            r = add_mod(r, r, q);
+            r = add_mod(r, bits[(j * nbits + b) * ctw + w], q);
+        }
+        out[i] = r;
+    }
+}
+
+__global__ void k_validate(DevCtx c, const uint64_t *__restrict__ a, size_t words, int kmod, int off,
+                           unsigned int *flag) {
+    const size_t n = c.n;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < words;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const int limb = (int)((i / n) % kmod) + off;
+        if (a[i] >= c.pc[limb].q) atomicOr(flag, 1u);
+    }
+}
+
+inline unsigned grid_for(size_t words, unsigned block = 256) {
+    size_t g = (words + block - 1) / block;
+    if (g > 65536 * 4) g = 65536 * 4;
+    if (g == 0) g = 1;
+    return (unsigned)g;
+}
+
+template <template <int, int> class Launcher, typename... A>
+hipError_t by_class(int k, int kp, A &&...args) {
+    if (k <= 4 && kp <= 4) return Launcher<4, 4>::run(args...);
+    if (k <= 8 && kp <= 8) return Launcher<8, 8>::run(args...);
+    if (k <= 8 && kp <= 12) return Launcher<8, 12>::run(args...);
+    if (k <= FHE_MAXK && kp <= FHE_MAXKP) return Launcher<FHE_MAXK, FHE_MAXKP>::run(args...);
+    return hipErrorInvalidValue;
+}
+
+template <int MK, int MKP>
+struct LiftL {
+    static hipError_t run(const DevCtx &c, const uint64_t *a, const uint64_t *b, uint64_t *E,
+                          int npoly, size_t items, hipStream_t s) {
+        dim3 grid((c.n + 255) / 256, npoly, (unsigned)items);
+        hipLaunchKernelGGL((k_lift<MK, MKP>), grid, dim3(256), 0, s, c, a, b, E, npoly);
+        return hipGetLastError();
+    }
+};
+
+template <int MK, int MKP>
+struct ScaleL {
+    static hipError_t run(const DevCtx &c, const uint64_t *Dt, uint64_t *out, uint64_t *C2,
+                          size_t items, hipStream_t s) {
+        dim3 grid((c.n + 255) / 256, 3, (unsigned)items);
+        hipLaunchKernelGGL((k_scale<MK, MKP>), grid, dim3(256), 0, s, c, Dt, out, C2);
+        return hipGetLastError();
+    }
+};
+
+}  // namespace
+
+hipError_t launch_lift(const DevCtx &c, const uint64_t *a, const uint64_t *b, uint64_t *E, int npoly,
+                       size_t items, hipStream_t s) {
+    if (items == 0) return hipSuccess;
+    return by_class<LiftL>(c.k, c.kp, c, a, b, E, npoly, items, s);
+}
+
+hipError_t launch_scale(const DevCtx &c, const uint64_t *Dt, uint64_t *out, uint64_t *C2,
+                        size_t items, hipStream_t s) {
+    if (items == 0) return hipSuccess;
+    return by_class<ScaleL>(c.k, c.kp, c, Dt, out, C2, items, s);
+}
+
+hipError_t launch_decrypt_scale(const DevCtx &c, const uint64_t *X, uint64_t *pt, size_t count,
+                                hipStream_t s) {
+    if (count == 0) return hipSuccess;
+    dim3 grid((c.n + 255) / 256, (unsigned)count);
+    if (c.k <= 4) hipLaunchKernelGGL((k_decrypt_scale<4>), grid, dim3(256), 0, s, c, X, pt);
+    else if (c.k <= 8) hipLaunchKernelGGL((k_decrypt_scale<8>), grid, dim3(256), 0, s, c, X, pt);
+    else hipLaunchKernelGGL((k_decrypt_scale<FHE_MAXK>), grid, dim3(256), 0, s, c, X, pt);
+    return hipGetLastError();
+}
+
+hipError_t launch_addsub(const DevCtx &c, const uint64_t *a, const uint64_t *b, uint64_t *out,
+                         size_t nrows, int op, hipStream_t s) {
+    const size_t words = nrows * c.n;
+    if (words == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_addsub, dim3(grid_for(words)), dim3(256), 0, s, c, a, b, out, words, op);
+    return hipGetLastError();
+}
+
+hipError_t launch_plain_const(const DevCtx &c, const uint64_t *a, uint64_t *out, size_t count,
+                              uint64_t cval, int sign, hipStream_t s) {
+    const size_t words = count * 2 * c.k * (size_t)c.n;
+    if (words == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_plain_const, dim3(grid_for(words)), dim3(256), 0, s, c, a, out, words, cval,
+                       sign);
+    return hipGetLastError();
+}
+
+hipError_t launch_small_to_rns(const DevCtx &c, const void *v, int is8, uint64_t *out, size_t count,
+                               hipStream_t s) {
+    const size_t words = count * c.k * (size_t)c.n;
+    if (words == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_small_to_rns, dim3(grid_for(words)), dim3(256), 0, s, c, v, is8, out, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_pointwise_mont(const DevCtx &c, const uint64_t *a, const uint64_t *b, uint64_t *out,
+                                 size_t nrows, int bcast, hipStream_t s) {
+    const size_t words = nrows * c.n;
+    if (words == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pointwise_mont, dim3(grid_for(words)), dim3(256), 0, s, c, a, b, out, words,
+                       bcast);
+    return hipGetLastError();
+}
+
+hipError_t launch_key_b(const DevCtx &c, const uint64_t *prod, const uint64_t *e_rns,
+                        const uint64_t *s2, int digit, uint64_t *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_key_b, dim3(grid_for((size_t)c.k * c.n)), dim3(256), 0, s, c, prod, e_rns, s2,
+                       digit, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_encrypt_finish(const DevCtx &c, const uint64_t *prod, const int32_t *e,
+                                 const uint64_t *pt, uint64_t *ct, size_t count, hipStream_t s) {
+    const size_t words = count * 2 * c.k * (size_t)c.n;
+    if (words == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_encrypt_finish, dim3(grid_for(words)), dim3(256), 0, s, c, prod, e, pt, ct,
+                       count);
+    return hipGetLastError();
+}
+
+hipError_t launch_bridge_init(const DevCtx &c, const uint64_t *x, uint64_t *y, size_t count,
+                              int tcount, hipStream_t s) {
+    const size_t words = count * tcount * 2 * c.k * (size_t)c.n;
+    if (words == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bridge_init, dim3(grid_for(words)), dim3(256), 0, s, c, x, y, count, tcount);
+    return hipGetLastError();
+}
+
+hipError_t launch_bridge_combine(const DevCtx &c, const uint64_t *y, uint64_t *bits, uint64_t *eq,
+                                 size_t count, int tcount, int nbits, hipStream_t s) {
+    if (count == 0) return hipSuccess;
+    if (nbits > FHE_MAXNB) return hipErrorInvalidValue;
+    dim3 grid((c.n + 255) / 256, 2 * c.k, (unsigned)count);
+    hipLaunchKernelGGL(k_bridge_combine, grid, dim3(256), 0, s, c, y, bits, eq, tcount, nbits);
+    return hipGetLastError();
+}
+
+hipError_t launch_horner(const DevCtx &c, const uint64_t *bits, int nbits, uint64_t *out,
+                         size_t count, hipStream_t s) {
+    const size_t words = count * 2 * c.k * (size_t)c.n;
+    if (words == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_horner, dim3(grid_for(words)), dim3(256), 0, s, c, bits, nbits, out, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_validate(const DevCtx &c, const uint64_t *a, size_t nrows, int kmod, int off,
+                           unsigned int *flag, hipStream_t s) {
+    const size_t words = nrows * c.n;
+    if (words == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_validate, dim3(grid_for(words)), dim3(256), 0, s, c, a, words, kmod, off, flag);
+    return hipGetLastError();
+}

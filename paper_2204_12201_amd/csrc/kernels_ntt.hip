@@ -1,0 +1,294 @@
+// Transform kernels: one workgroup of n/16 threads per row (ntt_core.hpp).
+//
+//  k_ntt_rows      generic batched forward / inverse transform of rows
+//  k_fwd_ext       forward transform of the extended inputs of a product
+//  k_tensor_intt   tensor component (Montgomery products of transformed
+//                  inputs, computed on load) followed by the inverse transform
+//  k_relin_digits  key-switching digits [C2]_{q_i} reduced mod q_j, transformed
+//  k_relin_ip      inner product of the transformed digits with the key, then
+//                  the inverse transform added into C0, C1
+#include "kernels.hpp"
+#include "modarith.hpp"
+#include "ntt_core.hpp"
+
+namespace {
+
+__device__ __forceinline__ uint64_t canon4(uint64_t x, uint64_t q) {  // [0, 4q) -> [0, q)
+    return csub(csub(x, q << 1), q);
+}
+
+template <int L>
+__device__ __forceinline__ void load_natural(uint64_t (&x)[16], const uint64_t *__restrict__ src,
+                                             int tid) {
+#pragma unroll
+    for (int s = 0; s < 16; s++) x[s] = src[natural_index<L>(tid, s)];
+}
+
+template <int L>
+__device__ __forceinline__ void load_bitrev(uint64_t (&x)[16], const uint64_t *__restrict__ src,
+                                            int tid) {
+#pragma unroll
+    for (int s = 0; s < 16; s++) x[s] = src[bitrev_layout_index<L>(tid, s)];
+}
+
+// mode: NttMode (kernels.hpp)
+template <int L>
+__global__ __launch_bounds__(Geo<L>::T) void k_ntt_rows(DevCtx c, uint64_t *__restrict__ data,
+                                                       int kmod, int limb_off, int mode) {
+    __shared__ uint64_t lds[Geo<L>::lds_words];
+    constexpr int n = Geo<L>::N;
+    const int tid = threadIdx.x;
+    const size_t row = blockIdx.x;
+    const int limb = (int)(row % kmod) + limb_off;
+    const PrimeConst &P = c.pc[limb];
+    const uint64_t q = P.q;
+    uint64_t *ptr = data + row * n;
+    uint64_t x[16];
+    if (mode == NTT_FWD || mode == NTT_FWD_NINVM) {
+        load_natural<L>(x, ptr, tid);
+        ntt_fwd_regs<L>(x, lds, tid, c.tw + (size_t)limb * n, q);
+#pragma unroll
+        for (int s = 0; s < 16; s++) {
+            uint64_t v = canon4(x[s], q);
+            if (mode == NTT_FWD_NINVM) v = mul_shoup(v, P.ninvm, P.ninvm_p, q);
+            ptr[bitrev_layout_index<L>(tid, s)] = v;
+        }
+    } else {
+        load_bitrev<L>(x, ptr, tid);
+        ntt_inv_regs<L>(x, lds, tid, c.itw + (size_t)limb * n, q);
+        const uint64_t w = mode == NTT_INV ? P.ninv : P.ninvm;
+        const uint64_t wp = mode == NTT_INV ? P.ninv_p : P.ninvm_p;
+#pragma unroll
+        for (int s = 0; s < 16; s++) ptr[natural_index<L>(tid, s)] = mul_shoup(x[s], w, wp, q);
+    }
+}
+
+// Rows (item, poly, limb), grid (K, npoly, items).  Q limbs come from the
+// input ciphertexts, P limbs from E (written there by the lift); the forward
+// transforms land in E[item][poly][limb], canonical.
+template <int L>
+__global__ __launch_bounds__(Geo<L>::T) void k_fwd_ext(DevCtx c, const uint64_t *__restrict__ a,
+                                                      const uint64_t *__restrict__ b,
+                                                      uint64_t *__restrict__ E, int npoly) {
+    __shared__ uint64_t lds[Geo<L>::lds_words];
+    constexpr int n = Geo<L>::N;
+    const int tid = threadIdx.x;
+    const int limb = blockIdx.x, poly = blockIdx.y;
+    const size_t item = blockIdx.z;
+    const int k = c.k, K = c.K;
+    const uint64_t q = c.pc[limb].q;
+    uint64_t *dst = E + ((item * npoly + poly) * K + limb) * (size_t)n;
+    const uint64_t *src;
+    if (limb < k)
+        src = (poly < 2 ? a + ((item * 2 + poly) * k + limb) * (size_t)n
+                        : b + ((item * 2 + poly - 2) * k + limb) * (size_t)n);
+    else
+        src = dst;
+    uint64_t x[16];
+    load_natural<L>(x, src, tid);
+    ntt_fwd_regs<L>(x, lds, tid, c.tw + (size_t)limb * n, q);
+#pragma unroll
+    for (int s = 0; s < 16; s++) dst[bitrev_layout_index<L>(tid, s)] = canon4(x[s], q);
+}
+
+// grid (K, 3, items): component comp of the tensor of item, limb `limb`.
+// Montgomery products carry a factor 2^-64, removed with n^-1 by the final
+// multiplication by n^-1 2^64.
+template <int L, bool SQ>
+__global__ __launch_bounds__(Geo<L>::T) void k_tensor_intt(DevCtx c, const uint64_t *__restrict__ E,
+                                                          uint64_t *__restrict__ Dt) {
+    __shared__ uint64_t lds[Geo<L>::lds_words];
+    constexpr int n = Geo<L>::N;
+    constexpr int npoly = SQ ? 2 : 4;
+    const int tid = threadIdx.x;
+    const int limb = blockIdx.x, comp = blockIdx.y;
+    const size_t item = blockIdx.z;
+    const int K = c.K;
+    const PrimeConst &P = c.pc[limb];
+    const uint64_t q = P.q, qi = P.qinv_neg, q2 = q << 1;
+    const size_t rs = (size_t)K * n;  // stride between polys of one item
+    const uint64_t *base = E + (item * npoly * K + limb) * (size_t)n;
+    uint64_t x[16];
+#pragma unroll
+    for (int s = 0; s < 16; s++) {
+        const int idx = bitrev_layout_index<L>(tid, s);
+        uint64_t v;
+        if (SQ) {
+            const uint64_t a0 = base[idx], a1 = base[rs + idx];
+            if (comp == 0) {
+                v = mont_mul_lazy(a0, a0, q, qi);
+            } else if (comp == 1) {
+                const uint64_t m = mont_mul_lazy(a0, a1, q, qi);  // d1 = 2 a0 a1
+                v = csub(m + m, q2);
+            } else {
+                v = mont_mul_lazy(a1, a1, q, qi);
+            }
+        } else {
+            const uint64_t a0 = base[idx], a1 = base[rs + idx];
+            const uint64_t b0 = base[2 * rs + idx], b1 = base[3 * rs + idx];
+            if (comp == 0) v = mont_mul_lazy(a0, b0, q, qi);
+            else if (comp == 1)
+                v = csub(mont_mul_lazy(a0, b1, q, qi) + mont_mul_lazy(a1, b0, q, qi), q2);
+            else v = mont_mul_lazy(a1, b1, q, qi);
+        }
+        x[s] = csub(v, q2);  // [0, 2q)
+    }
+    ntt_inv_regs<L>(x, lds, tid, c.itw + (size_t)limb * n, q);
+    uint64_t *dst = Dt + ((item * 3 + comp) * K + limb) * (size_t)n;
+#pragma unroll
+    for (int s = 0; s < 16; s++) dst[natural_index<L>(tid, s)] = mul_shoup(x[s], P.ninvm, P.ninvm_p, q);
+}
+
+// Key-switching digits: grid (k targets j, k digits i, items).  Row
+// Dhat[item][i][j] = NTT_j([C2]_{q_i} mod q_j), canonical.  j varies fastest so
+// the k workgroups reading one digit row run together and share it in L2.
+template <int L>
+__global__ __launch_bounds__(Geo<L>::T) void k_relin_digits(DevCtx c, const uint64_t *__restrict__ C2,
+                                                           uint64_t *__restrict__ Dhat) {
+    __shared__ uint64_t lds[Geo<L>::lds_words];
+    constexpr int n = Geo<L>::N;
+    const int tid = threadIdx.x;
+    const int j = blockIdx.x, i = blockIdx.y;
+    const size_t item = blockIdx.z;
+    const int k = c.k;
+    const PrimeConst &P = c.pc[j];
+    const uint64_t q = P.q;
+    const uint64_t *src = C2 + (item * k + i) * (size_t)n;
+    uint64_t x[16];
+#pragma unroll
+    for (int s = 0; s < 16; s++)
+        x[s] = mul_shoup_lazy(src[natural_index<L>(tid, s)], 1, P.one_p, q);  // < 2q
+    ntt_fwd_regs<L>(x, lds, tid, c.tw + (size_t)j * n, q);
+    uint64_t *dst = Dhat + ((item * k + i) * k + j) * (size_t)n;
+#pragma unroll
+    for (int s = 0; s < 16; s++) dst[bitrev_layout_index<L>(tid, s)] = canon4(x[s], q);
+}
+
+// Key-switching inner product: grid (2 components l, k limbs j, items).
+// rlk layout [digit i][comp l][limb j][n], transform domain, each entry
+// pre-multiplied by n^-1 2^64 so that the Montgomery products give
+// digit * key / n and the inverse transform needs no scaling.
+// out[item][l][j] += INTT(sum_i Dhat[item][i][j] * rlk[i][l][j]).
+template <int L>
+__global__ __launch_bounds__(Geo<L>::T) void k_relin_ip(DevCtx c, const uint64_t *__restrict__ Dhat,
+                                                       const uint64_t *__restrict__ rlk,
+                                                       uint64_t *__restrict__ out) {
+    __shared__ uint64_t lds[Geo<L>::lds_words];
+    constexpr int n = Geo<L>::N;
+    const int tid = threadIdx.x;
+    const int l = blockIdx.x, j = blockIdx.y;
+    const size_t item = blockIdx.z;
+    const int k = c.k;
+    const PrimeConst &P = c.pc[j];
+    const uint64_t q = P.q, qi = P.qinv_neg, q2 = q << 1;
+    uint64_t acc[16];
+#pragma unroll
+    for (int s = 0; s < 16; s++) acc[s] = 0;
+    for (int i = 0; i < k; i++) {
+        const uint64_t *d = Dhat + ((item * k + i) * k + j) * (size_t)n;
+        const uint64_t *r = rlk + (((size_t)i * 2 + l) * k + j) * n;
+#pragma unroll
+        for (int s0 = 0; s0 < 16; s0 += 8) {
+            asm volatile("" ::: "memory");  // keeps at most 8 pairs of loads in flight
+#pragma unroll
+            for (int s = s0; s < s0 + 8; s++) {
+                const int idx = bitrev_layout_index<L>(tid, s);
+                acc[s] = csub(acc[s] + mont_mul_lazy(d[idx], r[idx], q, qi), q2);  // [0, 2q)
+            }
+        }
+    }
+    ntt_inv_regs<L>(acc, lds, tid, c.itw + (size_t)j * n, q);
+    asm volatile("" ::: "memory");  // the C_l loads below stay after the transform
+    uint64_t *o = out + ((item * 2 + l) * k + j) * (size_t)n;
+#pragma unroll
+    for (int s = 0; s < 16; s++) {
+        const int idx = natural_index<L>(tid, s);
+        o[idx] = add_mod(csub(acc[s], q), o[idx], q);
+    }
+}
+
+template <int L>
+struct NttL {
+    static hipError_t rows(const DevCtx &c, uint64_t *data, size_t nrows, int kmod, int off, int mode,
+                           hipStream_t s) {
+        hipLaunchKernelGGL(k_ntt_rows<L>, dim3((unsigned)nrows), dim3(Geo<L>::T), 0, s, c, data, kmod,
+                           off, mode);
+        return hipGetLastError();
+    }
+    static hipError_t fwd_ext(const DevCtx &c, const uint64_t *a, const uint64_t *b, uint64_t *E,
+                              int npoly, size_t items, hipStream_t s) {
+        hipLaunchKernelGGL(k_fwd_ext<L>, dim3(c.K, npoly, (unsigned)items), dim3(Geo<L>::T), 0, s, c, a,
+                           b, E, npoly);
+        return hipGetLastError();
+    }
+    static hipError_t tensor(const DevCtx &c, const uint64_t *E, uint64_t *Dt, bool sq, size_t items,
+                             hipStream_t s) {
+        if (sq)
+            hipLaunchKernelGGL((k_tensor_intt<L, true>), dim3(c.K, 3, (unsigned)items), dim3(Geo<L>::T),
+                               0, s, c, E, Dt);
+        else
+            hipLaunchKernelGGL((k_tensor_intt<L, false>), dim3(c.K, 3, (unsigned)items),
+                               dim3(Geo<L>::T), 0, s, c, E, Dt);
+        return hipGetLastError();
+    }
+    static hipError_t relin_digits(const DevCtx &c, const uint64_t *C2, uint64_t *Dhat, size_t items,
+                                   hipStream_t s) {
+        hipLaunchKernelGGL(k_relin_digits<L>, dim3(c.k, c.k, (unsigned)items), dim3(Geo<L>::T), 0, s, c,
+                           C2, Dhat);
+        return hipGetLastError();
+    }
+    static hipError_t relin_ip(const DevCtx &c, const uint64_t *Dhat, const uint64_t *rlk, uint64_t *out,
+                               size_t items, hipStream_t s) {
+        hipLaunchKernelGGL(k_relin_ip<L>, dim3(2, c.k, (unsigned)items), dim3(Geo<L>::T), 0, s, c, Dhat,
+                           rlk, out);
+        return hipGetLastError();
+    }
+};
+
+#define FHE_DISPATCH_L(Lval, CALL)            \
+    switch (Lval) {                           \
+        case 4: return NttL<4>::CALL;         \
+        case 5: return NttL<5>::CALL;         \
+        case 6: return NttL<6>::CALL;         \
+        case 7: return NttL<7>::CALL;         \
+        case 8: return NttL<8>::CALL;         \
+        case 9: return NttL<9>::CALL;         \
+        case 10: return NttL<10>::CALL;       \
+        case 11: return NttL<11>::CALL;       \
+        case 12: return NttL<12>::CALL;       \
+        case 13: return NttL<13>::CALL;       \
+        case 14: return NttL<14>::CALL;       \
+        default: return hipErrorInvalidValue; \
+    }
+
+}  // namespace
+
+hipError_t launch_ntt_rows(const DevCtx &c, uint64_t *data, size_t nrows, int kmod, int limb_off,
+                           int mode, hipStream_t s) {
+    if (nrows == 0) return hipSuccess;
+    FHE_DISPATCH_L(c.L, rows(c, data, nrows, kmod, limb_off, mode, s));
+}
+
+hipError_t launch_fwd_ext(const DevCtx &c, const uint64_t *a, const uint64_t *b, uint64_t *E,
+                          int npoly, size_t items, hipStream_t s) {
+    if (items == 0) return hipSuccess;
+    FHE_DISPATCH_L(c.L, fwd_ext(c, a, b, E, npoly, items, s));
+}
+
+hipError_t launch_tensor_intt(const DevCtx &c, const uint64_t *E, uint64_t *Dt, bool square,
+                              size_t items, hipStream_t s) {
+    if (items == 0) return hipSuccess;
+    FHE_DISPATCH_L(c.L, tensor(c, E, Dt, square, items, s));
+}
+
+hipError_t launch_relin_digits(const DevCtx &c, const uint64_t *C2, uint64_t *Dhat, size_t items,
+                               hipStream_t s) {
+    if (items == 0) return hipSuccess;
+    FHE_DISPATCH_L(c.L, relin_digits(c, C2, Dhat, items, s));
+}
+
+hipError_t launch_relin_ip(const DevCtx &c, const uint64_t *Dhat, const uint64_t *rlk, uint64_t *out,
+                           size_t items, hipStream_t s) {
+    if (items == 0) return hipSuccess;
+    FHE_DISPATCH_L(c.L, relin_ip(c, Dhat, rlk, out, items, s));
+}

@@ -1,0 +1,85 @@
+// Modular arithmetic on 64-bit residues for gfx950 (and the host, for tables).
+//
+// All primes are below 2^62, so lazy values up to 4q fit a 64-bit word.
+//  * Shoup multiplication by a constant w (Harvey, "Faster arithmetic for
+//    number-theoretic transforms", 2014): with w' = floor(w 2^64 / q),
+//    a w - floor(a w' / 2^64) q lies in [0, 2q) for every a < 2^64.
+//  * Montgomery multiplication (R = 2^64): REDC(T) = T 2^-64 mod q in [0, 2q)
+//    for T < q 2^64, with qinv_neg = -q^-1 mod 2^64.
+// The 64 x 64 -> 128-bit products lower to v_mad_u64_u32 / v_mul_hi_u32
+// sequences on the 32-bit VALU.
+#pragma once
+#include <stdint.h>
+
+#if defined(__HIPCC__)
+#define FHE_HD __host__ __device__ __forceinline__
+#else
+#define FHE_HD inline
+#endif
+
+typedef unsigned __int128 u128;
+
+FHE_HD uint64_t mulhi64(uint64_t a, uint64_t b) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __umul64hi(a, b);
+#else
+    return (uint64_t)(((u128)a * b) >> 64);
+#endif
+}
+
+// a * w mod q in [0, 2q), any a < 2^64; wp = floor(w * 2^64 / q), w < q.
+FHE_HD uint64_t mul_shoup_lazy(uint64_t a, uint64_t w, uint64_t wp, uint64_t q) {
+    uint64_t qh = mulhi64(a, wp);
+    return a * w - qh * q;
+}
+
+FHE_HD uint64_t csub(uint64_t x, uint64_t m) { return x >= m ? x - m : x; }
+
+FHE_HD uint64_t mul_shoup(uint64_t a, uint64_t w, uint64_t wp, uint64_t q) {
+    return csub(mul_shoup_lazy(a, w, wp, q), q);
+}
+
+// REDC(hi:lo) for hi:lo < q 2^64: returns (hi:lo) 2^-64 mod q in [0, 2q).
+FHE_HD uint64_t redc_lazy(uint64_t hi, uint64_t lo, uint64_t q, uint64_t qinv_neg) {
+    uint64_t m = lo * qinv_neg;
+    uint64_t mh = mulhi64(m, q);
+    return hi + mh + (lo != 0 ? 1u : 0u);
+}
+
+// a b 2^-64 mod q in [0, 2q) for a b < q 2^64 (e.g. a < 4q, b < q, q < 2^62).
+FHE_HD uint64_t mont_mul_lazy(uint64_t a, uint64_t b, uint64_t q, uint64_t qinv_neg) {
+    return redc_lazy(mulhi64(a, b), a * b, q, qinv_neg);
+}
+
+FHE_HD uint64_t add_mod(uint64_t a, uint64_t b, uint64_t q) {  // a, b < q
+    uint64_t s = a + b;
+    return csub(s, q);
+}
+
+FHE_HD uint64_t sub_mod(uint64_t a, uint64_t b, uint64_t q) {  // a, b < q
+    return a >= b ? a - b : a + q - b;
+}
+
+// 128-bit accumulator helpers.
+struct Acc128 {
+    uint64_t lo, hi;
+};
+
+FHE_HD void acc_init(Acc128 &a) { a.lo = 0; a.hi = 0; }
+
+FHE_HD void acc_mac(Acc128 &a, uint64_t x, uint64_t y) {
+    u128 p = (u128)x * y;
+    u128 s = ((u128)a.hi << 64 | a.lo) + p;
+    a.lo = (uint64_t)s;
+    a.hi = (uint64_t)(s >> 64);
+}
+
+// (acc) 2^-64 mod q in [0, q) for any 128-bit acc: the high word is first
+// reduced below 2q by a Shoup multiplication by 1 (one_p = floor(2^64 / q)),
+// which keeps the REDC input below 2q 2^64; REDC then lands in [0, 3q).
+FHE_HD uint64_t acc_reduce_mont(const Acc128 &a, uint64_t q, uint64_t qinv_neg, uint64_t one_p) {
+    uint64_t h = mul_shoup_lazy(a.hi, 1, one_p, q);  // [0, 2q)
+    uint64_t r = redc_lazy(h, a.lo, q, qinv_neg);    // < (2q 2^64 + q 2^64) / 2^64 = 3q
+    r = csub(r, q << 1);
+    return csub(r, q);
+}

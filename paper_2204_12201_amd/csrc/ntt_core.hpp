@@ -1,0 +1,192 @@
+// Negacyclic NTT core for gfx950: one workgroup per row of n = 2^L residues.
+//
+// Transform: forward Cooley-Tukey with the psi twist merged into the twiddles
+// (twiddle table entry i holds psi^bitrev(i)), inverse Gentleman-Sande with
+// psi^-bitrev(i).  The forward output position bitrev(j) receives
+// sum_i a_i psi^(i(2j+1)); the inverse undoes it up to the factor n, which the
+// caller folds into a final scaling.
+//
+// Work decomposition: T = n/E threads, each holding E = 2^LE residues in
+// registers (E = 16 or 32).  The L butterfly levels are split into passes of
+// LE levels (radix E) plus one shorter pass when LE does not divide L.  In pass p
+// a thread owns groups of R = 2^r elements that differ only in the pass's r
+// index bits; between passes the row is exchanged through LDS, stored at
+// position idx + idx/16 (the padding keeps 16 consecutive lanes on distinct
+// bank pairs for every pass's access pattern).  Pass 0 reads the natural
+// order with lanes on consecutive addresses; the last pass leaves each lane
+// with runs of R consecutive positions of the bit-reversed output.
+//
+// Butterflies are Harvey's lazy ones: forward values live in [0, 4q),
+// inverse values in [0, 2q); twiddles are (w, floor(w 2^64 / q)) pairs.
+#pragma once
+#include <hip/hip_runtime.h>
+#include "modarith.hpp"
+
+struct Tw {
+    uint64_t w, wp;
+};
+
+template <int L, int LE = 4>
+struct Geo {
+    static_assert(L >= LE, "row shorter than one thread's elements");
+    static constexpr int N = 1 << L;
+    static constexpr int E = 1 << LE;
+    static constexpr int LT = L - LE;
+    static constexpr int T = 1 << LT;
+    static constexpr int NPASS = (L + LE - 1) / LE;
+    static constexpr int lds_words = N + N / 16;
+    static constexpr int R(int p) { return p < L / LE ? LE : L % LE; }
+    static constexpr int LO(int p) { return L - LE * p - R(p); }
+};
+
+__device__ __forceinline__ int lds_pos(int idx) { return idx + (idx >> 4); }
+
+// Global index of element e of group g of thread tid in pass P.
+template <int L, int LE, int P>
+__device__ __forceinline__ int elem_index(int tid, int g, int e) {
+    constexpr int r = Geo<L, LE>::R(P), lo = Geo<L, LE>::LO(P), LT = Geo<L, LE>::LT;
+    int F = (g << LT) | tid;
+    return ((F >> lo) << (lo + r)) | (e << lo) | (F & ((1 << lo) - 1));
+}
+
+__device__ __forceinline__ void ct_bfly(uint64_t &X, uint64_t &Y, uint64_t w, uint64_t wp,
+                                        uint64_t q, uint64_t q2) {
+    uint64_t x = csub(X, q2);                    // [0, 2q)
+    uint64_t t = mul_shoup_lazy(Y, w, wp, q);    // [0, 2q)
+    X = x + t;                                   // [0, 4q)
+    Y = x - t + q2;                              // [0, 4q)
+}
+
+__device__ __forceinline__ void gs_bfly(uint64_t &X, uint64_t &Y, uint64_t w, uint64_t wp,
+                                        uint64_t q, uint64_t q2) {
+    uint64_t x = X, y = Y;                       // [0, 2q)
+    X = csub(x + y, q2);                         // [0, 2q)
+    Y = mul_shoup_lazy(x - y + q2, w, wp, q);    // [0, 2q)
+}
+
+template <int L, int LE, int P>
+__device__ __forceinline__ void fwd_pass(uint64_t (&x)[1 << LE], int tid, const Tw *__restrict__ tw,
+                                         uint64_t q) {
+    constexpr int r = Geo<L, LE>::R(P), lo = Geo<L, LE>::LO(P), LT = Geo<L, LE>::LT;
+    constexpr int R = 1 << r, G = (1 << LE) >> r, l0 = LE * P;
+    const uint64_t q2 = q << 1;
+#pragma unroll
+    for (int g = 0; g < G; g++) {
+        int F = (g << LT) | tid;
+        int H = F >> lo;
+        if constexpr (lo >= 6 || LT <= lo) H = __builtin_amdgcn_readfirstlane(H);
+#pragma unroll
+        for (int u = 0; u < r; u++) {
+            const int half = R >> (u + 1);
+#pragma unroll
+            for (int v = 0; v < (1 << u); v++) {
+                const Tw W = tw[(1 << (l0 + u)) + (H << u) + v];
+#pragma unroll
+                for (int w = 0; w < half; w++) {
+                    const int e0 = (v << (r - u)) | w;
+                    ct_bfly(x[g * R + e0], x[g * R + e0 + half], W.w, W.wp, q, q2);
+                }
+            }
+        }
+    }
+}
+
+template <int L, int LE, int P>
+__device__ __forceinline__ void inv_pass(uint64_t (&x)[1 << LE], int tid, const Tw *__restrict__ tw,
+                                         uint64_t q) {
+    constexpr int r = Geo<L, LE>::R(P), lo = Geo<L, LE>::LO(P), LT = Geo<L, LE>::LT;
+    constexpr int R = 1 << r, G = (1 << LE) >> r, l0 = LE * P;
+    const uint64_t q2 = q << 1;
+#pragma unroll
+    for (int g = 0; g < G; g++) {
+        int F = (g << LT) | tid;
+        int H = F >> lo;
+        if constexpr (lo >= 6 || LT <= lo) H = __builtin_amdgcn_readfirstlane(H);
+#pragma unroll
+        for (int u = r - 1; u >= 0; u--) {
+            const int half = R >> (u + 1);
+#pragma unroll
+            for (int v = 0; v < (1 << u); v++) {
+                const Tw W = tw[(1 << (l0 + u)) + (H << u) + v];
+#pragma unroll
+                for (int w = 0; w < half; w++) {
+                    const int e0 = (v << (r - u)) | w;
+                    gs_bfly(x[g * R + e0], x[g * R + e0 + half], W.w, W.wp, q, q2);
+                }
+            }
+        }
+    }
+}
+
+template <int L, int LE, int P>
+__device__ __forceinline__ void lds_store(uint64_t *lds, const uint64_t (&x)[1 << LE], int tid) {
+    constexpr int R = 1 << Geo<L, LE>::R(P), G = (1 << LE) / R;
+#pragma unroll
+    for (int g = 0; g < G; g++)
+#pragma unroll
+        for (int e = 0; e < R; e++) lds[lds_pos(elem_index<L, LE, P>(tid, g, e))] = x[g * R + e];
+}
+
+template <int L, int LE, int P>
+__device__ __forceinline__ void lds_load(const uint64_t *lds, uint64_t (&x)[1 << LE], int tid) {
+    constexpr int R = 1 << Geo<L, LE>::R(P), G = (1 << LE) / R;
+#pragma unroll
+    for (int g = 0; g < G; g++)
+#pragma unroll
+        for (int e = 0; e < R; e++) x[g * R + e] = lds[lds_pos(elem_index<L, LE, P>(tid, g, e))];
+}
+
+template <int L, int LE, int P>
+__device__ __forceinline__ void fwd_from(uint64_t (&x)[1 << LE], uint64_t *lds, int tid,
+                                         const Tw *__restrict__ tw, uint64_t q) {
+    fwd_pass<L, LE, P>(x, tid, tw, q);
+    if constexpr (P + 1 < Geo<L, LE>::NPASS) {
+        __syncthreads();
+        lds_store<L, LE, P>(lds, x, tid);
+        __syncthreads();
+        lds_load<L, LE, P + 1>(lds, x, tid);
+        fwd_from<L, LE, P + 1>(x, lds, tid, tw, q);
+    }
+}
+
+template <int L, int LE, int P>
+__device__ __forceinline__ void inv_from(uint64_t (&x)[1 << LE], uint64_t *lds, int tid,
+                                         const Tw *__restrict__ tw, uint64_t q) {
+    inv_pass<L, LE, P>(x, tid, tw, q);
+    if constexpr (P > 0) {
+        __syncthreads();
+        lds_store<L, LE, P>(lds, x, tid);
+        __syncthreads();
+        lds_load<L, LE, P - 1>(lds, x, tid);
+        inv_from<L, LE, P - 1>(x, lds, tid, tw, q);
+    }
+}
+
+// Forward transform of a row held in registers in pass-0 (natural) layout,
+// values < 4q.  Leaves the transform in last-pass layout, values in [0, 4q).
+template <int L, int LE = 4>
+__device__ __forceinline__ void ntt_fwd_regs(uint64_t (&x)[1 << LE], uint64_t *lds, int tid,
+                                             const Tw *__restrict__ tw, uint64_t q) {
+    fwd_from<L, LE, 0>(x, lds, tid, tw, q);
+}
+
+// Inverse transform (without the 1/n factor) of a row held in last-pass
+// layout, values < 2q.  Leaves natural order in pass-0 layout, values < 2q.
+template <int L, int LE = 4>
+__device__ __forceinline__ void ntt_inv_regs(uint64_t (&x)[1 << LE], uint64_t *lds, int tid,
+                                             const Tw *__restrict__ tw, uint64_t q) {
+    inv_from<L, LE, Geo<L, LE>::NPASS - 1>(x, lds, tid, tw, q);
+}
+
+// Global index helpers for the two register layouts.
+template <int L, int LE = 4>
+__device__ __forceinline__ int natural_index(int tid, int s) {  // pass-0 layout, slot s
+    return elem_index<L, LE, 0>(tid, 0, s);
+}
+
+template <int L, int LE = 4>
+__device__ __forceinline__ int bitrev_layout_index(int tid, int s) {  // last-pass layout
+    constexpr int P = Geo<L, LE>::NPASS - 1;
+    constexpr int R = 1 << Geo<L, LE>::R(P);
+    return elem_index<L, LE, P>(tid, s / R, s % R);
+}

@@ -1,0 +1,74 @@
+// Device-side constant tables of a context.
+//
+// Basis Q = {q_0..q_{k-1}} (the ciphertext modulus) is extended by an
+// auxiliary basis P = {p_0..p_{k'-1}} (primes below 2^61 chosen by the
+// library) with P > t n q, so that round(t D / q) of the exact tensor D is
+// uniquely represented modulo P.  Rows of an extended polynomial are ordered
+// Q limbs first, then P limbs ("prime index" 0..K-1, K = k + k').
+#pragma once
+#include <stdint.h>
+
+constexpr int FHE_MAXK = 16;   // Q primes
+constexpr int FHE_MAXKP = 20;  // P primes
+constexpr int FHE_MAXB = 20;   // largest basis handled by the exact path
+
+struct PrimeConst {
+    uint64_t q;
+    uint64_t qinv_neg;   // -q^-1 mod 2^64
+    uint64_t one_p;      // floor(2^64 / q): Shoup companion of 1
+    uint64_t ninv, ninv_p;     // n^-1 mod q (Shoup pair)
+    uint64_t ninvm, ninvm_p;   // n^-1 2^64 mod q (Shoup pair): inverse after Montgomery products
+    uint64_t pad;
+};
+
+// Exact mixed-radix (Garner) conversion of a value given in basis M.
+struct MrcConst {
+    uint32_t K;                              // basis size
+    uint32_t ntarget;                        // number of target primes
+    uint64_t m[FHE_MAXB];                    // basis primes
+    uint64_t inv[FHE_MAXB][FHE_MAXB];        // [m_a^-1]_{m_b}, a < b
+    uint64_t inv_p[FHE_MAXB][FHE_MAXB];      //   Shoup companions (mod m_b)
+    uint64_t one_p[FHE_MAXB];                // floor(2^64 / m_b)
+    uint64_t half_digit[FHE_MAXB];           // mixed-radix digits of (M - 1) / 2
+    uint64_t target[FHE_MAXB + 1];           // target primes (last slot: t for decryption)
+    uint64_t tgt_one_p[FHE_MAXB + 1];
+    uint64_t m_mod_t[FHE_MAXB][FHE_MAXB + 1];    // [m_a]_{target_j}
+    uint64_t m_mod_t_p[FHE_MAXB][FHE_MAXB + 1];  //   Shoup companions
+    uint64_t M_mod_t[FHE_MAXB + 1];              // [M]_{target_j}
+};
+
+struct ConvConst {
+    uint32_t k, kp;
+    uint64_t t;
+    // ---- Q -> P, centred (lift of the inputs) ----
+    uint64_t qhinv[FHE_MAXK], qhinv_p[FHE_MAXK];        // [qhat_i^-1]_{q_i}
+    double inv_q[FHE_MAXK];                              // 1 / q_i
+    uint64_t qhat_pm[FHE_MAXK][FHE_MAXKP];               // [qhat_i]_{p_j} 2^64 (Montgomery form)
+    uint64_t beta_q_p[FHE_MAXK + 1][FHE_MAXKP];          // [beta q]_{p_j}, beta = 0..k
+    // ---- scale: floor((t D + h) / q) modulo P, h = (q-1)/2 ----
+    uint64_t tqhinv[FHE_MAXK], tqhinv_p[FHE_MAXK];      // [t qhat_i^-1]_{q_i}
+    uint64_t hqhinv[FHE_MAXK];                           // [h qhat_i^-1]_{q_i}
+    uint64_t nqinv_pm[FHE_MAXK][FHE_MAXKP];              // [-q_i^-1]_{p_j} 2^64
+    uint64_t tqinv_p[FHE_MAXKP], tqinv_ps[FHE_MAXKP];    // [t q^-1]_{p_j}
+    uint64_t hqinv_p[FHE_MAXKP];                         // [h q^-1]_{p_j}
+    uint64_t h_q[FHE_MAXK];                              // [h]_{q_i}
+    uint64_t h_p[FHE_MAXKP];                             // [h]_{p_j}
+    uint64_t t_q[FHE_MAXK], t_qs[FHE_MAXK];              // [t]_{q_i}
+    uint64_t t_p[FHE_MAXKP], t_ps[FHE_MAXKP];            // [t]_{p_j}
+    uint64_t qinv_p[FHE_MAXKP], qinv_ps[FHE_MAXKP];      // [q^-1]_{p_j}
+    // ---- P -> Q, centred ----
+    uint64_t phinv[FHE_MAXKP], phinv_p[FHE_MAXKP];      // [phat_j^-1]_{p_j}
+    double inv_p[FHE_MAXKP];
+    uint64_t phat_qm[FHE_MAXKP][FHE_MAXK];               // [phat_j]_{q_i} 2^64
+    uint64_t beta_p_q[FHE_MAXKP + 1][FHE_MAXK];          // [beta P]_{q_i}, beta = 0..k'
+    // ---- decryption: m = (h - [Y]_q) q^-1 mod t ----
+    uint64_t h_t, qinv_t, qinv_ts, t_one_p;
+    // ---- plaintext constant: Delta = floor(q / t) ----
+    uint64_t delta_q[FHE_MAXK], delta_qs[FHE_MAXK];      // [Delta]_{q_i}
+};
+
+// Threshold of the floating estimate: the estimate of sum y_i / m_i is within
+// 2^-44.8 of the exact value for bases of up to 16 primes below 2^62 (see the
+// error bound next to the estimate); coefficients whose fractional part is
+// within this margin of the rounding boundary take the exact path.
+constexpr double FHE_EST_MARGIN = 9.094947017729282e-13;  // 2^-40

@@ -1,0 +1,319 @@
+"""Thin ctypes binding of libfhe.so (include/fhe.h).
+
+Argument marshalling only: every homomorphic step runs in the library's HIP
+kernels.  Device buffers are torch int64 tensors used as raw uint64 storage
+(no torch arithmetic touches them); torch supplies device memory and the
+current stream.  Host arrays are numpy.  If the library is not built this
+module raises FheError on first use: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libfhe.so")
+
+ENC_SLOTS, ENC_COEFF = 0, 1
+OP_MUL_RELIN, OP_SQUARE_RELIN, OP_BRIDGE, OP_KEYGEN, OP_ENCRYPT, OP_DECRYPT, OP_RLK_IMPORT = range(1, 8)
+
+STATUS = {0: "ok", -1: "invalid argument", -2: "parameter set rejected", -3: "device allocation failed",
+          -4: "HIP error", -5: "shape mismatch", -6: "non-canonical input word",
+          -7: "operation not supported for these parameters", -8: "workspace too small"}
+
+
+class FheError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        super().__init__(f"{where}: {STATUS.get(status, status)} ({status})")
+        self.status = status
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint32), ("k", ctypes.c_uint32), ("t", ctypes.c_uint64),
+                ("q", ctypes.POINTER(ctypes.c_uint64)), ("encoding", ctypes.c_uint32)]
+
+
+_lib = None
+
+# (name, restype, argtypes); c_void_p stands for pointers and the stream.
+_P, _Z, _U64, _U32, _I = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int
+_SIGS = [
+    ("fhe_ctx_create", _I, [ctypes.POINTER(_Params), _I, ctypes.POINTER(_P)]),
+    ("fhe_ctx_destroy", None, [_P]),
+    ("fhe_ct_words", _Z, [_P]),
+    ("fhe_pk_words", _Z, [_P]),
+    ("fhe_rlk_words", _Z, [_P]),
+    ("fhe_aux_primes", _U32, [_P]),
+    ("fhe_workspace_bytes", _Z, [_P, _I, _Z]),
+    ("fhe_set_batch_limit", _I, [_P, _Z]),
+    ("fhe_keygen", _I, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _Z, _P]),
+    ("fhe_rlk_import", _I, [_P, _P, _P, _P, _Z, _P]),
+    ("fhe_encode", _I, [_P, _P, _P]),
+    ("fhe_decode", _I, [_P, _P, _P]),
+    ("fhe_encrypt", _I, [_P, _P, _P, _P, _P, _P, _Z, _P, _Z, _P]),
+    ("fhe_decrypt", _I, [_P, _P, _P, _P, _Z, _P, _Z, _P]),
+    ("fhe_add", _I, [_P, _P, _P, _P, _Z, _P]),
+    ("fhe_sub", _I, [_P, _P, _P, _P, _Z, _P]),
+    ("fhe_neg", _I, [_P, _P, _P, _Z, _P]),
+    ("fhe_add_plain_const", _I, [_P, _P, _U64, _P, _Z, _P]),
+    ("fhe_sub_plain_const", _I, [_P, _P, _U64, _P, _Z, _P]),
+    ("fhe_mul_relin", _I, [_P, _P, _P, _P, _P, _Z, _P, _Z, _P]),
+    ("fhe_bridge_to_bits", _I, [_P, _P, _P, _U32, _P, _P, _Z, _P, _Z, _P]),
+    ("fhe_bits_to_mod", _I, [_P, _P, _U32, _P, _Z, _P]),
+    ("fhe_ntt", _I, [_P, _I, _P, _Z, _P]),
+    ("fhe_set_timing", _I, [_P, _I]),
+    ("fhe_kernel_kinds", _I, []),
+    ("fhe_kernel_name", ctypes.c_char_p, [_I]),
+    ("fhe_kernel_stats", _I, [_P, _I, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_uint64)]),
+    ("fhe_reset_kernel_stats", _I, [_P]),
+    ("fhe_fallback_count", _I, [_P, ctypes.POINTER(ctypes.c_uint64)]),
+    ("fhe_status_str", ctypes.c_char_p, [_I]),
+]
+
+EXPORTED = [s[0] for s in _SIGS]
+
+
+def lib():
+    """Load libfhe.so; raises FheError if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIBPATH):
+            raise FheError(-4, f"HIP library missing at {LIBPATH} (run __graft_entry__.build())")
+        L = ctypes.CDLL(LIBPATH)
+        for name, res, args in _SIGS:
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status: int, where: str):
+    if status != 0:
+        raise FheError(status, where)
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dptr(t) -> ctypes.c_void_p:
+    assert t.is_cuda and t.is_contiguous(), "device tensor must be a contiguous CUDA tensor"
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _hptr(a: np.ndarray, dtype) -> tuple:
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, a.ctypes.data_as(ctypes.c_void_p)
+
+
+def to_numpy_u64(t) -> np.ndarray:
+    """Device int64 tensor (raw uint64 words) -> numpy uint64 copy."""
+    return t.detach().cpu().numpy().view(np.uint64)
+
+
+def from_numpy_u64(a: np.ndarray, device):
+    """numpy uint64 words -> device int64 tensor holding the same bits."""
+    import torch
+    a = np.ascontiguousarray(a, dtype=np.uint64)
+    return torch.from_numpy(a.view(np.int64).copy()).to(device)
+
+
+class Context:
+    """One parameter set on one HIP device (not thread safe)."""
+
+    def __init__(self, n: int, q, t: int, encoding: str = "slots", device: int = 0):
+        import torch
+        self.n, self.q, self.t = int(n), [int(x) for x in q], int(t)
+        self.k = len(self.q)
+        self.encoding = encoding
+        self.device = torch.device("cuda", device)
+        qarr = (ctypes.c_uint64 * self.k)(*self.q)
+        p = _Params(self.n, self.k, self.t, ctypes.cast(qarr, ctypes.POINTER(ctypes.c_uint64)),
+                    ENC_SLOTS if encoding == "slots" else ENC_COEFF)
+        h = ctypes.c_void_p()
+        _check(lib().fhe_ctx_create(ctypes.byref(p), device, ctypes.byref(h)), "fhe_ctx_create")
+        self._h = h
+        self.ct_words = lib().fhe_ct_words(h)
+        self.rlk_words = lib().fhe_rlk_words(h)
+        self.aux_primes = lib().fhe_aux_primes(h)
+        self._ws = {}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().fhe_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ----------------------------------------------------------- buffers ---
+    def empty_ct(self, count: int):
+        import torch
+        return torch.empty((count, 2, self.k, self.n), dtype=torch.int64, device=self.device)
+
+    def workspace(self, op: int, count: int):
+        """Cached device workspace of at least fhe_workspace_bytes(op, count)."""
+        import torch
+        need = lib().fhe_workspace_bytes(self._h, op, count)
+        cur = self._ws.get("buf")
+        if cur is None or cur.numel() < need:
+            self._ws["buf"] = None
+            cur = torch.empty(max(need, 8), dtype=torch.uint8, device=self.device)
+            self._ws["buf"] = cur
+        return cur, need
+
+    def set_batch_limit(self, items: int):
+        _check(lib().fhe_set_batch_limit(self._h, items), "fhe_set_batch_limit")
+        self._ws.clear()
+
+    # -------------------------------------------------------------- keys ---
+    def keygen(self, s, pk_a, pk_e, rlk_a, rlk_e):
+        import torch
+        s, ps = _hptr(s, np.int8)
+        pk_a, ppa = _hptr(pk_a, np.uint64)
+        pk_e, ppe = _hptr(pk_e, np.int32)
+        rlk_a, pra = _hptr(rlk_a, np.uint64)
+        rlk_e, pre = _hptr(rlk_e, np.int32)
+        pk = torch.empty((2, self.k, self.n), dtype=torch.int64, device=self.device)
+        rlk = torch.empty(self.rlk_words, dtype=torch.int64, device=self.device)
+        ws, need = self.workspace(OP_KEYGEN, 1)
+        _check(lib().fhe_keygen(self._h, ps, ppa, ppe, pra, pre, _dptr(pk), _dptr(rlk), _dptr(ws),
+                                ws.numel(), _stream()), "fhe_keygen")
+        return pk, rlk
+
+    def rlk_import(self, rlk_coeff):
+        """rlk_coeff: device tensor [k][2][k][n] (coefficient form)."""
+        import torch
+        rlk = torch.empty(self.rlk_words, dtype=torch.int64, device=self.device)
+        _check(lib().fhe_rlk_import(self._h, _dptr(rlk_coeff.contiguous()), _dptr(rlk), None, 0,
+                                    _stream()), "fhe_rlk_import")
+        return rlk
+
+    # ---------------------------------------------------------- encoding ---
+    def encode(self, vals) -> np.ndarray:
+        v, pv = _hptr(vals, np.uint64)
+        out = np.empty(self.n, dtype=np.uint64)
+        _check(lib().fhe_encode(self._h, pv, out.ctypes.data_as(ctypes.c_void_p)), "fhe_encode")
+        return out
+
+    def decode(self, pt) -> np.ndarray:
+        p, pp = _hptr(pt, np.uint64)
+        out = np.empty(self.n, dtype=np.uint64)
+        _check(lib().fhe_decode(self._h, pp, out.ctypes.data_as(ctypes.c_void_p)), "fhe_decode")
+        return out
+
+    # -------------------------------------------------------- enc / dec ---
+    def encrypt(self, pk, pts, u, e):
+        """pts uint64 [count][n], u int8 [count][n], e int32 [count][2][n]."""
+        pts, pp = _hptr(pts, np.uint64)
+        count = pts.shape[0]
+        u, pu = _hptr(u, np.int8)
+        e, pe = _hptr(e, np.int32)
+        ct = self.empty_ct(count)
+        ws, need = self.workspace(OP_ENCRYPT, count)
+        _check(lib().fhe_encrypt(self._h, _dptr(pk), pp, pu, pe, _dptr(ct), count, _dptr(ws), ws.numel(),
+                                 _stream()), "fhe_encrypt")
+        return ct
+
+    def decrypt(self, s, ct) -> np.ndarray:
+        s, ps = _hptr(s, np.int8)
+        count = ct.shape[0]
+        out = np.empty((count, self.n), dtype=np.uint64)
+        ws, need = self.workspace(OP_DECRYPT, count)
+        _check(lib().fhe_decrypt(self._h, ps, _dptr(ct), out.ctypes.data_as(ctypes.c_void_p), count,
+                                 _dptr(ws), ws.numel(), _stream()), "fhe_decrypt")
+        return out
+
+    # ------------------------------------------------------- elementwise ---
+    def _out(self, out, like):
+        return self.empty_ct(like.shape[0]) if out is None else out
+
+    def add(self, a, b, out=None):
+        out = self._out(out, a)
+        _check(lib().fhe_add(self._h, _dptr(a), _dptr(b), _dptr(out), a.shape[0], _stream()), "fhe_add")
+        return out
+
+    def sub(self, a, b, out=None):
+        out = self._out(out, a)
+        _check(lib().fhe_sub(self._h, _dptr(a), _dptr(b), _dptr(out), a.shape[0], _stream()), "fhe_sub")
+        return out
+
+    def neg(self, a, out=None):
+        out = self._out(out, a)
+        _check(lib().fhe_neg(self._h, _dptr(a), _dptr(out), a.shape[0], _stream()), "fhe_neg")
+        return out
+
+    def add_plain(self, a, c: int, out=None):
+        out = self._out(out, a)
+        _check(lib().fhe_add_plain_const(self._h, _dptr(a), c, _dptr(out), a.shape[0], _stream()),
+               "fhe_add_plain_const")
+        return out
+
+    def sub_plain(self, a, c: int, out=None):
+        out = self._out(out, a)
+        _check(lib().fhe_sub_plain_const(self._h, _dptr(a), c, _dptr(out), a.shape[0], _stream()),
+               "fhe_sub_plain_const")
+        return out
+
+    # ---------------------------------------------------------- hot path ---
+    def mul_relin(self, rlk, a, b, out=None):
+        out = self._out(out, a)
+        count = a.shape[0]
+        op = OP_SQUARE_RELIN if a.data_ptr() == b.data_ptr() else OP_MUL_RELIN
+        ws, need = self.workspace(op, count)
+        _check(lib().fhe_mul_relin(self._h, _dptr(rlk), _dptr(a), _dptr(b), _dptr(out), count, _dptr(ws),
+                                   ws.numel(), _stream()), "fhe_mul_relin")
+        return out
+
+    def bridge_to_bits(self, rlk, x, nbits: int, with_eq: bool = False):
+        import torch
+        count = x.shape[0]
+        bits = torch.empty((count, nbits, 2, self.k, self.n), dtype=torch.int64, device=self.device)
+        eq = (torch.empty((count, self.t, 2, self.k, self.n), dtype=torch.int64, device=self.device)
+              if with_eq else None)
+        ws, need = self.workspace(OP_BRIDGE, count)
+        _check(lib().fhe_bridge_to_bits(self._h, _dptr(rlk), _dptr(x), nbits, _dptr(bits),
+                                        _dptr(eq) if eq is not None else None, count, _dptr(ws),
+                                        ws.numel(), _stream()), "fhe_bridge_to_bits")
+        return (bits, eq) if with_eq else bits
+
+    def bits_to_mod(self, bits, out=None):
+        count, nbits = bits.shape[0], bits.shape[1]
+        out = self.empty_ct(count) if out is None else out
+        _check(lib().fhe_bits_to_mod(self._h, _dptr(bits), nbits, _dptr(out), count, _stream()),
+               "fhe_bits_to_mod")
+        return out
+
+    def ntt(self, polys, inverse: bool = False):
+        """In place on a device tensor [count][k][n]."""
+        _check(lib().fhe_ntt(self._h, 1 if inverse else 0, _dptr(polys), polys.shape[0], _stream()),
+               "fhe_ntt")
+        return polys
+
+    # ------------------------------------------------------------ timing ---
+    def set_timing(self, on: bool):
+        _check(lib().fhe_set_timing(self._h, 1 if on else 0), "fhe_set_timing")
+
+    def kernel_stats(self) -> dict:
+        out = {}
+        for kind in range(lib().fhe_kernel_kinds()):
+            ms, cnt = ctypes.c_double(), ctypes.c_uint64()
+            _check(lib().fhe_kernel_stats(self._h, kind, ctypes.byref(ms), ctypes.byref(cnt)),
+                   "fhe_kernel_stats")
+            out[lib().fhe_kernel_name(kind).decode()] = (ms.value, cnt.value)
+        return out
+
+    def reset_kernel_stats(self):
+        _check(lib().fhe_reset_kernel_stats(self._h), "fhe_reset_kernel_stats")
+
+    def fallback_count(self) -> int:
+        v = ctypes.c_uint64()
+        _check(lib().fhe_fallback_count(self._h, ctypes.byref(v)), "fhe_fallback_count")
+        return v.value

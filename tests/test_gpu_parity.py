@@ -1,0 +1,353 @@
+"""GPU parity: the HIP library against the CPU oracle, word for word.
+
+Every comparison is exact (integer work): each output uint64 word of the
+library must equal the oracle's.  Small sizes compare everything; the full
+workload sizes (n = 16384, eight 55-bit primes) compare sampled outputs the
+oracle can compute one by one, plus properties that hold at any size.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import bfv
+from paper_2204_12201_amd import fhe, inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[gpu-parity] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    fhe.lib()  # fails loudly when the HIP library is missing
+    return torch.device("cuda:0")
+
+
+def up(a):
+    return fhe.from_numpy_u64(np.asarray(a, dtype=np.uint64), "cuda")
+
+
+def down(t):
+    import torch
+    torch.cuda.synchronize()
+    return fhe.to_numpy_u64(t)
+
+
+def setup(n, qs, t, enc, seed):
+    P = bfv.Params(n, qs, t, enc)
+    km = inputs.key_material(n, qs, seed)
+    pk, rlk = bfv.keygen(P, km["s"], km["pk_a"], km["pk_e"], km["rlk_a"], km["rlk_e"])
+    ctx = fhe.Context(n, qs, t, enc)
+    rlk_dev = ctx.rlk_import(up(rlk))
+    return P, km, pk, rlk, ctx, rlk_dev
+
+
+SMALL = [
+    # (n, bits, k, t, encoding)
+    (16, 30, 2, 17, "coeff"),
+    (64, 50, 1, 17, "coeff"),        # one prime: trivial base of Q
+    (64, 55, 4, 257, "slots"),
+    (256, 36, 3, 65537, "slots"),
+    (1024, 55, 8, 17, "coeff"),
+    (2048, 61, 3, 65537, "slots"),   # primes right below 2^61
+]
+
+
+# ------------------------------------------------------------- transforms ----
+
+@pytest.mark.parametrize("n,bits,k", [(16, 30, 2), (32, 40, 2), (64, 50, 3), (512, 45, 2),
+                                      (1024, 55, 3), (4096, 36, 3), (8192, 43, 2), (16384, 55, 2),
+                                      (16384, 61, 1)])
+def test_ntt_pinned_order(dev, n, bits, k):
+    qs = bfv.ntt_primes(n, bits, k)
+    say(f"ntt n={n} k={k} bits={bits}")
+    ctx = fhe.Context(n, qs, 17, "coeff")
+    rng = np.random.default_rng(n + k)
+    count = 3
+    polys = np.stack([np.stack([rng.integers(0, q, n, dtype=np.uint64) for q in qs]) for _ in range(count)])
+    d = up(polys)
+    ctx.ntt(d)
+    got = down(d)
+    psis = [bfv.find_psi(q, n) for q in qs]
+    L = n.bit_length() - 1
+    rev = np.array([int(format(j, f"0{L}b")[::-1], 2) for j in range(n)])
+    for c in range(count):
+        want = bfv.clib.ntt_rows(polys[c], qs, psis)  # natural order A_j
+        assert (got[c][:, rev] == want).all(), f"poly {c}"
+    ctx.ntt(d, inverse=True)
+    assert (down(d) == polys).all()
+
+
+# -------------------------------------------------------- keys, enc, dec ----
+
+@pytest.mark.parametrize("n,bits,k,t,enc", [(64, 55, 4, 257, "slots"), (4096, 36, 3, 65537, "slots"),
+                                            (16384, 55, 8, 17, "coeff")])
+def test_keygen_encrypt_decrypt_match_oracle(dev, n, bits, k, t, enc):
+    qs = bfv.ntt_primes(n, bits, k)
+    say(f"keys n={n} k={k}")
+    P = bfv.Params(n, qs, t, enc)
+    km = inputs.key_material(n, qs, 21)
+    pk, rlk = bfv.keygen(P, km["s"], km["pk_a"], km["pk_e"], km["rlk_a"], km["rlk_e"])
+    ctx = fhe.Context(n, qs, t, enc)
+    pk_d, rlk_d = ctx.keygen(km["s"], km["pk_a"], km["pk_e"], km["rlk_a"], km["rlk_e"])
+    assert (down(pk_d) == pk).all()
+    assert (down(rlk_d) == down(ctx.rlk_import(up(rlk)))).all()
+    count = 2
+    vals = inputs.slot_messages(n, t, count, 21)
+    pts = np.stack([bfv.encode(P, v) for v in vals])
+    assert all((ctx.encode(v) == p).all() for v, p in zip(vals, pts))
+    assert all((ctx.decode(p) == v).all() for v, p in zip(vals, pts))
+    r = inputs.encryption_randomness(n, count, 21)
+    ct_d = ctx.encrypt(pk_d, pts, r["u"], r["e"])
+    want = np.stack([bfv.encrypt(P, pk, pts[j], r["u"][j], r["e"][j]) for j in range(count)])
+    assert (down(ct_d) == want).all()
+    dec = ctx.decrypt(km["s"], ct_d)
+    assert (dec == pts).all()
+    # decrypt of uniform (non-encryption) words still equals the oracle's rounding
+    u = inputs.uniform_ciphertexts(n, qs, 2, 5)
+    assert (ctx.decrypt(km["s"], up(u)) == np.stack([bfv.decrypt(P, km["s"], c) for c in u])).all()
+
+
+# ------------------------------------------------------------ multiply -------
+
+@pytest.mark.parametrize("n,bits,k,t,enc", SMALL)
+def test_mul_relin_small_all_words(dev, n, bits, k, t, enc):
+    qs = bfv.ntt_primes(n, bits, k)
+    say(f"mul_relin small n={n} k={k} t={t}")
+    P, km, pk, rlk, ctx, rlk_d = setup(n, qs, t, enc, 7)
+    count = 5
+    a = inputs.uniform_ciphertexts(n, qs, count, 1, "a")
+    b = inputs.uniform_ciphertexts(n, qs, count, 1, "b")
+    out = down(ctx.mul_relin(rlk_d, up(a), up(b)))
+    sq = down(ctx.mul_relin(rlk_d, up(a), up(a)))  # distinct buffers: general kernels
+    da = up(a)
+    sq2 = down(ctx.mul_relin(rlk_d, da, da))  # same buffer: squaring kernels
+    for j in range(count):
+        want = bfv.mul_relin(P, a[j], b[j], rlk)
+        assert (out[j] == want).all(), f"product {j}"
+        want_sq = bfv.mul_relin(P, a[j], a[j], rlk)
+        assert (sq[j] == want_sq).all() and (sq2[j] == want_sq).all(), f"square {j}"
+
+
+def test_exact_path_boundary_inputs(dev):
+    """Coefficients on the centring boundary (q-1)/2, (q+1)/2 and products whose
+    t D / q sits next to a half-integer force the exact mixed-radix path; the
+    words must still equal the oracle's."""
+    n = 64
+    qs = bfv.ntt_primes(n, 55, 4)
+    P, km, pk, rlk, ctx, rlk_d = setup(n, qs, 17, "coeff", 9)
+    q = P.q
+    before = ctx.fallback_count()
+    special = [(q - 1) // 2, (q + 1) // 2, 0, q - 1, 1, (q - 3) // 2, (q + 3) // 2]
+    vals = [special[i % len(special)] for i in range(n)]
+    rot = vals[3:] + vals[:3]
+    a = np.stack([bfv.from_ints(P, vals), bfv.from_ints(P, rot)])[None]
+    alpha = [((2 * m + 1) * q + P.t) // (2 * P.t) for m in range(4)]
+    a2 = np.stack([bfv.from_ints(P, alpha + [0] * (n - 4)), bfv.from_ints(P, [0] * n)])[None]
+    one = np.stack([bfv.from_ints(P, [1] + [0] * (n - 1)), bfv.from_ints(P, [0] * n)])[None]
+    A = np.concatenate([a, a2])
+    B = np.concatenate([a[:, ::-1].copy(), one])
+    out = down(ctx.mul_relin(rlk_d, up(A), up(B)))
+    for j in range(2):
+        assert (out[j] == bfv.mul_relin(P, A[j], B[j], rlk)).all(), j
+    assert ctx.fallback_count() > before
+
+
+def test_mul_relin_plain_bfv_n4096_workload(dev):
+    """n=4096, three 36-bit primes, t=65537: 64 products of fresh encryptions,
+    every word against the oracle, and decryption equal to a*b mod t."""
+    cfg = inputs.CONFIGS["bfv_n4096"]
+    n, qs, t = cfg["n"], cfg["q"], cfg["t"]
+    count = cfg["count"]
+    say("mul_relin n=4096 k=3 x64")
+    P, km, pk, rlk, ctx, rlk_d = setup(n, qs, t, "slots", 0)
+    msgs = inputs.slot_messages(n, t, 2 * count, 0)
+    r = inputs.encryption_randomness(n, 2 * count, 0)
+    pts = np.stack([bfv.encode(P, m) for m in msgs])
+    cts = np.stack([bfv.encrypt(P, pk, pts[j], r["u"][j], r["e"][j]) for j in range(2 * count)])
+    out = down(ctx.mul_relin(rlk_d, up(cts[:count]), up(cts[count:])))
+    for j in range(count):
+        want = bfv.mul_relin(P, cts[j], cts[count + j], rlk)
+        assert (out[j] == want).all(), f"product {j}"
+    dec = ctx.decrypt(km["s"], up(out))
+    for j in range(count):
+        prod = msgs[j].astype(object) * msgs[count + j].astype(object) % t
+        assert (ctx.decode(dec[j]).astype(object) == prod).all(), j
+
+
+def test_mul_relin_n8192_k5_sampled(dev):
+    cfg = inputs.CONFIGS["bfv_n8192"]
+    n, qs, t = cfg["n"], cfg["q"], cfg["t"]
+    say("mul_relin n=8192 k=5 x9 (3 compared)")
+    P, km, pk, rlk, ctx, rlk_d = setup(n, qs, t, "slots", 2)
+    a = inputs.uniform_ciphertexts(n, qs, 9, 2, "a")
+    b = inputs.uniform_ciphertexts(n, qs, 9, 2, "b")
+    out = down(ctx.mul_relin(rlk_d, up(a), up(b)))
+    for j in (0, 4, 8):
+        assert (out[j] == bfv.mul_relin(P, a[j], b[j], rlk)).all(), j
+
+
+def test_mul_relin_n16384_batched_equals_single(dev):
+    """n=16384, eight 55-bit primes, t=65537: two products against the oracle;
+    one batched call equals eight single-pair calls word for word, and a
+    repeated call is bitwise identical (determinism)."""
+    cfg = inputs.CONFIGS["bfv_n16384"]
+    n, qs, t = cfg["n"], cfg["q"], cfg["t"]
+    say("mul_relin n=16384 k=8 batched vs single")
+    P, km, pk, rlk, ctx, rlk_d = setup(n, qs, t, "slots", 3)
+    B = 8
+    a = inputs.uniform_ciphertexts(n, qs, B, 3, "a")
+    b = inputs.uniform_ciphertexts(n, qs, B, 3, "b")
+    da, db = up(a), up(b)
+    batched = down(ctx.mul_relin(rlk_d, da, db))
+    again = down(ctx.mul_relin(rlk_d, da, db))
+    assert (batched == again).all()
+    single = np.stack([down(ctx.mul_relin(rlk_d, da[j:j + 1].contiguous(), db[j:j + 1].contiguous()))[0]
+                       for j in range(B)])
+    assert (batched == single).all()
+    for j in (0, B - 1):
+        assert (batched[j] == bfv.mul_relin(P, a[j], b[j], rlk)).all(), j
+    # chunked execution (batch limit 3 < 8) gives the same words
+    ctx.set_batch_limit(3)
+    assert (down(ctx.mul_relin(rlk_d, da, db)) == batched).all()
+
+
+# ----------------------------------------------------------- elementwise ----
+
+def test_elementwise_ops(dev):
+    n = 256
+    qs = bfv.ntt_primes(n, 55, 3)
+    P = bfv.Params(n, qs, 17, "coeff")
+    ctx = fhe.Context(n, qs, 17, "coeff")
+    say("elementwise n=256")
+    a = inputs.uniform_ciphertexts(n, qs, 3, 8, "a")
+    b = inputs.uniform_ciphertexts(n, qs, 3, 8, "b")
+    da, db = up(a), up(b)
+    assert (down(ctx.add(da, db)) == np.stack([bfv.add(P, x, y) for x, y in zip(a, b)])).all()
+    assert (down(ctx.sub(da, db)) == np.stack([bfv.sub(P, x, y) for x, y in zip(a, b)])).all()
+    assert (down(ctx.neg(da)) == np.stack([bfv.neg(P, x) for x in a])).all()
+    for c in (0, 1, 16):
+        assert (down(ctx.add_plain(da, c)) == np.stack([bfv.add_plain(P, x, c) for x in a])).all()
+        assert (down(ctx.sub_plain(da, c)) == np.stack([bfv.sub_plain(P, x, c) for x in a])).all()
+    bits = inputs.uniform_ciphertexts(n, qs, 2 * 5, 8, "bits").reshape(2, 5, 2, 3, n)
+    got = down(ctx.bits_to_mod(up(bits.reshape(2, 5, 2, 3, n))))
+    for j in range(2):
+        assert (got[j] == bfv.recompose(P, list(bits[j]))).all()
+    # in place
+    ctx.add(da, db, out=da)
+    assert (down(da) == np.stack([bfv.add(P, x, y) for x, y in zip(a, b)])).all()
+
+
+# ----------------------------------------------------------------- bridge ----
+
+def test_bridge_small_all_words(dev):
+    """t = 17 at n = 64 (four 55-bit primes): every eq_c and bit word against
+    the oracle; decrypted bits are the plain bits of x and recompose to x."""
+    n = 64
+    qs = bfv.ntt_primes(n, 55, 4)
+    say("bridge n=64")
+    P, km, pk, rlk, ctx, rlk_d = setup(n, qs, 17, "coeff", 11)
+    xs = [0, 16, 5, 9]
+    r = inputs.encryption_randomness(n, len(xs), 11)
+    pts = np.zeros((len(xs), n), dtype=np.uint64)
+    pts[:, 0] = xs
+    cts = np.stack([bfv.encrypt(P, pk, pts[j], r["u"][j], r["e"][j]) for j in range(len(xs))])
+    bits, eq = ctx.bridge_to_bits(rlk_d, up(cts), 5, with_eq=True)
+    bits, eq = down(bits), down(eq)
+    for j, x in enumerate(xs):
+        want_bits, want_eq = bfv.bridge_to_bits(P, cts[j], rlk, 5)
+        assert (eq[j] == want_eq).all(), f"eq {j}"
+        assert (bits[j] == want_bits).all(), f"bits {j}"
+    dec = ctx.decrypt(km["s"], up(bits.reshape(-1, 2, 4, n))).reshape(len(xs), 5, n)
+    for j, x in enumerate(xs):
+        assert [int(dec[j, b, 0]) for b in range(5)] == [(x >> b) & 1 for b in range(5)]
+        assert (dec[j, :, 1:] == 0).all()
+    rec = ctx.bits_to_mod(up(bits))
+    assert [int(v) for v in ctx.decrypt(km["s"], rec)[:, 0]] == xs
+
+
+def test_bridge_full_size_sampled(dev):
+    """The bridge workload: n = 16384, eight 55-bit primes, p = 17.  A batch of
+    32 encrypted inputs: sampled equality chains against the oracle word for
+    word, every bit ciphertext equal to the sum of its eq_c (checked with the
+    oracle's addition), and every decrypted bit equal to the plain bit."""
+    cfg = inputs.CONFIGS["bridge_n16384"]
+    n, qs, t = cfg["n"], cfg["q"], cfg["t"]
+    say("bridge n=16384 k=8 x32")
+    P, km, pk, rlk, ctx, rlk_d = setup(n, qs, t, "coeff", 0)
+    count = 32
+    xs = inputs.bridge_values(t, count, 0)
+    pk_d = up(pk)
+    pts = np.zeros((count, n), dtype=np.uint64)
+    pts[:, 0] = xs
+    r = inputs.encryption_randomness(n, count, 0)
+    ct_d = ctx.encrypt(pk_d, pts, r["u"], r["e"])
+    cts = down(ct_d)
+    bits, eq = ctx.bridge_to_bits(rlk_d, ct_d, 5, with_eq=True)
+    bits_h, eq_h = down(bits), down(eq)
+    for (j, c) in [(0, int(xs[0])), (1, (int(xs[1]) + 3) % t)]:
+        assert (eq_h[j, c] == bfv.bridge_eq(P, cts[j], rlk, c)).all(), (j, c)
+    for j in (0, 7):
+        want = bfv.bridge_bits(P, list(eq_h[j]), 5)
+        assert (bits_h[j] == want).all(), j
+    dec = ctx.decrypt(km["s"], bits.reshape(-1, 2, len(qs), n)).reshape(count, 5, n)
+    for j in range(count):
+        assert [int(dec[j, b, 0]) for b in range(5)] == [(int(xs[j]) >> b) & 1 for b in range(5)], j
+
+
+# ------------------------------------------------------------------ edges ----
+
+def test_edge_cases(dev):
+    import torch
+    n = 64
+    qs = bfv.ntt_primes(n, 55, 3)
+    say("edge cases")
+    P, km, pk, rlk, ctx, rlk_d = setup(n, qs, 17, "coeff", 13)
+    a = inputs.uniform_ciphertexts(n, qs, 2, 13, "a")
+    b = inputs.uniform_ciphertexts(n, qs, 2, 13, "b")
+    da, db = up(a), up(b)
+    # count 0 is a no-op
+    empty = ctx.empty_ct(0)
+    assert ctx.mul_relin(rlk_d, empty, empty).shape[0] == 0
+    # in place: out == a
+    ctx.mul_relin(rlk_d, da, db, out=da)
+    assert (down(da) == np.stack([bfv.mul_relin(P, a[j], b[j], rlk) for j in range(2)])).all()
+    # workspace too small
+    ws = torch.empty(8, dtype=torch.uint8, device="cuda")
+    out = ctx.empty_ct(2)
+    st = fhe.lib().fhe_mul_relin(ctx._h, fhe._dptr(rlk_d), fhe._dptr(db), fhe._dptr(db), fhe._dptr(out), 2,
+                                 fhe._dptr(ws), 8, fhe._stream())
+    assert st == -8
+    # partial overlap rejected
+    big = ctx.empty_ct(3)
+    st = fhe.lib().fhe_add(ctx._h, fhe._dptr(big), fhe._dptr(big), fhe._dptr(big[1:]), 2, fhe._stream())
+    assert st == -1
+    # bridge needs coefficient encoding with t - 1 a power of two
+    ctx2 = fhe.Context(n, qs, 257, "slots")
+    with pytest.raises(fhe.FheError) as ei:
+        ctx2.bridge_to_bits(rlk_d, db, 9)
+    assert ei.value.status == -7
+    with pytest.raises(fhe.FheError) as ei:
+        ctx.bridge_to_bits(rlk_d, db, 4)  # 2^4 < 17
+    assert ei.value.status == -1
+
+
+def test_validate_flags_noncanonical(dev):
+    n = 64
+    qs = bfv.ntt_primes(n, 55, 3)
+    os.environ["FHE_VALIDATE"] = "1"
+    try:
+        ctx = fhe.Context(n, qs, 17, "coeff")
+    finally:
+        del os.environ["FHE_VALIDATE"]
+    a = inputs.uniform_ciphertexts(n, qs, 1, 2, "a")
+    a[0, 1, 2, 5] = np.uint64(qs[2])  # one word equal to its prime
+    with pytest.raises(fhe.FheError) as ei:
+        ctx.add(up(a), up(a))
+    assert ei.value.status == -6
