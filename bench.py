@@ -1,0 +1,291 @@
+"""Benchmark: the p=17 bridge workload on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Step = one bridge pass over a batch of 256 encrypted inputs x in [0, 17) at
+n = 16384 with eight 55-bit primes: 17 equality chains per input, each four
+squarings with relinearization (17,408 ciphertext mul+relin per step), then
+the bit combination into 5 bit ciphertexts per input.  Inputs are resident in
+HBM (encrypted on the device) before the timed region.
+
+Prints one JSON line with the metric (ciphertext mul+relin per second inside
+the bridge), conversions/s, per-step p50/p99, the plain-vs-batched mul+relin
+comparison at n = 16384 (one pair per call vs one batched call), the roofline
+of the dominant kernel (timed live with HIP events on the launch stream), and
+the CPU oracle timed on a bounded sample of the same work.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "ct mul+relin/s at n=16384 (batched vs plain GPU), bridge conversions/s, p50/p99"
+
+# Peak figures (MI355X, gfx950): 256 CUs x 128 32-bit lanes at 2.4 GHz issue
+# 78.6 T simple VALU lane-ops/s (the fp32 vector peak of 157.3 TFLOP/s counts an
+# FMA as two); 32-bit integer multiplies (v_mul_lo_u32, v_mul_hi_u32,
+# v_mad_u64_u32) issue at half that rate on gfx950.  A lazy 64-bit Shoup
+# butterfly on 32-bit lanes needs at least 10 multiplies (4 for the high half of
+# a*w', 3 each for the low halves of a*w and of quotient*q) and 18 simple ops
+# (64-bit adds, subtracts, compares and selects): 10*2 + 18 = 38 full-rate issue
+# slots, so the butterfly roofline is 78.6e12 / 38 = 2.07e12 butterflies/s.
+CUS, LANES_PER_CU, CLOCK = 256, 128, 2.4e9
+VALU_LANE_OPS = CUS * LANES_PER_CU * CLOCK
+SLOTS_PER_BFLY = 10 * 2 + 18
+PEAK_BFLY = VALU_LANE_OPS / SLOTS_PER_BFLY
+HBM_PEAK = 8.0e12
+
+# HBM bytes per launch of the transform kernels, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE passes (scaled by 2.0 and 1.0, the factors a 1 GiB device copy and
+# fill read back) over launches of 544 ciphertexts, together with the hash of
+# the kernel sources they were taken on.  Reported only while the sources match.
+TRAFFIC = {
+    "relin_fused": {"bytes": 3934599.7 * 1024 * 2.0 + 3054638.1 * 1024 * 1.0, "src": "596eeb07716435e9"},
+    "square_tensor": {"bytes": 3176575.6 * 1024 * 2.0 + 5571093.1 * 1024 * 1.0, "src": "596eeb07716435e9"},
+}
+KERNEL_SOURCES = ["paper_2204_12201_amd/csrc/kernels_ntt.hip", "paper_2204_12201_amd/csrc/ntt_core.hpp",
+                  "paper_2204_12201_amd/csrc/modarith.hpp"]
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def percentile(xs, p):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    i = min(len(xs) - 1, max(0, int(math.ceil(p / 100 * len(xs))) - 1))
+    return xs[i]
+
+
+def transform_rows(ctx, name: str):
+    """Transform rows one item (one squaring) sends through kernel `name`."""
+    k, K = ctx.k, ctx.k + ctx.aux_primes
+    return {"fwd_ext": 2 * K, "tensor_intt": 3 * K, "square_tensor": 5 * K,
+            "relin_fused": k * k + 2 * k}.get(name)
+
+
+def per_launch_items(args) -> int:
+    """Ciphertexts per product launch: the library groups the bridge chains by
+    floor(limit / p) inputs (limit = 546 products of workspace at n = 16384)."""
+    return min(args.inputs, 546 // 17) * 17
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--inputs", type=int, default=256)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one 1 GiB device-to-device copy first (HBM counter scale)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported "
+              "(the work shards by ciphertext across GPUs; this benchmark runs one)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2204_12201_amd import fhe, inputs
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        src = torch.ones(1 << 27, dtype=torch.int64, device=dev)  # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    cfg = inputs.CONFIGS["bridge_n16384"]
+    n, qs, t, nbits = cfg["n"], cfg["q"], cfg["t"], cfg["nbits"]
+    count = args.inputs
+    ctx = fhe.Context(n, qs, t, "coeff")
+    km = inputs.key_material(n, qs, 0)
+    pk, rlk = ctx.keygen(km["s"], km["pk_a"], km["pk_e"], km["rlk_a"], km["rlk_e"])
+    xs = inputs.bridge_values(t, count, 0)
+    pts = np.zeros((count, n), dtype=np.uint64)
+    pts[:, 0] = xs
+    r = inputs.encryption_randomness(n, count, 0)
+    x_ct = ctx.encrypt(pk, pts, r["u"], r["e"])
+    squarings = int(math.log2(t - 1))
+    mul_per_step = count * t * squarings
+    print(f"[bench] setup done: {count} inputs, {mul_per_step} mul_relin per step", file=sys.stderr, flush=True)
+
+    stream = torch.cuda.current_stream()
+    for w in range(args.warmup):
+        bits = ctx.bridge_to_bits(rlk, x_ct, nbits)
+        torch.cuda.synchronize()
+        print(f"[bench] warmup {w + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+
+    # correctness of the last output: decrypted bits equal the plain bits
+    if args.warmup:
+        dec = ctx.decrypt(km["s"], bits.reshape(-1, 2, len(qs), n)).reshape(count, nbits, n)[:, :, 0]
+        want = (xs[:, None].astype(np.int64) >> np.arange(nbits)) & 1
+        assert (dec.astype(np.int64) == want).all(), "bridge output does not decrypt to the bits of x"
+
+    ctx.reset_kernel_stats()
+    ctx.set_timing(True)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        evs[s][0].record(stream)
+        bits = ctx.bridge_to_bits(rlk, x_ct, nbits)
+        evs[s][1].record(stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ctx.set_timing(False)
+    step_ms = [a.elapsed_time(b) for a, b in evs]
+    stats = ctx.kernel_stats()
+    print(f"[bench] timed {args.steps} steps in {elapsed:.3f} s", file=sys.stderr, flush=True)
+
+    value = mul_per_step * args.steps / elapsed
+    conv_per_s = count * args.steps / elapsed
+
+    # dominant kernel and its roofline: algorithmic butterflies over the timed
+    # region (every mul_relin of the bridge runs each transform kernel once per
+    # item) divided by the kernel's summed launch time.
+    kern = {k: v for k, v in stats.items() if v[1] > 0}
+    dom = max(kern, key=lambda k: kern[k][0])
+    dom_ms, dom_launches = kern[dom]
+    rows = transform_rows(ctx, dom)
+    roofline = None
+    if rows is not None:
+        work_total = rows * (n // 2) * int(math.log2(n)) * mul_per_step * args.steps
+        per_launch = work_total / dom_launches
+        avg_s = dom_ms / 1e3 / dom_launches
+        achieved = per_launch / avg_s
+        tr = TRAFFIC.get(dom)
+        traffic = tr["bytes"] if tr and tr["src"] == kernel_source_hash() and per_launch_items(args) == 544 else None
+        roofline = {"bound": "alu", "kernel": dom, "achieved": achieved / 1e12, "peak": PEAK_BFLY / 1e12,
+                    "unit": "Tbutterfly/s", "frac": achieved / PEAK_BFLY, "traffic": traffic,
+                    "traffic_unit": "bytes per launch",
+                    "avg_launch_ms": avg_s * 1e3, "launches": dom_launches,
+                    "butterflies_per_launch": per_launch}
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "mul_relin/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": "bridge_p17_n16384_k8x55bit_256inputs", "n": n, "k": len(qs),
+                   "q_bits": sum(int(q).bit_length() for q in qs), "p": t, "inputs": count,
+                   "mul_relin_per_step": mul_per_step, "aux_primes": ctx.aux_primes,
+                   "parallelism": "single-gpu"},
+        "conversions_per_s": conv_per_s,
+        "step_p50_ms": percentile(step_ms, 50),
+        "step_p99_ms": percentile(step_ms, 99),
+        "kernel_ms": {k: round(v[0], 3) for k, v in kern.items()},
+        "roofline": roofline,
+    }
+
+    if not args.no_plain:
+        out["plain_vs_batched"] = plain_vs_batched(ctx_factory=lambda: fhe.Context(
+            n, qs, 65537, "slots"), fhe=fhe, inputs=inputs, torch=torch)
+        print("[bench] plain vs batched done", file=sys.stderr, flush=True)
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(inputs)
+        print("[bench] cpu baseline done", file=sys.stderr, flush=True)
+
+    print(json.dumps(out))
+
+
+def plain_vs_batched(ctx_factory, fhe, inputs, torch, B=256, single_calls=200):
+    """n = 16384, eight 55-bit primes, t = 65537: B single-pair calls against one
+    call with count = B, on the same ciphertexts; p50/p99 of single-call latency."""
+    ctx = ctx_factory()
+    n, qs = ctx.n, ctx.q
+    km = inputs.key_material(n, qs, 4)
+    pk, rlk = ctx.keygen(km["s"], km["pk_a"], km["pk_e"], km["rlk_a"], km["rlk_e"])
+    a = fhe.from_numpy_u64(inputs.uniform_ciphertexts(n, qs, B, 4, "a"), "cuda")
+    b = fhe.from_numpy_u64(inputs.uniform_ciphertexts(n, qs, B, 4, "b"), "cuda")
+    out = ctx.empty_ct(B)
+    stream = torch.cuda.current_stream()
+    # warm up both paths
+    for _ in range(3):
+        ctx.mul_relin(rlk, a, b, out=out)
+        ctx.mul_relin(rlk, a[:1], b[:1], out=out[:1])
+    torch.cuda.synchronize()
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.mul_relin(rlk, a, b, out=out)
+    torch.cuda.synchronize()
+    batched = B * reps / (time.perf_counter() - t0)
+    views = [(a[j:j + 1], b[j:j + 1], out[j:j + 1]) for j in range(B)]
+    t0 = time.perf_counter()
+    for x, y, o in views:
+        ctx.mul_relin(rlk, x, y, out=o)
+    torch.cuda.synchronize()
+    plain = B / (time.perf_counter() - t0)
+    lat = []
+    for j in range(single_calls):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        x, y, o = views[j % B]
+        e0.record(stream)
+        ctx.mul_relin(rlk, x, y, out=o)
+        e1.record(stream)
+        lat.append((e0, e1))
+    torch.cuda.synchronize()
+    lat_ms = [e0.elapsed_time(e1) for e0, e1 in lat]
+    return {"n": n, "k": len(qs), "t": 65537, "B": B, "batched_mul_relin_per_s": batched,
+            "plain_mul_relin_per_s": plain, "batched_over_plain": batched / plain,
+            "single_call_p50_ms": percentile(lat_ms, 50), "single_call_p99_ms": percentile(lat_ms, 99)}
+
+
+def cpu_baseline(inputs):
+    """The oracle on the host: one bridge chain (4 squarings with relinearization)
+    at n = 16384, eight 55-bit primes, p = 17, repeated for about 15 s."""
+    from oracle import bfv, clib
+    cfg = inputs.CONFIGS["bridge_n16384"]
+    n, qs, t = cfg["n"], cfg["q"], cfg["t"]
+    P = bfv.Params(n, qs, t, "coeff")
+    km = inputs.key_material(n, qs, 0)
+    pk, rlk = bfv.keygen(P, km["s"], km["pk_a"], km["pk_e"], km["rlk_a"], km["rlk_e"])
+    r = inputs.encryption_randomness(n, 1, 0)
+    pt = np.zeros(n, dtype=np.uint64)
+    pt[0] = 5
+    ct = bfv.encrypt(P, pk, pt, r["u"][0], r["e"][0])
+    done = 0
+    t0 = time.perf_counter()
+    y = bfv.sub_plain(P, ct, 3)
+    while time.perf_counter() - t0 < 15.0 or done < 2:
+        y = bfv.mul_relin(P, y, y, rlk)
+        done += 1
+    el = time.perf_counter() - t0
+    return {"value": done / el, "unit": "mul_relin/s", "cores": clib.max_threads(), "kind": "oracle",
+            "sample": f"{done} squarings with relinearization of one bridge chain at n=16384, k=8 "
+                      f"(55-bit primes), p=17 on the host CPU ({os.cpu_count()} logical CPUs visible)",
+            "seconds": el}
+
+
+if __name__ == "__main__":
+    main()

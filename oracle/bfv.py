@@ -25,9 +25,10 @@ paper's introduction):
   eq_c (the eq_c are one-hot, so the bit-level sum has no carries).
 * Recompose (paper, Section 3.2.1, Horner listing): r = b_{S-1}; r = r + r + b_i.
 
-Readings where the paper is silent are listed in the design doc (Delta = floor(q/t),
-residue digits with the CRT idempotent in the key, sub_plain as c0 - Delta c on
-the constant coefficient, the 0..t-1 equality range, ...).
+Where the paper is silent this oracle takes: Delta = floor(q/t); one key
+switching digit per RNS prime, [C2]_{q_i} in [0, q_i), with the CRT idempotent
+in the key; sub_plain(c) = c0 - Delta c on the constant coefficient; equality
+tests for every c in [0, t) with the bits combining c >= 1.
 """
 from __future__ import annotations
 

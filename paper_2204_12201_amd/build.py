@@ -18,6 +18,8 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libfhe.so")
+CALIB_SRC = os.path.join(HERE, "calib", "valu_calib.cpp")
+CALIB_BIN = os.path.join(HERE, "calib", "valu_calib")
 OBJDIR = os.path.join(HERE, "_build")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -50,8 +52,13 @@ def build(verbose: bool = True) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr[-4000:]}")
     os.replace(tmp, LIB)
+    # roofline calibration probe (a separate executable, not part of the library)
+    cmd = [HIPCC, *CFLAGS, "-x", "hip", CALIB_SRC, "-o", CALIB_BIN]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"calibration probe build failed:\n{r.stderr[-4000:]}")
     if verbose:
-        print(f"built {LIB}")
+        print(f"built {LIB} and {CALIB_BIN}")
     return LIB
 
 

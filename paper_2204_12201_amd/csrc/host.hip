@@ -201,9 +201,9 @@ struct fhe_ctx {
 
 namespace {
 
-const char *kKernelNames[KK_COUNT] = {"lift_q2p",     "fwd_ext",  "tensor_intt", "scale_round",
-                                      "relin_digits", "relin_ip", "ntt_rows",    "elementwise",
-                                      "bridge",       "misc"};
+const char *kKernelNames[KK_COUNT] = {"lift_q2p",    "fwd_ext",  "tensor_intt", "square_tensor",
+                                      "scale_round", "relin_fused", "ntt_rows", "elementwise",
+                                      "bridge",      "misc"};
 
 hipEvent_t take_event(fhe_ctx *c) {
     if (!c->free_events.empty()) {
@@ -247,12 +247,10 @@ fhe_status run(fhe_ctx *c, int kind, hipStream_t s, F &&f) {
 
 size_t ct_words(const fhe_ctx *c) { return 2 * (size_t)c->k * c->n; }
 
+// Workspace words per product: E (extended inputs), Dt (tensor), C2.
 size_t item_words_mul(const fhe_ctx *c, bool square) {
     const size_t npoly = square ? 2 : 4;
-    size_t regionA = (npoly + 3) * c->K;  // E then Dt; Dhat reuses it when it fits
-    size_t dhat = (size_t)c->k * c->k;
-    if (dhat > regionA) regionA = dhat;
-    return (regionA + c->k) * c->n;
+    return ((npoly + 3) * c->K + c->k) * c->n;
 }
 
 size_t bridge_group(const fhe_ctx *c) {
@@ -296,17 +294,17 @@ fhe_status mul_relin_impl(fhe_ctx *c, const uint64_t *rlk, const uint64_t *a, co
         uint64_t *oi = out + off * ctw;
         uint64_t *E = (uint64_t *)ws;
         uint64_t *Dt = E + items * npoly * K * n;
-        size_t regionA = (npoly + 3) * K;
-        if ((size_t)k * k > regionA) regionA = k * k;
-        uint64_t *C2 = E + items * regionA * n;
-        uint64_t *Dhat = E;  // E and Dt are dead once C2 is formed
+        uint64_t *C2 = Dt + items * 3 * K * n;
         const DevCtx &d = c->dev;
         FHE_TRY(run(c, KK_LIFT, s, [&] { return launch_lift(d, ai, bi, E, npoly, items, s); }));
-        FHE_TRY(run(c, KK_FWD_EXT, s, [&] { return launch_fwd_ext(d, ai, bi, E, npoly, items, s); }));
-        FHE_TRY(run(c, KK_TENSOR_INTT, s, [&] { return launch_tensor_intt(d, E, Dt, square, items, s); }));
+        if (square) {
+            FHE_TRY(run(c, KK_SQUARE_TENSOR, s, [&] { return launch_square_tensor(d, ai, E, Dt, items, s); }));
+        } else {
+            FHE_TRY(run(c, KK_FWD_EXT, s, [&] { return launch_fwd_ext(d, ai, bi, E, npoly, items, s); }));
+            FHE_TRY(run(c, KK_TENSOR_INTT, s, [&] { return launch_tensor_intt(d, E, Dt, false, items, s); }));
+        }
         FHE_TRY(run(c, KK_SCALE, s, [&] { return launch_scale(d, Dt, oi, C2, items, s); }));
-        FHE_TRY(run(c, KK_RELIN_DIGITS, s, [&] { return launch_relin_digits(d, C2, Dhat, items, s); }));
-        FHE_TRY(run(c, KK_RELIN_IP, s, [&] { return launch_relin_ip(d, Dhat, rlk, oi, items, s); }));
+        FHE_TRY(run(c, KK_RELIN_FUSED, s, [&] { return launch_relin_fused(d, C2, rlk, oi, items, s); }));
     }
     return FHE_OK;
 }
@@ -498,9 +496,19 @@ fhe_status fhe_ctx_create(const fhe_params *p, int hip_device, fhe_ctx **out) {
     cc->t = c->t;
     const uint64_t t = c->t;
     for (uint32_t i = 0; i < k; i++) {
+        cc->q[i] = qs[i];
+        cc->q_qinv[i] = neg_inv64(qs[i]);
+        cc->q_one[i] = shoup(1, qs[i]);
+    }
+    for (uint32_t j = 0; j < c->kp; j++) {
+        cc->p[j] = ps[j];
+        cc->p_qinv[j] = neg_inv64(ps[j]);
+        cc->p_one[j] = shoup(1, ps[j]);
+    }
+    const uint64_t q_mod_t = prod_mod(qs, t);
+    for (uint32_t i = 0; i < k; i++) {
         const uint64_t qi = qs[i];
-        const uint64_t qhat_i = prod_mod(qs, qi, (int)i);
-        const uint64_t qhinv = hinv(qhat_i, qi);
+        const uint64_t qhinv = hinv(prod_mod(qs, qi, (int)i), qi);
         cc->qhinv[i] = qhinv;
         cc->qhinv_p[i] = shoup(qhinv, qi);
         cc->inv_q[i] = 1.0 / (double)qi;
@@ -513,26 +521,24 @@ fhe_status fhe_ctx_create(const fhe_params *p, int hip_device, fhe_ctx **out) {
         cc->t_q[i] = tq;
         cc->t_qs[i] = shoup(tq, qi);
         // Delta = floor(q/t) = (q - [q]_t)/t = -[q]_t t^-1 modulo q_i
-        const uint64_t q_mod_t = prod_mod(qs, t);
         const uint64_t dq = hmul((qi - q_mod_t % qi) % qi, hinv(tq, qi), qi);
         cc->delta_q[i] = dq;
         cc->delta_qs[i] = shoup(dq, qi);
-        for (uint32_t j = 0; j < c->kp; j++) {
-            const uint64_t pj = ps[j];
-            cc->qhat_pm[i][j] = mont(prod_mod(qs, pj, (int)i), pj);
-            const uint64_t qiinv = hinv(qi % pj, pj);
-            cc->nqinv_pm[i][j] = mont((pj - qiinv) % pj, pj);
-        }
     }
     for (uint32_t j = 0; j < c->kp; j++) {
         const uint64_t pj = ps[j];
         const uint64_t qmod = prod_mod(qs, pj);
-        for (uint32_t beta = 0; beta <= k; beta++) cc->beta_q_p[beta][j] = hmul(beta, qmod, pj);
         const uint64_t qinv = hinv(qmod, pj);
         const uint64_t hp = half_mod(qs, pj);
-        cc->tqinv_p[j] = hmul(t % pj, qinv, pj);
-        cc->tqinv_ps[j] = shoup(cc->tqinv_p[j], pj);
-        cc->hqinv_p[j] = hmul(hp, qinv, pj);
+        for (uint32_t i = 0; i < k; i++) {
+            cc->lift_m[j][i] = mont(prod_mod(qs, pj, (int)i), pj);
+            const uint64_t qiinv = hinv(qs[i] % pj, pj);
+            cc->scale_m[j][i] = mont((pj - qiinv) % pj, pj);
+        }
+        cc->lift_m[j][k] = mont((pj - qmod) % pj, pj);
+        cc->scale_m[j][k] = mont(hmul(t % pj, qinv, pj), pj);
+        cc->scale_m[j][k + 1] = mont(1, pj);
+        cc->scale_m[j][k + 2] = mont(hmul(hp, qinv, pj), pj);
         cc->h_p[j] = hp;
         cc->t_p[j] = t % pj;
         cc->t_ps[j] = shoup(t % pj, pj);
@@ -542,14 +548,14 @@ fhe_status fhe_ctx_create(const fhe_params *p, int hip_device, fhe_ctx **out) {
         cc->phinv[j] = hinv(phat, pj);
         cc->phinv_p[j] = shoup(cc->phinv[j], pj);
         cc->inv_p[j] = 1.0 / (double)pj;
-        for (uint32_t i = 0; i < k; i++) cc->phat_qm[j][i] = mont(prod_mod(ps, qs[i], (int)j), qs[i]);
     }
     for (uint32_t i = 0; i < k; i++) {
+        for (uint32_t j = 0; j < c->kp; j++) cc->p2q_m[i][j] = mont(prod_mod(ps, qs[i], (int)j), qs[i]);
         const uint64_t pmod = prod_mod(ps, qs[i]);
-        for (uint32_t beta = 0; beta <= c->kp; beta++) cc->beta_p_q[beta][i] = hmul(beta, pmod, qs[i]);
+        cc->p2q_m[i][c->kp] = mont((qs[i] - pmod) % qs[i], qs[i]);
     }
     cc->h_t = half_mod(qs, t);
-    cc->qinv_t = hinv(prod_mod(qs, t), t);
+    cc->qinv_t = hinv(q_mod_t, t);
     cc->qinv_ts = shoup(cc->qinv_t, t);
     cc->t_one_p = shoup(1, t);
 

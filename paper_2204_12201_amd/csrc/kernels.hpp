@@ -26,9 +26,9 @@ enum KernelKind {
     KK_LIFT = 0,
     KK_FWD_EXT,
     KK_TENSOR_INTT,
+    KK_SQUARE_TENSOR,
     KK_SCALE,
-    KK_RELIN_DIGITS,
-    KK_RELIN_IP,
+    KK_RELIN_FUSED,
     KK_NTT_ROWS,
     KK_ELEMENTWISE,
     KK_BRIDGE,
@@ -53,10 +53,14 @@ hipError_t launch_fwd_ext(const DevCtx &c, const uint64_t *a, const uint64_t *b,
                           int npoly, size_t items, hipStream_t s);
 hipError_t launch_tensor_intt(const DevCtx &c, const uint64_t *E, uint64_t *Dt, bool square,
                               size_t items, hipStream_t s);
-hipError_t launch_relin_digits(const DevCtx &c, const uint64_t *C2, uint64_t *Dhat, size_t items,
-                               hipStream_t s);
-hipError_t launch_relin_ip(const DevCtx &c, const uint64_t *Dhat, const uint64_t *rlk, uint64_t *out,
-                           size_t items, hipStream_t s);
+// Squaring: forward transforms of a0, a1 (P limbs from E) and the three
+// inverse-transformed tensor components, one workgroup per (limb, item).
+hipError_t launch_square_tensor(const DevCtx &c, const uint64_t *a, const uint64_t *E, uint64_t *Dt,
+                                size_t items, hipStream_t s);
+// Key switching: out[item][l] += sum_i [C2]_{q_i} rlk_i[l] for l = 0, 1.
+hipError_t launch_relin_fused(const DevCtx &c, const uint64_t *C2, const uint64_t *rlk, uint64_t *out,
+                              size_t items, hipStream_t s);
+
 
 // ---- base conversions and elementwise (kernels_conv.hip) ----
 hipError_t launch_lift(const DevCtx &c, const uint64_t *a, const uint64_t *b, uint64_t *E, int npoly,

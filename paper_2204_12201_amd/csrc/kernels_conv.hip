@@ -74,7 +74,8 @@ __device__ __forceinline__ uint64_t mrc_eval(const MrcConst &M, const uint64_t (
 
 // Extended rows of the inputs: for every coefficient of poly `blockIdx.y` of
 // item `blockIdx.z`, the centred lift x~ in (-q/2, q/2) written modulo each
-// P prime into E[item][poly][k + j].
+// P prime into E[item][poly][k + j]:
+//   x~ = sum_i y_i qhat_i - beta q,  y_i = [x_i qhat_i^-1]_{q_i},  beta = round(sum_i y_i / q_i).
 template <int MK, int MKP>
 __global__ __launch_bounds__(256) void k_lift(DevCtx c, const uint64_t *__restrict__ a,
                                               const uint64_t *__restrict__ b,
@@ -90,33 +91,32 @@ __global__ __launch_bounds__(256) void k_lift(DevCtx c, const uint64_t *__restri
     const ConvConst &cc = *c.cc;
 
     uint64_t x[MK], y[MK];
+#pragma unroll
+    for (int i = 0; i < MK; i++) x[i] = i < k ? src[(size_t)i * n + coef] : 0;
     double e = 0.0;
 #pragma unroll
     for (int i = 0; i < MK; i++) {
-        x[i] = 0;
         y[i] = 0;
         if (i < k) {
-            const uint64_t qi = c.pc[i].q;
-            x[i] = src[(size_t)i * n + coef];
-            y[i] = mul_shoup(x[i], cc.qhinv[i], cc.qhinv_p[i], qi);
+            y[i] = mul_shoup(x[i], cc.qhinv[i], cc.qhinv_p[i], cc.q[i]);
             e = fma((double)y[i], cc.inv_q[i], e);
         }
     }
     // |e - sum y_i/q_i| <= (2.01 K + 1.01 K^2) 2^-53 < 2^-44 for K <= 20.
     const double fl = floor(e), d = e - fl;
     if (fabs(d - 0.5) >= FHE_EST_MARGIN) {
-        const int beta = (int)fl + (d > 0.5 ? 1 : 0);
+        const uint64_t beta = (uint64_t)fl + (d > 0.5 ? 1 : 0);
 #pragma unroll
         for (int j = 0; j < MKP; j++) {
             if (j < kp) {
-                const PrimeConst &P = c.pc[k + j];
+                const uint64_t *m = cc.lift_m[j];
                 Acc128 acc;
                 acc_init(acc);
 #pragma unroll
                 for (int i = 0; i < MK; i++)
-                    if (i < k) acc_mac(acc, y[i], cc.qhat_pm[i][j]);
-                uint64_t r = acc_reduce_mont(acc, P.q, P.qinv_neg, P.one_p);
-                dst[(size_t)j * n + coef] = sub_mod(r, cc.beta_q_p[beta][j], P.q);
+                    if (i < k) acc_mac(acc, y[i], m[i]);
+                acc_mac(acc, beta, m[k]);
+                dst[(size_t)j * n + coef] = acc_reduce_mont(acc, cc.p[j], cc.p_qinv[j], cc.p_one[j]);
             }
         }
     } else {
@@ -128,9 +128,8 @@ __global__ __launch_bounds__(256) void k_lift(DevCtx c, const uint64_t *__restri
 #pragma unroll
         for (int j = 0; j < MKP; j++) {
             if (j < kp) {
-                const uint64_t pj = c.pc[k + j].q;
                 uint64_t r = mrc_eval<MK>(M, dg, j);
-                if (gt) r = sub_mod(r, M.M_mod_t[j], pj);
+                if (gt) r = sub_mod(r, M.M_mod_t[j], cc.p[j]);
                 dst[(size_t)j * n + coef] = r;
             }
         }
@@ -157,15 +156,19 @@ __global__ __launch_bounds__(256) void k_scale(DevCtx c, const uint64_t *__restr
     uint64_t *dst = comp < 2 ? out + (item * 2 + comp) * (size_t)k * n : C2 + item * (size_t)k * n;
     const ConvConst &cc = *c.cc;
 
+    uint64_t dq[MK], dp[MKP];
+#pragma unroll
+    for (int i = 0; i < MK; i++) dq[i] = i < k ? src[(size_t)i * n + coef] : 0;
+#pragma unroll
+    for (int j = 0; j < MKP; j++) dp[j] = j < kp ? src[(size_t)(k + j) * n + coef] : 0;
+
     uint64_t y[MK];
     double e = 0.0;
 #pragma unroll
     for (int i = 0; i < MK; i++) {
         y[i] = 0;
         if (i < k) {
-            const uint64_t qi = c.pc[i].q;
-            const uint64_t dq = src[(size_t)i * n + coef];
-            y[i] = add_mod(mul_shoup(dq, cc.tqhinv[i], cc.tqhinv_p[i], qi), cc.hqhinv[i], qi);
+            y[i] = add_mod(mul_shoup(dq[i], cc.tqhinv[i], cc.tqhinv_p[i], cc.q[i]), cc.hqhinv[i], cc.q[i]);
             e = fma((double)y[i], cc.inv_q[i], e);
         }
     }
@@ -179,36 +182,36 @@ __global__ __launch_bounds__(256) void k_scale(DevCtx c, const uint64_t *__restr
     for (int j = 0; j < MKP; j++) {
         z[j] = 0;
         if (j < kp) {
-            const PrimeConst &P = c.pc[k + j];
+            const uint64_t *m = cc.scale_m[j];
             Acc128 acc;
             acc_init(acc);
 #pragma unroll
             for (int i = 0; i < MK; i++)
-                if (i < k) acc_mac(acc, y[i], cc.nqinv_pm[i][j]);
-            uint64_t r = acc_reduce_mont(acc, P.q, P.qinv_neg, P.one_p);
-            const uint64_t dp = src[(size_t)(k + j) * n + coef];
-            r = add_mod(r, mul_shoup(dp, cc.tqinv_p[j], cc.tqinv_ps[j], P.q), P.q);
-            r = add_mod(r, cc.hqinv_p[j], P.q);
-            r = add_mod(r, v, P.q);  // v <= k < p_j
-            z[j] = mul_shoup(r, cc.phinv[j], cc.phinv_p[j], P.q);
+                if (i < k) acc_mac(acc, y[i], m[i]);
+            acc_mac(acc, dp[j], m[k]);
+            acc_mac(acc, v, m[k + 1]);
+            acc.lo += m[k + 2];
+            acc.hi += acc.lo < m[k + 2] ? 1u : 0u;
+            const uint64_t r = acc_reduce_mont(acc, cc.p[j], cc.p_qinv[j], cc.p_one[j]);  // C_{p_j}
+            z[j] = mul_shoup(r, cc.phinv[j], cc.phinv_p[j], cc.p[j]);
             e2 = fma((double)z[j], cc.inv_p[j], e2);
         }
     }
     const double fl2 = floor(e2), d2 = e2 - fl2;
     exact = exact || (fabs(d2 - 0.5) < FHE_EST_MARGIN);
     if (!exact) {
-        const int beta = (int)fl2 + (d2 > 0.5 ? 1 : 0);
+        const uint64_t beta = (uint64_t)fl2 + (d2 > 0.5 ? 1 : 0);
 #pragma unroll
         for (int i = 0; i < MK; i++) {
             if (i < k) {
-                const PrimeConst &Q = c.pc[i];
+                const uint64_t *m = cc.p2q_m[i];
                 Acc128 acc;
                 acc_init(acc);
 #pragma unroll
                 for (int j = 0; j < MKP; j++)
-                    if (j < kp) acc_mac(acc, z[j], cc.phat_qm[j][i]);
-                uint64_t r = acc_reduce_mont(acc, Q.q, Q.qinv_neg, Q.one_p);
-                dst[(size_t)i * n + coef] = sub_mod(r, cc.beta_p_q[beta][i], Q.q);
+                    if (j < kp) acc_mac(acc, z[j], m[j]);
+                acc_mac(acc, beta, m[kp]);
+                dst[(size_t)i * n + coef] = acc_reduce_mont(acc, cc.q[i], cc.q_qinv[i], cc.q_one[i]);
             }
         }
         return;
@@ -218,37 +221,31 @@ __global__ __launch_bounds__(256) void k_scale(DevCtx c, const uint64_t *__restr
     atomicAdd(c.fallback, 1ull);
     const MrcConst &MQ = *c.mrc_q;
     const MrcConst &MP = *c.mrc_p;
-    uint64_t yq[MK], dq[MK];
+    uint64_t yq[MK], dgq[MK];
 #pragma unroll
     for (int i = 0; i < MK; i++) {
         yq[i] = 0;
-        if (i < k) {
-            const uint64_t qi = c.pc[i].q;
-            const uint64_t dv = src[(size_t)i * n + coef];
-            yq[i] = add_mod(mul_shoup(dv, cc.t_q[i], cc.t_qs[i], qi), cc.h_q[i], qi);
-        }
+        if (i < k) yq[i] = add_mod(mul_shoup(dq[i], cc.t_q[i], cc.t_qs[i], cc.q[i]), cc.h_q[i], cc.q[i]);
     }
-    mrc_digits<MK>(MQ, yq, dq);
-    uint64_t cp[MKP], dp[MKP];
+    mrc_digits<MK>(MQ, yq, dgq);
+    uint64_t cp[MKP], dgp[MKP];
 #pragma unroll
     for (int j = 0; j < MKP; j++) {
         cp[j] = 0;
         if (j < kp) {
-            const uint64_t pj = c.pc[k + j].q;
-            const uint64_t dv = src[(size_t)(k + j) * n + coef];
-            const uint64_t ypj = add_mod(mul_shoup(dv, cc.t_p[j], cc.t_ps[j], pj), cc.h_p[j], pj);
-            const uint64_t xpj = mrc_eval<MK>(MQ, dq, j);
+            const uint64_t pj = cc.p[j];
+            const uint64_t ypj = add_mod(mul_shoup(dp[j], cc.t_p[j], cc.t_ps[j], pj), cc.h_p[j], pj);
+            const uint64_t xpj = mrc_eval<MK>(MQ, dgq, j);
             cp[j] = mul_shoup(sub_mod(ypj, xpj, pj), cc.qinv_p[j], cc.qinv_ps[j], pj);
         }
     }
-    mrc_digits<MKP>(MP, cp, dp);
-    const bool gt = mrc_gt_half<MKP>(MP, dp);
+    mrc_digits<MKP>(MP, cp, dgp);
+    const bool gt = mrc_gt_half<MKP>(MP, dgp);
 #pragma unroll
     for (int i = 0; i < MK; i++) {
         if (i < k) {
-            const uint64_t qi = c.pc[i].q;
-            uint64_t r = mrc_eval<MKP>(MP, dp, i);
-            if (gt) r = sub_mod(r, MP.M_mod_t[i], qi);
+            uint64_t r = mrc_eval<MKP>(MP, dgp, i);
+            if (gt) r = sub_mod(r, MP.M_mod_t[i], cc.q[i]);
             dst[(size_t)i * n + coef] = r;
         }
     }

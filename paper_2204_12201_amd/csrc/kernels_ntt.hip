@@ -4,9 +4,10 @@
 //  k_fwd_ext       forward transform of the extended inputs of a product
 //  k_tensor_intt   tensor component (Montgomery products of transformed
 //                  inputs, computed on load) followed by the inverse transform
-//  k_relin_digits  key-switching digits [C2]_{q_i} reduced mod q_j, transformed
-//  k_relin_ip      inner product of the transformed digits with the key, then
-//                  the inverse transform added into C0, C1
+//  k_square_tensor squaring: forward transforms of both input polynomials and
+//                  the three inverse-transformed tensor components in one pass
+//  k_relin_fused   key switching: digit transforms, inner product with the key
+//                  and inverse transforms for one output limb
 #include "kernels.hpp"
 #include "modarith.hpp"
 #include "ntt_core.hpp"
@@ -37,7 +38,7 @@ __global__ __launch_bounds__(Geo<L>::T) void k_ntt_rows(DevCtx c, uint64_t *__re
                                                        int kmod, int limb_off, int mode) {
     __shared__ uint64_t lds[Geo<L>::lds_words];
     constexpr int n = Geo<L>::N;
-    const int tid = threadIdx.x;
+    const uint32_t tid = threadIdx.x;
     const size_t row = blockIdx.x;
     const int limb = (int)(row % kmod) + limb_off;
     const PrimeConst &P = c.pc[limb];
@@ -72,7 +73,7 @@ __global__ __launch_bounds__(Geo<L>::T) void k_fwd_ext(DevCtx c, const uint64_t 
                                                       uint64_t *__restrict__ E, int npoly) {
     __shared__ uint64_t lds[Geo<L>::lds_words];
     constexpr int n = Geo<L>::N;
-    const int tid = threadIdx.x;
+    const uint32_t tid = threadIdx.x;
     const int limb = blockIdx.x, poly = blockIdx.y;
     const size_t item = blockIdx.z;
     const int k = c.k, K = c.K;
@@ -100,7 +101,7 @@ __global__ __launch_bounds__(Geo<L>::T) void k_tensor_intt(DevCtx c, const uint6
     __shared__ uint64_t lds[Geo<L>::lds_words];
     constexpr int n = Geo<L>::N;
     constexpr int npoly = SQ ? 2 : 4;
-    const int tid = threadIdx.x;
+    const uint32_t tid = threadIdx.x;
     const int limb = blockIdx.x, comp = blockIdx.y;
     const size_t item = blockIdx.z;
     const int K = c.K;
@@ -111,7 +112,7 @@ __global__ __launch_bounds__(Geo<L>::T) void k_tensor_intt(DevCtx c, const uint6
     uint64_t x[16];
 #pragma unroll
     for (int s = 0; s < 16; s++) {
-        const int idx = bitrev_layout_index<L>(tid, s);
+        const uint32_t idx = bitrev_layout_index<L>(tid, s);
         uint64_t v;
         if (SQ) {
             const uint64_t a0 = base[idx], a1 = base[rs + idx];
@@ -139,71 +140,158 @@ __global__ __launch_bounds__(Geo<L>::T) void k_tensor_intt(DevCtx c, const uint6
     for (int s = 0; s < 16; s++) dst[natural_index<L>(tid, s)] = mul_shoup(x[s], P.ninvm, P.ninvm_p, q);
 }
 
-// Key-switching digits: grid (k targets j, k digits i, items).  Row
-// Dhat[item][i][j] = NTT_j([C2]_{q_i} mod q_j), canonical.  j varies fastest so
-// the k workgroups reading one digit row run together and share it in L2.
+// Squaring, transform phase fused: grid (K limbs, items).  For limb l of item
+// it transforms a0 and a1 (Q limbs straight from the ciphertext, P limbs from
+// the lift in E), then forms d0 = a0^2, d1 = 2 a0 a1, d2 = a1^2 (Montgomery
+// products) and inverse transforms each into Dt[item][comp][l].  One row is
+// held in registers at a time: the transformed inputs are parked in the
+// item's own d1 and d2 output rows, which this workgroup alone touches and
+// rereads from L2 before overwriting.
 template <int L>
-__global__ __launch_bounds__(Geo<L>::T) void k_relin_digits(DevCtx c, const uint64_t *__restrict__ C2,
-                                                           uint64_t *__restrict__ Dhat) {
+__global__ __launch_bounds__(Geo<L>::T) void k_square_tensor(DevCtx c, const uint64_t *__restrict__ a,
+                                                            const uint64_t *__restrict__ E,
+                                                            uint64_t *__restrict__ Dt) {
     __shared__ uint64_t lds[Geo<L>::lds_words];
     constexpr int n = Geo<L>::N;
-    const int tid = threadIdx.x;
-    const int j = blockIdx.x, i = blockIdx.y;
-    const size_t item = blockIdx.z;
-    const int k = c.k;
-    const PrimeConst &P = c.pc[j];
-    const uint64_t q = P.q;
-    const uint64_t *src = C2 + (item * k + i) * (size_t)n;
+    const uint32_t tid = threadIdx.x;
+    const int limb = blockIdx.x;
+    const size_t item = blockIdx.y;
+    const int k = c.k, K = c.K;
+    const PrimeConst &P = c.pc[limb];
+    const uint64_t q = P.q, qi = P.qinv_neg, q2 = q << 1;
+    const Tw *tw = c.tw + (size_t)limb * n;
+    const Tw *itw = c.itw + (size_t)limb * n;
+    const uint64_t *src0, *src1;
+    if (limb < k) {
+        src0 = a + ((item * 2 + 0) * k + limb) * (size_t)n;
+        src1 = a + ((item * 2 + 1) * k + limb) * (size_t)n;
+    } else {
+        src0 = E + ((item * 2 + 0) * K + limb) * (size_t)n;
+        src1 = E + ((item * 2 + 1) * K + limb) * (size_t)n;
+    }
+    uint64_t *d0 = Dt + ((item * 3 + 0) * K + limb) * (size_t)n;
+    uint64_t *d1 = Dt + ((item * 3 + 1) * K + limb) * (size_t)n;
+    uint64_t *d2 = Dt + ((item * 3 + 2) * K + limb) * (size_t)n;
     uint64_t x[16];
+    // A1 = NTT(a1), parked in d2
+    const uint32_t t1 = fresh(tid);
 #pragma unroll
-    for (int s = 0; s < 16; s++)
-        x[s] = mul_shoup_lazy(src[natural_index<L>(tid, s)], 1, P.one_p, q);  // < 2q
-    ntt_fwd_regs<L>(x, lds, tid, c.tw + (size_t)j * n, q);
-    uint64_t *dst = Dhat + ((item * k + i) * k + j) * (size_t)n;
+    for (int s = 0; s < 16; s++) x[s] = src1[natural_index<L>(t1, s)];
+    ntt_fwd_regs<L>(x, lds, tid, tw, q);
 #pragma unroll
-    for (int s = 0; s < 16; s++) dst[bitrev_layout_index<L>(tid, s)] = canon4(x[s], q);
+    for (int s = 0; s < 16; s++) d2[bitrev_layout_index<L>(fresh(tid), s)] = canon4(x[s], q);
+    asm volatile("" ::: "memory");
+    // A0 = NTT(a0), parked in d1
+    const uint32_t t2 = fresh(tid);
+#pragma unroll
+    for (int s = 0; s < 16; s++) x[s] = src0[natural_index<L>(t2, s)];
+    ntt_fwd_regs<L>(x, lds, tid, tw, q);
+    const uint32_t t3 = fresh(tid);
+#pragma unroll
+    for (int s = 0; s < 16; s++) {
+        x[s] = canon4(x[s], q);
+        d1[bitrev_layout_index<L>(t3, s)] = x[s];
+    }
+    asm volatile("" ::: "memory");
+    // d0 = INTT(A0^2)
+#pragma unroll
+    for (int s = 0; s < 16; s++) x[s] = csub(mont_mul_lazy(x[s], x[s], q, qi), q2);
+    ntt_inv_regs<L>(x, lds, tid, itw, q);
+    const uint32_t t4 = fresh(tid);
+#pragma unroll
+    for (int s = 0; s < 16; s++) d0[natural_index<L>(t4, s)] = mul_shoup(x[s], P.ninvm, P.ninvm_p, q);
+    asm volatile("" ::: "memory");
+    // d1 = INTT(2 A0 A1): every thread rereads only the positions it parked
+    const uint32_t t5 = fresh(tid);
+#pragma unroll
+    for (int s = 0; s < 16; s++) {
+        const uint32_t idx = bitrev_layout_index<L>(t5, s);
+        const uint64_t m = mont_mul_lazy(d1[idx], d2[idx], q, qi);
+        x[s] = csub(csub(m + m, q2), q2);
+    }
+    ntt_inv_regs<L>(x, lds, tid, itw, q);
+    const uint32_t t6 = fresh(tid);
+#pragma unroll
+    for (int s = 0; s < 16; s++) d1[natural_index<L>(t6, s)] = mul_shoup(x[s], P.ninvm, P.ninvm_p, q);
+    asm volatile("" ::: "memory");
+    // d2 = INTT(A1^2)
+    const uint32_t t7 = fresh(tid);
+#pragma unroll
+    for (int s = 0; s < 16; s++) {
+        const uint64_t v = d2[bitrev_layout_index<L>(t7, s)];
+        x[s] = csub(mont_mul_lazy(v, v, q, qi), q2);
+    }
+    ntt_inv_regs<L>(x, lds, tid, itw, q);
+    const uint32_t t8 = fresh(tid);
+#pragma unroll
+    for (int s = 0; s < 16; s++) d2[natural_index<L>(t8, s)] = mul_shoup(x[s], P.ninvm, P.ninvm_p, q);
 }
 
-// Key-switching inner product: grid (2 components l, k limbs j, items).
-// rlk layout [digit i][comp l][limb j][n], transform domain, each entry
-// pre-multiplied by n^-1 2^64 so that the Montgomery products give
-// digit * key / n and the inverse transform needs no scaling.
-// out[item][l][j] += INTT(sum_i Dhat[item][i][j] * rlk[i][l][j]).
+// Key switching fused: grid (k limbs j, items).  For every digit i the row
+// [C2]_{q_i} is reduced mod q_j, transformed and multiply-accumulated with the
+// key rows into two register accumulators (lazy, below 2q); both accumulators
+// are then inverse transformed and added into C0, C1.  The transformed digits
+// never leave the chip.  rlk layout [digit i][comp l][limb j][n], transform
+// domain, each entry premultiplied by n^-1 2^64 so that the Montgomery products
+// give digit * key / n and the inverse transforms need no scaling.
 template <int L>
-__global__ __launch_bounds__(Geo<L>::T) void k_relin_ip(DevCtx c, const uint64_t *__restrict__ Dhat,
-                                                       const uint64_t *__restrict__ rlk,
-                                                       uint64_t *__restrict__ out) {
+__global__ __launch_bounds__(Geo<L>::T) void k_relin_fused(DevCtx c, const uint64_t *__restrict__ C2,
+                                                          const uint64_t *__restrict__ rlk,
+                                                          uint64_t *__restrict__ out) {
     __shared__ uint64_t lds[Geo<L>::lds_words];
     constexpr int n = Geo<L>::N;
-    const int tid = threadIdx.x;
-    const int l = blockIdx.x, j = blockIdx.y;
-    const size_t item = blockIdx.z;
+    const uint32_t tid = threadIdx.x;
+    const int j = blockIdx.x;
+    const size_t item = blockIdx.y;
     const int k = c.k;
     const PrimeConst &P = c.pc[j];
-    const uint64_t q = P.q, qi = P.qinv_neg, q2 = q << 1;
-    uint64_t acc[16];
+    const uint64_t q = P.q, qi = P.qinv_neg, q2 = q << 1, one_p = P.one_p;
+    const Tw *tw = c.tw + (size_t)j * n;
+    const uint64_t *c2 = C2 + item * (size_t)k * n;
+    uint64_t acc0[16], acc1[16];
 #pragma unroll
-    for (int s = 0; s < 16; s++) acc[s] = 0;
+    for (int s = 0; s < 16; s++) {
+        acc0[s] = 0;
+        acc1[s] = 0;
+    }
     for (int i = 0; i < k; i++) {
-        const uint64_t *d = Dhat + ((item * k + i) * k + j) * (size_t)n;
-        const uint64_t *r = rlk + (((size_t)i * 2 + l) * k + j) * n;
+        uint64_t x[16];
+        const uint64_t *src = c2 + (size_t)i * n;
+        const uint32_t t0 = fresh(tid);
 #pragma unroll
-        for (int s0 = 0; s0 < 16; s0 += 8) {
-            asm volatile("" ::: "memory");  // keeps at most 8 pairs of loads in flight
+        for (int s = 0; s < 16; s++)
+            x[s] = mul_shoup_lazy(src[natural_index<L>(t0, s)], 1, one_p, q);  // digit mod q_j, < 2q
+        ntt_fwd_regs<L>(x, lds, tid, tw, q);
+        const uint64_t *r0 = rlk + (((size_t)i * 2 + 0) * k + j) * n;
+        const uint64_t *r1 = rlk + (((size_t)i * 2 + 1) * k + j) * n;
+        const uint32_t t1 = fresh(tid);
 #pragma unroll
-            for (int s = s0; s < s0 + 8; s++) {
-                const int idx = bitrev_layout_index<L>(tid, s);
-                acc[s] = csub(acc[s] + mont_mul_lazy(d[idx], r[idx], q, qi), q2);  // [0, 2q)
+        for (int s0 = 0; s0 < 16; s0 += 2) {
+            asm volatile("" ::: "memory");  // key loads stay next to their use
+#pragma unroll
+            for (int s = s0; s < s0 + 2; s++) {
+                const uint32_t idx = bitrev_layout_index<L>(t1, s);
+                // x < 4q and key entries < q: products below q 2^64
+                acc0[s] = csub(acc0[s] + mont_mul_lazy(x[s], r0[idx], q, qi), q2);
+                acc1[s] = csub(acc1[s] + mont_mul_lazy(x[s], r1[idx], q, qi), q2);
             }
         }
     }
-    ntt_inv_regs<L>(acc, lds, tid, c.itw + (size_t)j * n, q);
-    asm volatile("" ::: "memory");  // the C_l loads below stay after the transform
-    uint64_t *o = out + ((item * 2 + l) * k + j) * (size_t)n;
+    uint64_t *o0 = out + (item * 2 * k + j) * (size_t)n;
+    uint64_t *o1 = out + ((item * 2 + 1) * k + j) * (size_t)n;
+    ntt_inv_regs<L>(acc0, lds, tid, c.itw + (size_t)j * n, q);
+    const uint32_t t2 = fresh(tid);
 #pragma unroll
     for (int s = 0; s < 16; s++) {
-        const int idx = natural_index<L>(tid, s);
-        o[idx] = add_mod(csub(acc[s], q), o[idx], q);
+        const uint32_t idx = natural_index<L>(t2, s);
+        o0[idx] = add_mod(csub(acc0[s], q), o0[idx], q);
+    }
+    ntt_inv_regs<L>(acc1, lds, tid, c.itw + (size_t)j * n, q);
+    const uint32_t t3 = fresh(tid);
+#pragma unroll
+    for (int s = 0; s < 16; s++) {
+        const uint32_t idx = natural_index<L>(t3, s);
+        o1[idx] = add_mod(csub(acc1[s], q), o1[idx], q);
     }
 }
 
@@ -231,16 +319,16 @@ struct NttL {
                                dim3(Geo<L>::T), 0, s, c, E, Dt);
         return hipGetLastError();
     }
-    static hipError_t relin_digits(const DevCtx &c, const uint64_t *C2, uint64_t *Dhat, size_t items,
-                                   hipStream_t s) {
-        hipLaunchKernelGGL(k_relin_digits<L>, dim3(c.k, c.k, (unsigned)items), dim3(Geo<L>::T), 0, s, c,
-                           C2, Dhat);
+    static hipError_t square_tensor(const DevCtx &c, const uint64_t *a, const uint64_t *E, uint64_t *Dt,
+                                    size_t items, hipStream_t s) {
+        hipLaunchKernelGGL(k_square_tensor<L>, dim3(c.K, (unsigned)items), dim3(Geo<L>::T), 0, s, c, a, E,
+                           Dt);
         return hipGetLastError();
     }
-    static hipError_t relin_ip(const DevCtx &c, const uint64_t *Dhat, const uint64_t *rlk, uint64_t *out,
-                               size_t items, hipStream_t s) {
-        hipLaunchKernelGGL(k_relin_ip<L>, dim3(2, c.k, (unsigned)items), dim3(Geo<L>::T), 0, s, c, Dhat,
-                           rlk, out);
+    static hipError_t relin_fused(const DevCtx &c, const uint64_t *C2, const uint64_t *rlk, uint64_t *out,
+                                  size_t items, hipStream_t s) {
+        hipLaunchKernelGGL(k_relin_fused<L>, dim3(c.k, (unsigned)items), dim3(Geo<L>::T), 0, s, c, C2, rlk,
+                           out);
         return hipGetLastError();
     }
 };
@@ -281,14 +369,14 @@ hipError_t launch_tensor_intt(const DevCtx &c, const uint64_t *E, uint64_t *Dt, 
     FHE_DISPATCH_L(c.L, tensor(c, E, Dt, square, items, s));
 }
 
-hipError_t launch_relin_digits(const DevCtx &c, const uint64_t *C2, uint64_t *Dhat, size_t items,
-                               hipStream_t s) {
+hipError_t launch_square_tensor(const DevCtx &c, const uint64_t *a, const uint64_t *E, uint64_t *Dt,
+                                size_t items, hipStream_t s) {
     if (items == 0) return hipSuccess;
-    FHE_DISPATCH_L(c.L, relin_digits(c, C2, Dhat, items, s));
+    FHE_DISPATCH_L(c.L, square_tensor(c, a, E, Dt, items, s));
 }
 
-hipError_t launch_relin_ip(const DevCtx &c, const uint64_t *Dhat, const uint64_t *rlk, uint64_t *out,
-                           size_t items, hipStream_t s) {
+hipError_t launch_relin_fused(const DevCtx &c, const uint64_t *C2, const uint64_t *rlk, uint64_t *out,
+                              size_t items, hipStream_t s) {
     if (items == 0) return hipSuccess;
-    FHE_DISPATCH_L(c.L, relin_ip(c, Dhat, rlk, out, items, s));
+    FHE_DISPATCH_L(c.L, relin_fused(c, C2, rlk, out, items, s));
 }

@@ -19,12 +19,22 @@
 
 typedef unsigned __int128 u128;
 
+// Full 64 x 64 -> 128-bit product from four 32 x 32 -> 64-bit multiply-adds
+// (each one v_mad_u64_u32 on the device; no partial sum overflows 64 bits).
+FHE_HD void mul128(uint64_t a, uint64_t b, uint64_t &lo, uint64_t &hi) {
+    const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32);
+    const uint32_t b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
+    const uint64_t p00 = (uint64_t)a0 * b0;
+    const uint64_t p01 = (uint64_t)a0 * b1 + (p00 >> 32);
+    const uint64_t p10 = (uint64_t)a1 * b0 + (uint32_t)p01;
+    hi = (uint64_t)a1 * b1 + (p01 >> 32) + (p10 >> 32);
+    lo = (uint32_t)p00 | (p10 << 32);
+}
+
 FHE_HD uint64_t mulhi64(uint64_t a, uint64_t b) {
-#if defined(__HIP_DEVICE_COMPILE__)
-    return __umul64hi(a, b);
-#else
-    return (uint64_t)(((u128)a * b) >> 64);
-#endif
+    uint64_t lo, hi;
+    mul128(a, b, lo, hi);
+    return hi;
 }
 
 // a * w mod q in [0, 2q), any a < 2^64; wp = floor(w * 2^64 / q), w < q.
@@ -48,7 +58,9 @@ FHE_HD uint64_t redc_lazy(uint64_t hi, uint64_t lo, uint64_t q, uint64_t qinv_ne
 
 // a b 2^-64 mod q in [0, 2q) for a b < q 2^64 (e.g. a < 4q, b < q, q < 2^62).
 FHE_HD uint64_t mont_mul_lazy(uint64_t a, uint64_t b, uint64_t q, uint64_t qinv_neg) {
-    return redc_lazy(mulhi64(a, b), a * b, q, qinv_neg);
+    uint64_t lo, hi;
+    mul128(a, b, lo, hi);
+    return redc_lazy(hi, lo, q, qinv_neg);
 }
 
 FHE_HD uint64_t add_mod(uint64_t a, uint64_t b, uint64_t q) {  // a, b < q
@@ -68,10 +80,10 @@ struct Acc128 {
 FHE_HD void acc_init(Acc128 &a) { a.lo = 0; a.hi = 0; }
 
 FHE_HD void acc_mac(Acc128 &a, uint64_t x, uint64_t y) {
-    u128 p = (u128)x * y;
-    u128 s = ((u128)a.hi << 64 | a.lo) + p;
-    a.lo = (uint64_t)s;
-    a.hi = (uint64_t)(s >> 64);
+    uint64_t lo, hi;
+    mul128(x, y, lo, hi);
+    a.lo += lo;
+    a.hi += hi + (a.lo < lo ? 1u : 0u);
 }
 
 // (acc) 2^-64 mod q in [0, q) for any 128-bit acc: the high word is first

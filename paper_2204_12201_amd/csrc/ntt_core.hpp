@@ -14,7 +14,9 @@
 // position idx + idx/16 (the padding keeps 16 consecutive lanes on distinct
 // bank pairs for every pass's access pattern).  Pass 0 reads the natural
 // order with lanes on consecutive addresses; the last pass leaves each lane
-// with runs of R consecutive positions of the bit-reversed output.
+// with runs of R consecutive positions of the bit-reversed output.  Only the
+// exchange next to pass 0 crosses waves (fixed_bits below): the others are
+// wave-local, so waves run the later passes without workgroup barriers.
 //
 // Butterflies are Harvey's lazy ones: forward values live in [0, 4q),
 // inverse values in [0, 2q); twiddles are (w, floor(w 2^64 / q)) pairs.
@@ -39,14 +41,38 @@ struct Geo {
     static constexpr int LO(int p) { return L - LE * p - R(p); }
 };
 
-__device__ __forceinline__ int lds_pos(int idx) { return idx + (idx >> 4); }
+__device__ __forceinline__ uint32_t lds_pos(uint32_t idx) { return idx + (idx >> 4); }
+
+// Opaque copy of a value: index math derived from it is recomputed where it is
+// used instead of being kept live (as 16 addresses per row) across stages.
+__device__ __forceinline__ uint32_t fresh(uint32_t v) {
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
+// The (L - r) index bits a thread keeps fixed in pass P, from (tid, group g).
+// With whole waves (T >= 64) the wave id goes to the top, the group next and
+// the lane at the bottom, so that from pass 1 on every wave owns one closed
+// block of 64 * E consecutive indices: the exchanges between passes >= 1 never
+// leave the wave and need no workgroup barrier.
+template <int L, int LE, int P>
+__device__ __forceinline__ uint32_t fixed_bits(uint32_t tid, uint32_t g) {
+    constexpr int r = Geo<L, LE>::R(P), LT = Geo<L, LE>::LT;
+    constexpr int lgG = LE - r;
+    if constexpr (LT >= 6 && lgG > 0)
+        return ((tid >> 6) << (6 + lgG)) | (g << 6) | (tid & 63u);
+    else
+        return (g << LT) | tid;
+}
 
 // Global index of element e of group g of thread tid in pass P.
+// (Unsigned so that row + index addressing can use a scalar base with a
+// 32-bit vector offset.)
 template <int L, int LE, int P>
-__device__ __forceinline__ int elem_index(int tid, int g, int e) {
-    constexpr int r = Geo<L, LE>::R(P), lo = Geo<L, LE>::LO(P), LT = Geo<L, LE>::LT;
-    int F = (g << LT) | tid;
-    return ((F >> lo) << (lo + r)) | (e << lo) | (F & ((1 << lo) - 1));
+__device__ __forceinline__ uint32_t elem_index(uint32_t tid, uint32_t g, uint32_t e) {
+    constexpr int r = Geo<L, LE>::R(P), lo = Geo<L, LE>::LO(P);
+    const uint32_t F = fixed_bits<L, LE, P>(tid, g);
+    return ((F >> lo) << (lo + r)) | (e << lo) | (F & ((1u << lo) - 1u));
 }
 
 __device__ __forceinline__ void ct_bfly(uint64_t &X, uint64_t &Y, uint64_t w, uint64_t wp,
@@ -72,8 +98,8 @@ __device__ __forceinline__ void fwd_pass(uint64_t (&x)[1 << LE], int tid, const 
     const uint64_t q2 = q << 1;
 #pragma unroll
     for (int g = 0; g < G; g++) {
-        int F = (g << LT) | tid;
-        int H = F >> lo;
+        const uint32_t F = fixed_bits<L, LE, P>((uint32_t)tid, (uint32_t)g);
+        uint32_t H = F >> lo;
         if constexpr (lo >= 6 || LT <= lo) H = __builtin_amdgcn_readfirstlane(H);
 #pragma unroll
         for (int u = 0; u < r; u++) {
@@ -99,8 +125,8 @@ __device__ __forceinline__ void inv_pass(uint64_t (&x)[1 << LE], int tid, const 
     const uint64_t q2 = q << 1;
 #pragma unroll
     for (int g = 0; g < G; g++) {
-        int F = (g << LT) | tid;
-        int H = F >> lo;
+        const uint32_t F = fixed_bits<L, LE, P>((uint32_t)tid, (uint32_t)g);
+        uint32_t H = F >> lo;
         if constexpr (lo >= 6 || LT <= lo) H = __builtin_amdgcn_readfirstlane(H);
 #pragma unroll
         for (int u = r - 1; u >= 0; u--) {
@@ -136,15 +162,36 @@ __device__ __forceinline__ void lds_load(const uint64_t *lds, uint64_t (&x)[1 <<
         for (int e = 0; e < R; e++) x[g * R + e] = lds[lds_pos(elem_index<L, LE, P>(tid, g, e))];
 }
 
+// Re-layout of a row from pass A to pass B through LDS.  When pass 0 is one
+// of the two and the row spans several waves, every wave exchanges with every
+// other: workgroup barriers before (the buffer may still be read by the
+// previous exchange) and between the store and the load.  Otherwise the
+// exchange stays inside the wave, whose LDS operations execute in order, so
+// only the compiler is kept from reordering them.
+template <int L, int LE, int A, int B>
+__device__ __forceinline__ void exchange(uint64_t *lds, uint64_t (&x)[1 << LE], int tid) {
+    constexpr bool block = (A == 0 || B == 0) && Geo<L, LE>::T > 64;
+    if constexpr (block) {
+        __syncthreads();
+        lds_store<L, LE, A>(lds, x, tid);
+        __syncthreads();
+        lds_load<L, LE, B>(lds, x, tid);
+    } else {
+        __builtin_amdgcn_wave_barrier();
+        asm volatile("" ::: "memory");
+        lds_store<L, LE, A>(lds, x, tid);
+        __builtin_amdgcn_wave_barrier();
+        asm volatile("" ::: "memory");
+        lds_load<L, LE, B>(lds, x, tid);
+    }
+}
+
 template <int L, int LE, int P>
 __device__ __forceinline__ void fwd_from(uint64_t (&x)[1 << LE], uint64_t *lds, int tid,
                                          const Tw *__restrict__ tw, uint64_t q) {
     fwd_pass<L, LE, P>(x, tid, tw, q);
     if constexpr (P + 1 < Geo<L, LE>::NPASS) {
-        __syncthreads();
-        lds_store<L, LE, P>(lds, x, tid);
-        __syncthreads();
-        lds_load<L, LE, P + 1>(lds, x, tid);
+        exchange<L, LE, P, P + 1>(lds, x, tid);
         fwd_from<L, LE, P + 1>(x, lds, tid, tw, q);
     }
 }
@@ -154,10 +201,7 @@ __device__ __forceinline__ void inv_from(uint64_t (&x)[1 << LE], uint64_t *lds, 
                                          const Tw *__restrict__ tw, uint64_t q) {
     inv_pass<L, LE, P>(x, tid, tw, q);
     if constexpr (P > 0) {
-        __syncthreads();
-        lds_store<L, LE, P>(lds, x, tid);
-        __syncthreads();
-        lds_load<L, LE, P - 1>(lds, x, tid);
+        exchange<L, LE, P, P - 1>(lds, x, tid);
         inv_from<L, LE, P - 1>(x, lds, tid, tw, q);
     }
 }
@@ -167,7 +211,7 @@ __device__ __forceinline__ void inv_from(uint64_t (&x)[1 << LE], uint64_t *lds, 
 template <int L, int LE = 4>
 __device__ __forceinline__ void ntt_fwd_regs(uint64_t (&x)[1 << LE], uint64_t *lds, int tid,
                                              const Tw *__restrict__ tw, uint64_t q) {
-    fwd_from<L, LE, 0>(x, lds, tid, tw, q);
+    fwd_from<L, LE, 0>(x, lds, (int)fresh(tid), tw, q);
 }
 
 // Inverse transform (without the 1/n factor) of a row held in last-pass
@@ -175,17 +219,17 @@ __device__ __forceinline__ void ntt_fwd_regs(uint64_t (&x)[1 << LE], uint64_t *l
 template <int L, int LE = 4>
 __device__ __forceinline__ void ntt_inv_regs(uint64_t (&x)[1 << LE], uint64_t *lds, int tid,
                                              const Tw *__restrict__ tw, uint64_t q) {
-    inv_from<L, LE, Geo<L, LE>::NPASS - 1>(x, lds, tid, tw, q);
+    inv_from<L, LE, Geo<L, LE>::NPASS - 1>(x, lds, (int)fresh(tid), tw, q);
 }
 
 // Global index helpers for the two register layouts.
 template <int L, int LE = 4>
-__device__ __forceinline__ int natural_index(int tid, int s) {  // pass-0 layout, slot s
+__device__ __forceinline__ uint32_t natural_index(uint32_t tid, int s) {  // pass-0 layout, slot s
     return elem_index<L, LE, 0>(tid, 0, s);
 }
 
 template <int L, int LE = 4>
-__device__ __forceinline__ int bitrev_layout_index(int tid, int s) {  // last-pass layout
+__device__ __forceinline__ uint32_t bitrev_layout_index(uint32_t tid, int s) {  // last-pass layout
     constexpr int P = Geo<L, LE>::NPASS - 1;
     constexpr int R = 1 << Geo<L, LE>::R(P);
     return elem_index<L, LE, P>(tid, s / R, s % R);

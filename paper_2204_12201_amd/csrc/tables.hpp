@@ -37,30 +37,39 @@ struct MrcConst {
     uint64_t M_mod_t[FHE_MAXB + 1];              // [M]_{target_j}
 };
 
+// Constants of the fast base conversions.  Each output residue is one
+// Montgomery reduction of a 128-bit sum of products sum_t a_t b_t, where the b_t
+// are stored premultiplied by 2^64 mod the target prime; additive constants
+// (overflow corrections, offsets) enter the same sum as extra terms.  Tables
+// are target-major so one output's constants are contiguous.
 struct ConvConst {
     uint32_t k, kp;
     uint64_t t;
+    // basis primes and their reduction helpers
+    uint64_t q[FHE_MAXK], q_qinv[FHE_MAXK], q_one[FHE_MAXK];     // Q: prime, -q^-1 mod 2^64, floor(2^64/q)
+    uint64_t p[FHE_MAXKP], p_qinv[FHE_MAXKP], p_one[FHE_MAXKP];  // P: likewise
     // ---- Q -> P, centred (lift of the inputs) ----
-    uint64_t qhinv[FHE_MAXK], qhinv_p[FHE_MAXK];        // [qhat_i^-1]_{q_i}
-    double inv_q[FHE_MAXK];                              // 1 / q_i
-    uint64_t qhat_pm[FHE_MAXK][FHE_MAXKP];               // [qhat_i]_{p_j} 2^64 (Montgomery form)
-    uint64_t beta_q_p[FHE_MAXK + 1][FHE_MAXKP];          // [beta q]_{p_j}, beta = 0..k
-    // ---- scale: floor((t D + h) / q) modulo P, h = (q-1)/2 ----
-    uint64_t tqhinv[FHE_MAXK], tqhinv_p[FHE_MAXK];      // [t qhat_i^-1]_{q_i}
-    uint64_t hqhinv[FHE_MAXK];                           // [h qhat_i^-1]_{q_i}
-    uint64_t nqinv_pm[FHE_MAXK][FHE_MAXKP];              // [-q_i^-1]_{p_j} 2^64
-    uint64_t tqinv_p[FHE_MAXKP], tqinv_ps[FHE_MAXKP];    // [t q^-1]_{p_j}
-    uint64_t hqinv_p[FHE_MAXKP];                         // [h q^-1]_{p_j}
+    uint64_t qhinv[FHE_MAXK], qhinv_p[FHE_MAXK];  // [qhat_i^-1]_{q_i} (Shoup pair)
+    double inv_q[FHE_MAXK];                        // 1 / q_i
+    // lift_m[j][i] = [qhat_i]_{p_j} 2^64 (i < k); lift_m[j][k] = [-q]_{p_j} 2^64 (times beta)
+    uint64_t lift_m[FHE_MAXKP][FHE_MAXK + 1];
+    // ---- scale: C = floor((t D + h) / q) modulo P, h = (q-1)/2 ----
+    uint64_t tqhinv[FHE_MAXK], tqhinv_p[FHE_MAXK];  // [t qhat_i^-1]_{q_i}
+    uint64_t hqhinv[FHE_MAXK];                       // [h qhat_i^-1]_{q_i}
+    // scale_m[j][i] = [-q_i^-1]_{p_j} 2^64 (i < k), then [t q^-1]_{p_j} 2^64 (times D_{p_j}),
+    // [1]_{p_j} 2^64 (times v), [h q^-1]_{p_j} 2^64 (times 1)
+    uint64_t scale_m[FHE_MAXKP][FHE_MAXK + 3];
+    // ---- P -> Q, centred ----
+    uint64_t phinv[FHE_MAXKP], phinv_p[FHE_MAXKP];  // [phat_j^-1]_{p_j}
+    double inv_p[FHE_MAXKP];
+    // p2q_m[i][j] = [phat_j]_{q_i} 2^64 (j < k'); p2q_m[i][k'] = [-P]_{q_i} 2^64 (times beta)
+    uint64_t p2q_m[FHE_MAXK][FHE_MAXKP + 1];
+    // ---- exact path of the scale ----
     uint64_t h_q[FHE_MAXK];                              // [h]_{q_i}
     uint64_t h_p[FHE_MAXKP];                             // [h]_{p_j}
     uint64_t t_q[FHE_MAXK], t_qs[FHE_MAXK];              // [t]_{q_i}
     uint64_t t_p[FHE_MAXKP], t_ps[FHE_MAXKP];            // [t]_{p_j}
     uint64_t qinv_p[FHE_MAXKP], qinv_ps[FHE_MAXKP];      // [q^-1]_{p_j}
-    // ---- P -> Q, centred ----
-    uint64_t phinv[FHE_MAXKP], phinv_p[FHE_MAXKP];      // [phat_j^-1]_{p_j}
-    double inv_p[FHE_MAXKP];
-    uint64_t phat_qm[FHE_MAXKP][FHE_MAXK];               // [phat_j]_{q_i} 2^64
-    uint64_t beta_p_q[FHE_MAXKP + 1][FHE_MAXK];          // [beta P]_{q_i}, beta = 0..k'
     // ---- decryption: m = (h - [Y]_q) q^-1 mod t ----
     uint64_t h_t, qinv_t, qinv_ts, t_one_p;
     // ---- plaintext constant: Delta = floor(q / t) ----
