@@ -83,7 +83,7 @@ typedef struct {
     uint32_t n;        /* ring degree, power of two in [16, 16384] */
     uint32_t k;        /* number of RNS primes of q, 1..16 */
     uint64_t t;        /* plaintext modulus, 2 <= t < 2^62, gcd(t, q) = 1 */
-    const uint64_t *q; /* host array of k distinct primes, q_i = 1 mod 2n, q_i < 2^62 */
+    const uint64_t *q; /* host array of k distinct primes, q_i = 1 mod 2n, q_i < 2^61 */
     uint32_t encoding; /* FHE_ENC_SLOTS (needs t prime, t = 1 mod 2n) or FHE_ENC_COEFF */
 } fhe_params;
 

@@ -401,7 +401,7 @@ fhe_status fhe_ctx_create(const fhe_params *p, int hip_device, fhe_ctx **out) {
     double log2q = 0;
     for (uint32_t i = 0; i < k; i++) {
         const uint64_t qi = qs[i];
-        if (qi < 3 || qi >= (1ull << 62) || qi % (2ull * n) != 1 || !is_prime_u64(qi)) return FHE_EPARAM;
+        if (qi < 3 || qi >= (1ull << 61) || qi % (2ull * n) != 1 || !is_prime_u64(qi)) return FHE_EPARAM;
         for (uint32_t j = 0; j < i; j++)
             if (qs[j] == qi) return FHE_EPARAM;
         if (hgcd(p->t, qi) != 1) return FHE_EPARAM;
@@ -599,6 +599,9 @@ fhe_status fhe_ctx_create(const fhe_params *p, int hip_device, fhe_ctx **out) {
     d.mrc_q = (const MrcConst *)c->d_mrc_q;
     d.mrc_p = (const MrcConst *)c->d_mrc_p;
     d.fallback = (unsigned long long *)c->d_counters;
+    d.lazy_q = 1;
+    for (uint32_t i = 0; i < k; i++)
+        if (c->primes[i] >= UINT64_MAX / (4ull * (c->L + 1))) d.lazy_q = 0;
     // default chunk: about 8 GiB of product workspace
     size_t per = item_words_mul(c, false) * 8;
     c->default_limit = ((size_t)8 << 30) / per;

@@ -19,6 +19,7 @@ struct DevCtx {
     const MrcConst *mrc_q;  // basis Q -> targets P (and t in the last slot)
     const MrcConst *mrc_p;  // basis P -> targets Q
     unsigned long long *fallback;  // count of coefficients that took the exact path
+    int lazy_q;             // every Q prime below 2^64 / (4 (L + 1)): lazy digit transforms
 };
 
 // Kernel kinds (timing and profiling names).

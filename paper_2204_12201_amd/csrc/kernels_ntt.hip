@@ -14,8 +14,8 @@
 
 namespace {
 
-__device__ __forceinline__ uint64_t canon4(uint64_t x, uint64_t q) {  // [0, 4q) -> [0, q)
-    return csub(csub(x, q << 1), q);
+__device__ __forceinline__ uint64_t canon8(uint64_t x, uint64_t q) {  // [0, 8q) -> [0, q)
+    return csub(csub(csub(x, q << 2), q << 1), q);
 }
 
 template <int L>
@@ -50,7 +50,7 @@ __global__ __launch_bounds__(Geo<L>::T) void k_ntt_rows(DevCtx c, uint64_t *__re
         ntt_fwd_regs<L>(x, lds, tid, c.tw + (size_t)limb * n, q);
 #pragma unroll
         for (int s = 0; s < 16; s++) {
-            uint64_t v = canon4(x[s], q);
+            uint64_t v = canon8(x[s], q);
             if (mode == NTT_FWD_NINVM) v = mul_shoup(v, P.ninvm, P.ninvm_p, q);
             ptr[bitrev_layout_index<L>(tid, s)] = v;
         }
@@ -89,7 +89,7 @@ __global__ __launch_bounds__(Geo<L>::T) void k_fwd_ext(DevCtx c, const uint64_t 
     load_natural<L>(x, src, tid);
     ntt_fwd_regs<L>(x, lds, tid, c.tw + (size_t)limb * n, q);
 #pragma unroll
-    for (int s = 0; s < 16; s++) dst[bitrev_layout_index<L>(tid, s)] = canon4(x[s], q);
+    for (int s = 0; s < 16; s++) dst[bitrev_layout_index<L>(tid, s)] = canon8(x[s], q);
 }
 
 // grid (K, 3, items): component comp of the tensor of item, limb `limb`.
@@ -143,10 +143,10 @@ __global__ __launch_bounds__(Geo<L>::T) void k_tensor_intt(DevCtx c, const uint6
 // Squaring, transform phase fused: grid (K limbs, items).  For limb l of item
 // it transforms a0 and a1 (Q limbs straight from the ciphertext, P limbs from
 // the lift in E), then forms d0 = a0^2, d1 = 2 a0 a1, d2 = a1^2 (Montgomery
-// products) and inverse transforms each into Dt[item][comp][l].  One row is
-// held in registers at a time: the transformed inputs are parked in the
-// item's own d1 and d2 output rows, which this workgroup alone touches and
-// rereads from L2 before overwriting.
+// products) and inverse transforms each into Dt[item][comp][l].  Two rows
+// live in registers: a0 is loaded while a1 is transformed; d1 (transform
+// domain) is parked in its own output row, which this workgroup alone touches,
+// and read back while d2 is inverse transformed.
 template <int L>
 __global__ __launch_bounds__(Geo<L>::T) void k_square_tensor(DevCtx c, const uint64_t *__restrict__ a,
                                                             const uint64_t *__restrict__ E,
@@ -158,7 +158,7 @@ __global__ __launch_bounds__(Geo<L>::T) void k_square_tensor(DevCtx c, const uin
     const size_t item = blockIdx.y;
     const int k = c.k, K = c.K;
     const PrimeConst &P = c.pc[limb];
-    const uint64_t q = P.q, qi = P.qinv_neg, q2 = q << 1;
+    const uint64_t q = P.q, qi = P.qinv_neg, q2 = q << 1, q4 = q << 2;
     const Tw *tw = c.tw + (size_t)limb * n;
     const Tw *itw = c.itw + (size_t)limb * n;
     const uint64_t *src0, *src1;
@@ -172,59 +172,45 @@ __global__ __launch_bounds__(Geo<L>::T) void k_square_tensor(DevCtx c, const uin
     uint64_t *d0 = Dt + ((item * 3 + 0) * K + limb) * (size_t)n;
     uint64_t *d1 = Dt + ((item * 3 + 1) * K + limb) * (size_t)n;
     uint64_t *d2 = Dt + ((item * 3 + 2) * K + limb) * (size_t)n;
-    uint64_t x[16];
-    // A1 = NTT(a1), parked in d2
+    uint64_t x[16], y[16];
     const uint32_t t1 = fresh(tid);
 #pragma unroll
     for (int s = 0; s < 16; s++) x[s] = src1[natural_index<L>(t1, s)];
-    ntt_fwd_regs<L>(x, lds, tid, tw, q);
 #pragma unroll
-    for (int s = 0; s < 16; s++) d2[bitrev_layout_index<L>(fresh(tid), s)] = canon4(x[s], q);
+    for (int s = 0; s < 16; s++) y[s] = src0[natural_index<L>(t1, s)];
     asm volatile("" ::: "memory");
-    // A0 = NTT(a0), parked in d1
+    ntt_fwd_regs<L>(x, lds, tid, tw, q);  // A1
+#pragma unroll
+    for (int s = 0; s < 16; s++) x[s] = csub(csub(x[s], q4), q2);  // [0, 2q)
+    ntt_fwd_regs<L>(y, lds, tid, tw, q);  // A0
+    // d1 = 2 A0 A1 parked in d1; d0 = A0^2 in y, d2 = A1^2 in x (all below 4q)
     const uint32_t t2 = fresh(tid);
 #pragma unroll
-    for (int s = 0; s < 16; s++) x[s] = src0[natural_index<L>(t2, s)];
-    ntt_fwd_regs<L>(x, lds, tid, tw, q);
+    for (int s = 0; s < 16; s++) {
+        const uint64_t a0 = csub(csub(y[s], q4), q2);
+        const uint64_t m = mont_mul_lazy(a0, x[s], q, qi);
+        d1[bitrev_layout_index<L>(t2, s)] = m + m;
+        y[s] = mont_mul_lazy(a0, a0, q, qi);
+        x[s] = mont_mul_lazy(x[s], x[s], q, qi);
+    }
+    asm volatile("" ::: "memory");
+    ntt_inv_regs<L>(y, lds, tid, itw, q);
     const uint32_t t3 = fresh(tid);
 #pragma unroll
-    for (int s = 0; s < 16; s++) {
-        x[s] = canon4(x[s], q);
-        d1[bitrev_layout_index<L>(t3, s)] = x[s];
-    }
-    asm volatile("" ::: "memory");
-    // d0 = INTT(A0^2)
-#pragma unroll
-    for (int s = 0; s < 16; s++) x[s] = csub(mont_mul_lazy(x[s], x[s], q, qi), q2);
-    ntt_inv_regs<L>(x, lds, tid, itw, q);
+    for (int s = 0; s < 16; s++) d0[natural_index<L>(t3, s)] = mul_shoup(y[s], P.ninvm, P.ninvm_p, q);
+    // every thread rereads only the positions it parked
     const uint32_t t4 = fresh(tid);
 #pragma unroll
-    for (int s = 0; s < 16; s++) d0[natural_index<L>(t4, s)] = mul_shoup(x[s], P.ninvm, P.ninvm_p, q);
+    for (int s = 0; s < 16; s++) y[s] = d1[bitrev_layout_index<L>(t4, s)];
     asm volatile("" ::: "memory");
-    // d1 = INTT(2 A0 A1): every thread rereads only the positions it parked
+    ntt_inv_regs<L>(x, lds, tid, itw, q);
     const uint32_t t5 = fresh(tid);
 #pragma unroll
-    for (int s = 0; s < 16; s++) {
-        const uint32_t idx = bitrev_layout_index<L>(t5, s);
-        const uint64_t m = mont_mul_lazy(d1[idx], d2[idx], q, qi);
-        x[s] = csub(csub(m + m, q2), q2);
-    }
-    ntt_inv_regs<L>(x, lds, tid, itw, q);
+    for (int s = 0; s < 16; s++) d2[natural_index<L>(t5, s)] = mul_shoup(x[s], P.ninvm, P.ninvm_p, q);
+    ntt_inv_regs<L>(y, lds, tid, itw, q);
     const uint32_t t6 = fresh(tid);
 #pragma unroll
-    for (int s = 0; s < 16; s++) d1[natural_index<L>(t6, s)] = mul_shoup(x[s], P.ninvm, P.ninvm_p, q);
-    asm volatile("" ::: "memory");
-    // d2 = INTT(A1^2)
-    const uint32_t t7 = fresh(tid);
-#pragma unroll
-    for (int s = 0; s < 16; s++) {
-        const uint64_t v = d2[bitrev_layout_index<L>(t7, s)];
-        x[s] = csub(mont_mul_lazy(v, v, q, qi), q2);
-    }
-    ntt_inv_regs<L>(x, lds, tid, itw, q);
-    const uint32_t t8 = fresh(tid);
-#pragma unroll
-    for (int s = 0; s < 16; s++) d2[natural_index<L>(t8, s)] = mul_shoup(x[s], P.ninvm, P.ninvm_p, q);
+    for (int s = 0; s < 16; s++) d1[natural_index<L>(t6, s)] = mul_shoup(y[s], P.ninvm, P.ninvm_p, q);
 }
 
 // Key switching fused: grid (k limbs j, items).  For every digit i the row
@@ -234,12 +220,18 @@ __global__ __launch_bounds__(Geo<L>::T) void k_square_tensor(DevCtx c, const uin
 // never leave the chip.  rlk layout [digit i][comp l][limb j][n], transform
 // domain, each entry premultiplied by n^-1 2^64 so that the Montgomery products
 // give digit * key / n and the inverse transforms need no scaling.
-template <int L>
+// While digit i finishes its transform and inner product, each wave copies its
+// share of digit i + 1 into its own LDS block (prefetch_row_lds).  LAZY: every
+// q_j is below 2^64 / (4 (L + 1)), so the digit transforms skip the
+// conditional subtractions (digits below 4 (L + 1) q_j, still a valid
+// Montgomery operand against key entries below q_j).
+template <int L, bool LAZY>
 __global__ __launch_bounds__(Geo<L>::T) void k_relin_fused(DevCtx c, const uint64_t *__restrict__ C2,
                                                           const uint64_t *__restrict__ rlk,
                                                           uint64_t *__restrict__ out) {
     __shared__ uint64_t lds[Geo<L>::lds_words];
     constexpr int n = Geo<L>::N;
+    constexpr bool PREFETCH = Geo<L>::T >= 64;
     const uint32_t tid = threadIdx.x;
     const int j = blockIdx.x;
     const size_t item = blockIdx.y;
@@ -256,25 +248,55 @@ __global__ __launch_bounds__(Geo<L>::T) void k_relin_fused(DevCtx c, const uint6
     }
     for (int i = 0; i < k; i++) {
         uint64_t x[16];
-        const uint64_t *src = c2 + (size_t)i * n;
         const uint32_t t0 = fresh(tid);
+        if (PREFETCH && i > 0) {
+            prefetch_wait();
 #pragma unroll
-        for (int s = 0; s < 16; s++)
-            x[s] = mul_shoup_lazy(src[natural_index<L>(t0, s)], 1, one_p, q);  // digit mod q_j, < 2q
-        ntt_fwd_regs<L>(x, lds, tid, tw, q);
+            for (int s = 0; s < 16; s++)  // digit mod q_j, < 4q
+                x[s] = mul_shoup_lazy4(prefetched(lds, t0, s), 1, one_p, q);
+        } else {
+            const uint64_t *src = c2 + (size_t)i * n;
+#pragma unroll
+            for (int s = 0; s < 16; s++) x[s] = mul_shoup_lazy4(src[natural_index<L>(t0, s)], 1, one_p, q);
+        }
+        auto hook = [&]() {
+            if constexpr (PREFETCH)
+                if (i + 1 < k) prefetch_row_lds<L>(lds, c2 + (size_t)(i + 1) * n, fresh(tid));
+        };
+        ntt_fwd_regs<L, 4, !LAZY>(x, lds, tid, tw, q, hook);
+        // inner product with the key rows, the loads of slot pair s0 + 2 in
+        // flight while pair s0 is multiplied
         const uint64_t *r0 = rlk + (((size_t)i * 2 + 0) * k + j) * n;
         const uint64_t *r1 = rlk + (((size_t)i * 2 + 1) * k + j) * n;
         const uint32_t t1 = fresh(tid);
+        uint64_t ka[4], kb[4];
+#pragma unroll
+        for (int u = 0; u < 2; u++) {
+            const uint32_t idx = bitrev_layout_index<L>(t1, u);
+            ka[u] = r0[idx];
+            kb[u] = r1[idx];
+        }
 #pragma unroll
         for (int s0 = 0; s0 < 16; s0 += 2) {
-            asm volatile("" ::: "memory");  // key loads stay next to their use
+            if (s0 + 2 < 16) {
 #pragma unroll
-            for (int s = s0; s < s0 + 2; s++) {
-                const uint32_t idx = bitrev_layout_index<L>(t1, s);
-                // x < 4q and key entries < q: products below q 2^64
-                acc0[s] = csub(acc0[s] + mont_mul_lazy(x[s], r0[idx], q, qi), q2);
-                acc1[s] = csub(acc1[s] + mont_mul_lazy(x[s], r1[idx], q, qi), q2);
+                for (int u = 0; u < 2; u++) {
+                    const uint32_t idx = bitrev_layout_index<L>(t1, s0 + 2 + u);
+                    ka[2 + u] = r0[idx];
+                    kb[2 + u] = r1[idx];
+                }
             }
+            asm volatile("" ::: "memory");
+#pragma unroll
+            for (int u = 0; u < 2; u++) {
+                // digit < 4 (L + 1) q and key entries < q: products below q 2^64
+                acc0[s0 + u] = csub(acc0[s0 + u] + mont_mul_lazy(x[s0 + u], ka[u], q, qi), q2);
+                acc1[s0 + u] = csub(acc1[s0 + u] + mont_mul_lazy(x[s0 + u], kb[u], q, qi), q2);
+            }
+            ka[0] = ka[2];
+            ka[1] = ka[3];
+            kb[0] = kb[2];
+            kb[1] = kb[3];
         }
     }
     uint64_t *o0 = out + (item * 2 * k + j) * (size_t)n;
@@ -284,14 +306,14 @@ __global__ __launch_bounds__(Geo<L>::T) void k_relin_fused(DevCtx c, const uint6
 #pragma unroll
     for (int s = 0; s < 16; s++) {
         const uint32_t idx = natural_index<L>(t2, s);
-        o0[idx] = add_mod(csub(acc0[s], q), o0[idx], q);
+        o0[idx] = add_mod(csub(csub(acc0[s], q2), q), o0[idx], q);
     }
     ntt_inv_regs<L>(acc1, lds, tid, c.itw + (size_t)j * n, q);
     const uint32_t t3 = fresh(tid);
 #pragma unroll
     for (int s = 0; s < 16; s++) {
         const uint32_t idx = natural_index<L>(t3, s);
-        o1[idx] = add_mod(csub(acc1[s], q), o1[idx], q);
+        o1[idx] = add_mod(csub(csub(acc1[s], q2), q), o1[idx], q);
     }
 }
 
@@ -327,8 +349,12 @@ struct NttL {
     }
     static hipError_t relin_fused(const DevCtx &c, const uint64_t *C2, const uint64_t *rlk, uint64_t *out,
                                   size_t items, hipStream_t s) {
-        hipLaunchKernelGGL(k_relin_fused<L>, dim3(c.k, (unsigned)items), dim3(Geo<L>::T), 0, s, c, C2, rlk,
-                           out);
+        if (c.lazy_q)
+            hipLaunchKernelGGL((k_relin_fused<L, true>), dim3(c.k, (unsigned)items), dim3(Geo<L>::T), 0, s, c,
+                               C2, rlk, out);
+        else
+            hipLaunchKernelGGL((k_relin_fused<L, false>), dim3(c.k, (unsigned)items), dim3(Geo<L>::T), 0, s,
+                               c, C2, rlk, out);
         return hipGetLastError();
     }
 };

@@ -1,9 +1,11 @@
 // Modular arithmetic on 64-bit residues for gfx950 (and the host, for tables).
 //
-// All primes are below 2^62, so lazy values up to 4q fit a 64-bit word.
+// All primes are below 2^61, so lazy values up to 8q fit a 64-bit word.
 //  * Shoup multiplication by a constant w (Harvey, "Faster arithmetic for
 //    number-theoretic transforms", 2014): with w' = floor(w 2^64 / q),
-//    a w - floor(a w' / 2^64) q lies in [0, 2q) for every a < 2^64.
+//    a w - floor(a w' / 2^64) q lies in [0, 2q) for every a < 2^64.  The
+//    transforms use a cheaper quotient estimate that is low by at most 2,
+//    leaving the remainder in [0, 4q) (mul_shoup_lazy4).
 //  * Montgomery multiplication (R = 2^64): REDC(T) = T 2^-64 mod q in [0, 2q)
 //    for T < q 2^64, with qinv_neg = -q^-1 mod 2^64.
 // The 64 x 64 -> 128-bit products lower to v_mad_u64_u32 / v_mul_hi_u32
@@ -41,6 +43,24 @@ FHE_HD uint64_t mulhi64(uint64_t a, uint64_t b) {
 FHE_HD uint64_t mul_shoup_lazy(uint64_t a, uint64_t w, uint64_t wp, uint64_t q) {
     uint64_t qh = mulhi64(a, wp);
     return a * w - qh * q;
+}
+
+// 32 x 32 -> upper 32 bits of the product (v_mul_hi_u32 on the device).
+FHE_HD uint32_t mulhi32(uint32_t a, uint32_t b) { return (uint32_t)(((uint64_t)a * b) >> 32); }
+
+// a * w mod q in [0, 4q) for any a < 2^64, w < q, wp = floor(w 2^64 / q).
+// floor(a wp / 2^64) = a1 wp1 + floor((a1 wp0 + a0 wp1 + floor(a0 wp0 / 2^32)) / 2^32)
+// (32-bit halves); keeping a1 wp1 and the upper halves of the two cross
+// products drops three terms below 2^32 each, so the estimate h is low by at
+// most 2 and a w - h q (exact modulo 2^64, as it is below 2^64) by at most 2q
+// above the [0, 2q) of the exact quotient.  Three 32-bit multiplies for the
+// estimate instead of four, and no carry propagation.
+FHE_HD uint64_t mul_shoup_lazy4(uint64_t a, uint64_t w, uint64_t wp, uint64_t q) {
+    const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32);
+    const uint32_t p0 = (uint32_t)wp, p1 = (uint32_t)(wp >> 32);
+    uint64_t h = (uint64_t)a1 * p1 + mulhi32(a1, p0);
+    h += mulhi32(a0, p1);
+    return a * w - h * q;
 }
 
 FHE_HD uint64_t csub(uint64_t x, uint64_t m) { return x >= m ? x - m : x; }

@@ -18,8 +18,13 @@
 // exchange next to pass 0 crosses waves (fixed_bits below): the others are
 // wave-local, so waves run the later passes without workgroup barriers.
 //
-// Butterflies are Harvey's lazy ones: forward values live in [0, 4q),
-// inverse values in [0, 2q); twiddles are (w, floor(w 2^64 / q)) pairs.
+// Butterflies are Harvey's lazy ones with the quotient estimate of
+// mul_shoup_lazy4 (twiddle products in [0, 4q)): forward values live in
+// [0, 8q), inverse values in [0, 4q), so primes must stay below 2^61.  For
+// primes below 2^64 / (4 (L + 1)) the forward transform can also drop the
+// conditional subtraction (REDUCE = false): a stage then raises the bound by at
+// most 4q, and a row entering below 4q leaves below 4 (L + 1) q.  Twiddles are
+// (w, floor(w 2^64 / q)) pairs.
 #pragma once
 #include <hip/hip_runtime.h>
 #include "modarith.hpp"
@@ -75,27 +80,30 @@ __device__ __forceinline__ uint32_t elem_index(uint32_t tid, uint32_t g, uint32_
     return ((F >> lo) << (lo + r)) | (e << lo) | (F & ((1u << lo) - 1u));
 }
 
+// q4 = 4q.  REDUCE: X, Y in [0, 8q) -> [0, 8q); otherwise bounds grow by 4q.
+template <bool REDUCE>
 __device__ __forceinline__ void ct_bfly(uint64_t &X, uint64_t &Y, uint64_t w, uint64_t wp,
-                                        uint64_t q, uint64_t q2) {
-    uint64_t x = csub(X, q2);                    // [0, 2q)
-    uint64_t t = mul_shoup_lazy(Y, w, wp, q);    // [0, 2q)
-    X = x + t;                                   // [0, 4q)
-    Y = x - t + q2;                              // [0, 4q)
+                                        uint64_t q, uint64_t q4) {
+    uint64_t x = REDUCE ? csub(X, q4) : X;       // [0, 4q)
+    uint64_t t = mul_shoup_lazy4(Y, w, wp, q);   // [0, 4q)
+    X = x + t;                                   // [0, 8q)
+    Y = x - t + q4;                              // (0, 8q)
 }
 
+// X, Y in [0, 4q) -> [0, 4q).
 __device__ __forceinline__ void gs_bfly(uint64_t &X, uint64_t &Y, uint64_t w, uint64_t wp,
-                                        uint64_t q, uint64_t q2) {
-    uint64_t x = X, y = Y;                       // [0, 2q)
-    X = csub(x + y, q2);                         // [0, 2q)
-    Y = mul_shoup_lazy(x - y + q2, w, wp, q);    // [0, 2q)
+                                        uint64_t q, uint64_t q4) {
+    uint64_t x = X, y = Y;
+    X = csub(x + y, q4);
+    Y = mul_shoup_lazy4(x - y + q4, w, wp, q);
 }
 
-template <int L, int LE, int P>
+template <int L, int LE, int P, bool REDUCE>
 __device__ __forceinline__ void fwd_pass(uint64_t (&x)[1 << LE], int tid, const Tw *__restrict__ tw,
                                          uint64_t q) {
     constexpr int r = Geo<L, LE>::R(P), lo = Geo<L, LE>::LO(P), LT = Geo<L, LE>::LT;
     constexpr int R = 1 << r, G = (1 << LE) >> r, l0 = LE * P;
-    const uint64_t q2 = q << 1;
+    const uint64_t q4 = q << 2;
 #pragma unroll
     for (int g = 0; g < G; g++) {
         const uint32_t F = fixed_bits<L, LE, P>((uint32_t)tid, (uint32_t)g);
@@ -110,7 +118,7 @@ __device__ __forceinline__ void fwd_pass(uint64_t (&x)[1 << LE], int tid, const 
 #pragma unroll
                 for (int w = 0; w < half; w++) {
                     const int e0 = (v << (r - u)) | w;
-                    ct_bfly(x[g * R + e0], x[g * R + e0 + half], W.w, W.wp, q, q2);
+                    ct_bfly<REDUCE>(x[g * R + e0], x[g * R + e0 + half], W.w, W.wp, q, q4);
                 }
             }
         }
@@ -122,7 +130,7 @@ __device__ __forceinline__ void inv_pass(uint64_t (&x)[1 << LE], int tid, const 
                                          uint64_t q) {
     constexpr int r = Geo<L, LE>::R(P), lo = Geo<L, LE>::LO(P), LT = Geo<L, LE>::LT;
     constexpr int R = 1 << r, G = (1 << LE) >> r, l0 = LE * P;
-    const uint64_t q2 = q << 1;
+    const uint64_t q4 = q << 2;
 #pragma unroll
     for (int g = 0; g < G; g++) {
         const uint32_t F = fixed_bits<L, LE, P>((uint32_t)tid, (uint32_t)g);
@@ -137,7 +145,7 @@ __device__ __forceinline__ void inv_pass(uint64_t (&x)[1 << LE], int tid, const 
 #pragma unroll
                 for (int w = 0; w < half; w++) {
                     const int e0 = (v << (r - u)) | w;
-                    gs_bfly(x[g * R + e0], x[g * R + e0 + half], W.w, W.wp, q, q2);
+                    gs_bfly(x[g * R + e0], x[g * R + e0 + half], W.w, W.wp, q, q4);
                 }
             }
         }
@@ -186,13 +194,21 @@ __device__ __forceinline__ void exchange(uint64_t *lds, uint64_t (&x)[1 << LE], 
     }
 }
 
-template <int L, int LE, int P>
+struct NoHook {
+    __device__ __forceinline__ void operator()() const {}
+};
+
+// Passes P.. of the forward transform.  hook() runs once, right after the
+// exchange into the last pass (when the wave's LDS block is no longer read by
+// this transform).
+template <int L, int LE, int P, bool REDUCE, class Hook>
 __device__ __forceinline__ void fwd_from(uint64_t (&x)[1 << LE], uint64_t *lds, int tid,
-                                         const Tw *__restrict__ tw, uint64_t q) {
-    fwd_pass<L, LE, P>(x, tid, tw, q);
+                                         const Tw *__restrict__ tw, uint64_t q, const Hook &hook) {
+    fwd_pass<L, LE, P, REDUCE>(x, tid, tw, q);
     if constexpr (P + 1 < Geo<L, LE>::NPASS) {
         exchange<L, LE, P, P + 1>(lds, x, tid);
-        fwd_from<L, LE, P + 1>(x, lds, tid, tw, q);
+        if constexpr (P + 2 == Geo<L, LE>::NPASS) hook();
+        fwd_from<L, LE, P + 1, REDUCE>(x, lds, tid, tw, q, hook);
     }
 }
 
@@ -206,16 +222,18 @@ __device__ __forceinline__ void inv_from(uint64_t (&x)[1 << LE], uint64_t *lds, 
     }
 }
 
-// Forward transform of a row held in registers in pass-0 (natural) layout,
-// values < 4q.  Leaves the transform in last-pass layout, values in [0, 4q).
-template <int L, int LE = 4>
+// Forward transform of a row held in registers in pass-0 (natural) layout.
+// Leaves the transform in last-pass layout.  REDUCE: values < 8q in and out.
+// Otherwise values < 4q in and < 4 (L + 1) q out, for q < 2^64 / (4 (L + 1)).
+template <int L, int LE = 4, bool REDUCE = true, class Hook = NoHook>
 __device__ __forceinline__ void ntt_fwd_regs(uint64_t (&x)[1 << LE], uint64_t *lds, int tid,
-                                             const Tw *__restrict__ tw, uint64_t q) {
-    fwd_from<L, LE, 0>(x, lds, (int)fresh(tid), tw, q);
+                                             const Tw *__restrict__ tw, uint64_t q,
+                                             const Hook &hook = Hook()) {
+    fwd_from<L, LE, 0, REDUCE>(x, lds, (int)fresh(tid), tw, q, hook);
 }
 
 // Inverse transform (without the 1/n factor) of a row held in last-pass
-// layout, values < 2q.  Leaves natural order in pass-0 layout, values < 2q.
+// layout, values < 4q.  Leaves natural order in pass-0 layout, values < 4q.
 template <int L, int LE = 4>
 __device__ __forceinline__ void ntt_inv_regs(uint64_t (&x)[1 << LE], uint64_t *lds, int tid,
                                              const Tw *__restrict__ tw, uint64_t q) {
@@ -233,4 +251,40 @@ __device__ __forceinline__ uint32_t bitrev_layout_index(uint32_t tid, int s) {  
     constexpr int P = Geo<L, LE>::NPASS - 1;
     constexpr int R = 1 << Geo<L, LE>::R(P);
     return elem_index<L, LE, P>(tid, s / R, s % R);
+}
+
+// Prefetch of a row's pass-0 elements through LDS (E = 16, T >= 64).  From
+// pass 1 on, wave w keeps its exchanges inside the LDS block of positions
+// lds_pos([1024 w, 1024 w + 1024)), which starts at word 1088 w.  Once the
+// last exchange of a transform has been read, that block is free until the
+// next transform's first (workgroup-wide) exchange; it can then receive the
+// wave's pass-0 elements of the next row (16 runs of 64 consecutive residues,
+// run s holding elements s T + 64 w + [0, 64)) by the LDS-DMA path, 16 bytes
+// per lane and no registers, while the wave keeps computing.  Run s lands at
+// word 1088 w + 64 s.  The caller waits for the copies (vmcnt) before reading.
+typedef __attribute__((address_space(3))) void *lds_void_ptr;
+
+template <int L>
+__device__ __forceinline__ void prefetch_row_lds(uint64_t *lds, const uint64_t *__restrict__ src,
+                                                 uint32_t tid) {
+    constexpr uint32_t T = Geo<L>::T;
+    static_assert(T >= 64, "whole waves only");
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  // the block's last reads are done
+    const uint32_t w = __builtin_amdgcn_readfirstlane(tid >> 6), l = tid & 63u;
+    uint64_t *blk = lds + 1088u * w;
+#pragma unroll
+    for (uint32_t m = 0; m < 8; m++) {
+        const uint32_t s = 2u * m + (l >> 5);
+        const uint64_t *g = src + s * T + 64u * w + 2u * (l & 31u);
+        __builtin_amdgcn_global_load_lds((const void *)g, (lds_void_ptr)(blk + 128u * m), 16, 0, 0);
+    }
+}
+
+// Waits for the copies of prefetch_row_lds (and every other outstanding
+// vector-memory load of the wave).
+__device__ __forceinline__ void prefetch_wait() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// Slot s of the pass-0 layout of the prefetched row.
+__device__ __forceinline__ uint64_t prefetched(const uint64_t *lds, uint32_t tid, int s) {
+    return lds[1088u * (tid >> 6) + 64u * (uint32_t)s + (tid & 63u)];
 }

@@ -297,8 +297,12 @@ def test_bridge_full_size_sampled(dev):
         want = bfv.bridge_bits(P, list(eq_h[j]), 5)
         assert (bits_h[j] == want).all(), j
     dec = ctx.decrypt(km["s"], bits.reshape(-1, 2, len(qs), n)).reshape(count, 5, n)
-    for j in range(count):
-        assert [int(dec[j, b, 0]) for b in range(5)] == [(int(xs[j]) >> b) & 1 for b in range(5)], j
+    bad = [j for j in range(count)
+           if [int(dec[j, b, 0]) for b in range(5)] != [(int(xs[j]) >> b) & 1 for b in range(5)]]
+    if bad:  # name the chains that differ from the oracle before failing
+        j = bad[0]
+        wrong = [c for c in range(t) if not (eq_h[j, c] == bfv.bridge_eq(P, cts[j], rlk, c)).all()]
+        pytest.fail(f"items {bad} decrypt wrong; item {j} (x = {int(xs[j])}) chains {wrong} differ")
 
 
 # ------------------------------------------------------------------ edges ----

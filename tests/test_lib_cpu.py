@@ -54,6 +54,7 @@ Q4096 = inputs.PRIMES[(4096, 36)]
     dict(n=4096, q=[68719403009 + 8192], t=65537),       # 1 mod 2n but composite
     dict(n=8192, q=Q4096, t=65537),                      # q_i != 1 mod 2n
     dict(n=4096, q=[(1 << 62) + 1], t=65537),            # q_i >= 2^62
+    dict(n=4096, q=[2305843009213800449], t=65537),     # prime, 1 mod 2n, but >= 2^61
     dict(n=4096, q=Q4096, t=Q4096[1]),                   # gcd(t, q) != 1
     dict(n=4096, q=Q4096, t=65539),                      # slots need t = 1 mod 2n
     dict(n=4096, q=Q4096, t=1),                          # t < 2
