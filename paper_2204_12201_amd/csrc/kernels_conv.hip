@@ -15,6 +15,13 @@
 
 namespace {
 
+// A table word read through the constant address space: the tables do not
+// change while a kernel runs, and wave-uniform reads then become scalar loads
+// (the multiply-add asm takes its constant operand from SGPRs).
+__device__ __forceinline__ uint64_t ldc(const uint64_t *p) {
+    return *(const __attribute__((address_space(4))) uint64_t *)p;
+}
+
 // ---------------------------------------------------------------- exact path --
 
 // Garner digits d of X (residues r in basis M): X = sum_b d_b prod_{a<b} m_a.
@@ -76,11 +83,12 @@ __device__ __forceinline__ uint64_t mrc_eval(const MrcConst &M, const uint64_t (
 // item `blockIdx.z`, the centred lift x~ in (-q/2, q/2) written modulo each
 // P prime into E[item][poly][k + j]:
 //   x~ = sum_i y_i qhat_i - beta q,  y_i = [x_i qhat_i^-1]_{q_i},  beta = round(sum_i y_i / q_i).
-template <int MK, int MKP>
+// EX: the basis sizes are exactly MK and MKP (loops without per-term branches).
+template <int MK, int MKP, bool EX>
 __global__ __launch_bounds__(256) void k_lift(DevCtx c, const uint64_t *__restrict__ a,
                                               const uint64_t *__restrict__ b,
                                               uint64_t *__restrict__ E, int npoly) {
-    const int n = c.n, k = c.k, kp = c.kp, K = c.K;
+    const int n = c.n, k = EX ? MK : c.k, kp = EX ? MKP : c.kp, K = EX ? MK + MKP : c.K;
     const int coef = blockIdx.x * 256 + threadIdx.x;
     if (coef >= n) return;
     const int poly = blockIdx.y;
@@ -110,13 +118,13 @@ __global__ __launch_bounds__(256) void k_lift(DevCtx c, const uint64_t *__restri
         for (int j = 0; j < MKP; j++) {
             if (j < kp) {
                 const uint64_t *m = cc.lift_m[j];
-                Acc128 acc;
-                acc_init(acc);
+                Acc3 acc;
+                acc3_init(acc);
 #pragma unroll
                 for (int i = 0; i < MK; i++)
-                    if (i < k) acc_mac(acc, y[i], m[i]);
-                acc_mac(acc, beta, m[k]);
-                dst[(size_t)j * n + coef] = acc_reduce_mont(acc, cc.p[j], cc.p_qinv[j], cc.p_one[j]);
+                    if (i < k) acc3_mac(acc, y[i], ldc(m + i));
+                acc3_mac(acc, beta, ldc(m + k));
+                dst[(size_t)j * n + coef] = acc_reduce_mont(acc3_value(acc), cc.p[j], cc.p_qinv[j], cc.p_one[j]);
             }
         }
     } else {
@@ -143,11 +151,11 @@ __global__ __launch_bounds__(256) void k_lift(DevCtx c, const uint64_t *__restri
 // Step 1 (in P):   C_{p_j} = [t q^-1 D_{p_j} + h q^-1 + v - sum_i y_i q_i^-1]_{p_j},
 //                  y_i = [(t D_{q_i} + h) qhat_i^-1]_{q_i}, v = floor(sum_i y_i / q_i).
 // Step 2 (P -> Q): centred conversion of C, which satisfies |C| < P/2.
-template <int MK, int MKP>
+template <int MK, int MKP, bool EX>
 __global__ __launch_bounds__(256) void k_scale(DevCtx c, const uint64_t *__restrict__ Dt,
                                                uint64_t *__restrict__ out,
                                                uint64_t *__restrict__ C2) {
-    const int n = c.n, k = c.k, kp = c.kp, K = c.K;
+    const int n = c.n, k = EX ? MK : c.k, kp = EX ? MKP : c.kp, K = EX ? MK + MKP : c.K;
     const int coef = blockIdx.x * 256 + threadIdx.x;
     if (coef >= n) return;
     const int comp = blockIdx.y;
@@ -183,16 +191,15 @@ __global__ __launch_bounds__(256) void k_scale(DevCtx c, const uint64_t *__restr
         z[j] = 0;
         if (j < kp) {
             const uint64_t *m = cc.scale_m[j];
-            Acc128 acc;
-            acc_init(acc);
+            Acc3 acc;
+            acc3_init(acc);
 #pragma unroll
             for (int i = 0; i < MK; i++)
-                if (i < k) acc_mac(acc, y[i], m[i]);
-            acc_mac(acc, dp[j], m[k]);
-            acc_mac(acc, v, m[k + 1]);
-            acc.lo += m[k + 2];
-            acc.hi += acc.lo < m[k + 2] ? 1u : 0u;
-            const uint64_t r = acc_reduce_mont(acc, cc.p[j], cc.p_qinv[j], cc.p_one[j]);  // C_{p_j}
+                if (i < k) acc3_mac(acc, y[i], ldc(m + i));
+            acc3_mac(acc, dp[j], ldc(m + k));
+            acc3_mac(acc, v, ldc(m + k + 1));
+            acc3_add(acc, ldc(m + k + 2));
+            const uint64_t r = acc_reduce_mont(acc3_value(acc), cc.p[j], cc.p_qinv[j], cc.p_one[j]);  // C_{p_j}
             z[j] = mul_shoup(r, cc.phinv[j], cc.phinv_p[j], cc.p[j]);
             e2 = fma((double)z[j], cc.inv_p[j], e2);
         }
@@ -205,13 +212,13 @@ __global__ __launch_bounds__(256) void k_scale(DevCtx c, const uint64_t *__restr
         for (int i = 0; i < MK; i++) {
             if (i < k) {
                 const uint64_t *m = cc.p2q_m[i];
-                Acc128 acc;
-                acc_init(acc);
+                Acc3 acc;
+                acc3_init(acc);
 #pragma unroll
                 for (int j = 0; j < MKP; j++)
-                    if (j < kp) acc_mac(acc, z[j], m[j]);
-                acc_mac(acc, beta, m[kp]);
-                dst[(size_t)i * n + coef] = acc_reduce_mont(acc, cc.q[i], cc.q_qinv[i], cc.q_one[i]);
+                    if (j < kp) acc3_mac(acc, z[j], ldc(m + j));
+                acc3_mac(acc, beta, ldc(m + kp));
+                dst[(size_t)i * n + coef] = acc_reduce_mont(acc3_value(acc), cc.q[i], cc.q_qinv[i], cc.q_one[i]);
             }
         }
         return;
@@ -465,31 +472,34 @@ inline unsigned grid_for(size_t words, unsigned block = 256) {
     return (unsigned)g;
 }
 
-template <template <int, int> class Launcher, typename... A>
-hipError_t by_class(int k, int kp, A &&...args) {
-    if (k <= 4 && kp <= 4) return Launcher<4, 4>::run(args...);
-    if (k <= 8 && kp <= 8) return Launcher<8, 8>::run(args...);
-    if (k <= 8 && kp <= 12) return Launcher<8, 12>::run(args...);
-    if (k <= FHE_MAXK && kp <= FHE_MAXKP) return Launcher<FHE_MAXK, FHE_MAXKP>::run(args...);
+template <template <int, int, bool> class Launcher, typename... A>
+hipError_t by_class(int k, int kp, A... args) {
+    if (k == 3 && kp == 3) return Launcher<3, 3, true>::run(args...);
+    if (k == 5 && kp == 5) return Launcher<5, 5, true>::run(args...);
+    if (k == 8 && kp == 8) return Launcher<8, 8, true>::run(args...);
+    if (k <= 4 && kp <= 4) return Launcher<4, 4, false>::run(args...);
+    if (k <= 8 && kp <= 8) return Launcher<8, 8, false>::run(args...);
+    if (k <= 8 && kp <= 12) return Launcher<8, 12, false>::run(args...);
+    if (k <= FHE_MAXK && kp <= FHE_MAXKP) return Launcher<FHE_MAXK, FHE_MAXKP, false>::run(args...);
     return hipErrorInvalidValue;
 }
 
-template <int MK, int MKP>
+template <int MK, int MKP, bool EX>
 struct LiftL {
     static hipError_t run(const DevCtx &c, const uint64_t *a, const uint64_t *b, uint64_t *E,
                           int npoly, size_t items, hipStream_t s) {
         dim3 grid((c.n + 255) / 256, npoly, (unsigned)items);
-        hipLaunchKernelGGL((k_lift<MK, MKP>), grid, dim3(256), 0, s, c, a, b, E, npoly);
+        hipLaunchKernelGGL((k_lift<MK, MKP, EX>), grid, dim3(256), 0, s, c, a, b, E, npoly);
         return hipGetLastError();
     }
 };
 
-template <int MK, int MKP>
+template <int MK, int MKP, bool EX>
 struct ScaleL {
     static hipError_t run(const DevCtx &c, const uint64_t *Dt, uint64_t *out, uint64_t *C2,
                           size_t items, hipStream_t s) {
         dim3 grid((c.n + 255) / 256, 3, (unsigned)items);
-        hipLaunchKernelGGL((k_scale<MK, MKP>), grid, dim3(256), 0, s, c, Dt, out, C2);
+        hipLaunchKernelGGL((k_scale<MK, MKP, EX>), grid, dim3(256), 0, s, c, Dt, out, C2);
         return hipGetLastError();
     }
 };

@@ -106,6 +106,63 @@ FHE_HD void acc_mac(Acc128 &a, uint64_t x, uint64_t y) {
     a.hi += hi + (a.lo < lo ? 1u : 0u);
 }
 
+#if defined(__HIPCC__)
+// Sum of 64 x 64-bit products kept as three 64-bit partial sums (of the
+// products of 32-bit halves lo*lo, lo*hi + hi*lo, hi*hi) plus carry counts of
+// the first two, so that a term costs four v_mad_u64_u32 and three
+// carry additions and nothing is propagated until the end:
+//   sum = lo + mid 2^32 + (hi + clo) 2^64 + cmid 2^96.
+// The carry-out of each multiply-add (an SGPR lane mask) is added into the
+// counts with v_addc; every such read comes at least two instructions after
+// the write that produced it.
+struct Acc3 {
+    uint64_t lo, mid, hi;
+    uint32_t clo, cmid;
+};
+
+__device__ __forceinline__ void acc3_init(Acc3 &A) {
+    A.lo = 0;
+    A.mid = 0;
+    A.hi = 0;
+    A.clo = 0;
+    A.cmid = 0;
+}
+
+// A += a b for a < 2^64 (vector) and b < 2^64 (wave-uniform).
+__device__ __forceinline__ void acc3_mac(Acc3 &A, uint64_t a, uint64_t b) {
+    const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32);
+    const uint32_t b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
+    uint64_t c1, c2, c3, c4;
+    asm("v_mad_u64_u32 %[lo], %[c1], %[a0], %[b0], %[lo]\n\t"
+        "v_mad_u64_u32 %[mid], %[c2], %[a0], %[b1], %[mid]\n\t"
+        "v_mad_u64_u32 %[hi], %[c4], %[a1], %[b1], %[hi]\n\t"
+        "v_addc_co_u32_e64 %[clo], %[c1], 0, %[clo], %[c1]\n\t"
+        "v_mad_u64_u32 %[mid], %[c3], %[a1], %[b0], %[mid]\n\t"
+        "v_addc_co_u32_e64 %[cmid], %[c2], 0, %[cmid], %[c2]\n\t"
+        "s_nop 1\n\t"
+        "v_addc_co_u32_e64 %[cmid], %[c3], 0, %[cmid], %[c3]"
+        : [lo] "+v"(A.lo), [mid] "+v"(A.mid), [hi] "+v"(A.hi), [clo] "+v"(A.clo), [cmid] "+v"(A.cmid),
+          [c1] "=&s"(c1), [c2] "=&s"(c2), [c3] "=&s"(c3), [c4] "=&s"(c4)
+        : [a0] "v"(a0), [a1] "v"(a1), [b0] "s"(b0), [b1] "s"(b1));
+}
+
+// A += c for a constant c < 2^64.
+__device__ __forceinline__ void acc3_add(Acc3 &A, uint64_t c) {
+    const uint64_t s = A.lo + c;
+    A.clo += s < c ? 1u : 0u;
+    A.lo = s;
+}
+
+// The 128-bit value of A (its sums of products stay below 2^127).
+__device__ __forceinline__ Acc128 acc3_value(const Acc3 &A) {
+    const uint64_t m = A.mid << 32;
+    Acc128 r;
+    r.lo = A.lo + m;
+    r.hi = A.hi + (A.mid >> 32) + A.clo + ((uint64_t)A.cmid << 32) + (r.lo < m ? 1u : 0u);
+    return r;
+}
+#endif
+
 // (acc) 2^-64 mod q in [0, q) for any 128-bit acc: the high word is first
 // reduced below 2q by a Shoup multiplication by 1 (one_p = floor(2^64 / q)),
 // which keeps the REDC input below 2q 2^64; REDC then lands in [0, 3q).

@@ -98,6 +98,21 @@ __device__ __forceinline__ void gs_bfly(uint64_t &X, uint64_t &Y, uint64_t w, ui
     Y = mul_shoup_lazy4(x - y + q4, w, wp, q);
 }
 
+// Twiddle i.  UNIFORM: the index is the same in every lane of the wave; the
+// table is then read through the constant address space, which lets the
+// compiler use scalar loads (merged into wide ones, one wait per pass) instead
+// of per-lane vector loads waited one at a time.
+template <bool UNIFORM>
+__device__ __forceinline__ Tw load_tw(const Tw *__restrict__ tw, uint32_t i) {
+    if constexpr (UNIFORM) {
+        typedef const __attribute__((address_space(4))) uint64_t *cptr;
+        const cptr p = (cptr)tw + 2u * i;
+        return Tw{p[0], p[1]};
+    } else {
+        return tw[i];
+    }
+}
+
 template <int L, int LE, int P, bool REDUCE>
 __device__ __forceinline__ void fwd_pass(uint64_t (&x)[1 << LE], int tid, const Tw *__restrict__ tw,
                                          uint64_t q) {
@@ -114,7 +129,7 @@ __device__ __forceinline__ void fwd_pass(uint64_t (&x)[1 << LE], int tid, const 
             const int half = R >> (u + 1);
 #pragma unroll
             for (int v = 0; v < (1 << u); v++) {
-                const Tw W = tw[(1 << (l0 + u)) + (H << u) + v];
+                const Tw W = load_tw<(lo >= 6 || LT <= lo)>(tw, (1u << (l0 + u)) + (H << u) + v);
 #pragma unroll
                 for (int w = 0; w < half; w++) {
                     const int e0 = (v << (r - u)) | w;
@@ -141,7 +156,7 @@ __device__ __forceinline__ void inv_pass(uint64_t (&x)[1 << LE], int tid, const 
             const int half = R >> (u + 1);
 #pragma unroll
             for (int v = 0; v < (1 << u); v++) {
-                const Tw W = tw[(1 << (l0 + u)) + (H << u) + v];
+                const Tw W = load_tw<(lo >= 6 || LT <= lo)>(tw, (1u << (l0 + u)) + (H << u) + v);
 #pragma unroll
                 for (int w = 0; w < half; w++) {
                     const int e0 = (v << (r - u)) | w;
