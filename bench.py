@@ -77,7 +77,7 @@ def percentile(xs, p):
 def transform_rows(ctx, name: str):
     """Transform rows one item (one squaring) sends through kernel `name`."""
     k, K = ctx.k, ctx.k + ctx.aux_primes
-    return {"fwd_ext": 2 * K, "tensor_intt": 3 * K, "square_tensor": 5 * K,
+    return {"mul_tensor": 7 * K, "square_tensor": 5 * K,
             "relin_fused": k * k + 2 * k}.get(name)
 
 
@@ -218,34 +218,52 @@ def main():
     print(json.dumps(out))
 
 
-def plain_vs_batched(ctx_factory, fhe, inputs, torch, B=256, single_calls=200):
-    """n = 16384, eight 55-bit primes, t = 65537: B single-pair calls against one
-    call with count = B, on the same ciphertexts; p50/p99 of single-call latency."""
+def plain_vs_batched(ctx_factory, fhe, inputs, torch, B=256, single_calls=200,
+                     sweep=(1, 16, 64, 256, 341)):
+    """n = 16384, eight 55-bit primes, t = 65537: for every batch size Bs in
+    `sweep`, Bs single-pair calls against one call with count = Bs on the same
+    ciphertexts; p50/p99 of single-call latency; per-kernel time of the
+    batched call at B."""
     ctx = ctx_factory()
     n, qs = ctx.n, ctx.q
     km = inputs.key_material(n, qs, 4)
     pk, rlk = ctx.keygen(km["s"], km["pk_a"], km["pk_e"], km["rlk_a"], km["rlk_e"])
-    a = fhe.from_numpy_u64(inputs.uniform_ciphertexts(n, qs, B, 4, "a"), "cuda")
-    b = fhe.from_numpy_u64(inputs.uniform_ciphertexts(n, qs, B, 4, "b"), "cuda")
-    out = ctx.empty_ct(B)
+    bmax = max(max(sweep), B)
+    a = fhe.from_numpy_u64(inputs.uniform_ciphertexts(n, qs, bmax, 4, "a"), "cuda")
+    b = fhe.from_numpy_u64(inputs.uniform_ciphertexts(n, qs, bmax, 4, "b"), "cuda")
+    out = ctx.empty_ct(bmax)
     stream = torch.cuda.current_stream()
     # warm up both paths
     for _ in range(3):
-        ctx.mul_relin(rlk, a, b, out=out)
+        ctx.mul_relin(rlk, a[:B], b[:B], out=out[:B])
         ctx.mul_relin(rlk, a[:1], b[:1], out=out[:1])
     torch.cuda.synchronize()
-    reps = 3
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        ctx.mul_relin(rlk, a, b, out=out)
+
+    def rates(bs, reps):
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ctx.mul_relin(rlk, a[:bs], b[:bs], out=out[:bs])
+        torch.cuda.synchronize()
+        batched = bs * reps / (time.perf_counter() - t0)
+        views = [(a[j:j + 1], b[j:j + 1], out[j:j + 1]) for j in range(bs)]
+        t0 = time.perf_counter()
+        for x, y, o in views:
+            ctx.mul_relin(rlk, x, y, out=o)
+        torch.cuda.synchronize()
+        return batched, bs / (time.perf_counter() - t0)
+
+    rows = []
+    for bs in sweep:
+        bt, pl = rates(bs, 3 if bs >= 64 else 20)
+        rows.append({"B": bs, "batched_mul_relin_per_s": bt, "plain_mul_relin_per_s": pl})
+    batched, plain = rates(B, 3)
+    ctx.reset_kernel_stats()
+    ctx.set_timing(True)
+    ctx.mul_relin(rlk, a[:B], b[:B], out=out[:B])
     torch.cuda.synchronize()
-    batched = B * reps / (time.perf_counter() - t0)
+    ctx.set_timing(False)
+    kern = {k: round(v[0], 3) for k, v in ctx.kernel_stats().items() if v[1] > 0}
     views = [(a[j:j + 1], b[j:j + 1], out[j:j + 1]) for j in range(B)]
-    t0 = time.perf_counter()
-    for x, y, o in views:
-        ctx.mul_relin(rlk, x, y, out=o)
-    torch.cuda.synchronize()
-    plain = B / (time.perf_counter() - t0)
     lat = []
     for j in range(single_calls):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -258,7 +276,8 @@ def plain_vs_batched(ctx_factory, fhe, inputs, torch, B=256, single_calls=200):
     lat_ms = [e0.elapsed_time(e1) for e0, e1 in lat]
     return {"n": n, "k": len(qs), "t": 65537, "B": B, "batched_mul_relin_per_s": batched,
             "plain_mul_relin_per_s": plain, "batched_over_plain": batched / plain,
-            "single_call_p50_ms": percentile(lat_ms, 50), "single_call_p99_ms": percentile(lat_ms, 99)}
+            "single_call_p50_ms": percentile(lat_ms, 50), "single_call_p99_ms": percentile(lat_ms, 99),
+            "batched_kernel_ms": kern, "sweep": rows}
 
 
 def cpu_baseline(inputs):

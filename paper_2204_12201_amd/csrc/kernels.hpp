@@ -25,8 +25,6 @@ struct DevCtx {
 // Kernel kinds (timing and profiling names).
 enum KernelKind {
     KK_LIFT = 0,
-    KK_FWD_EXT,
-    KK_TENSOR_INTT,
     KK_SQUARE_TENSOR,
     KK_SCALE,
     KK_RELIN_FUSED,
@@ -34,6 +32,9 @@ enum KernelKind {
     KK_ELEMENTWISE,
     KK_BRIDGE,
     KK_MISC,
+    KK_MUL_TENSOR,
+    KK_FWD_EXT,
+    KK_TENSOR_INTT,
     KK_COUNT
 };
 
@@ -56,6 +57,8 @@ hipError_t launch_tensor_intt(const DevCtx &c, const uint64_t *E, uint64_t *Dt, 
                               size_t items, hipStream_t s);
 // Squaring: forward transforms of a0, a1 (P limbs from E) and the three
 // inverse-transformed tensor components, one workgroup per (limb, item).
+hipError_t launch_mul_tensor(const DevCtx &c, const uint64_t *a, const uint64_t *b, const uint64_t *E,
+                             uint64_t *Dt, size_t items, hipStream_t s);
 hipError_t launch_square_tensor(const DevCtx &c, const uint64_t *a, const uint64_t *E, uint64_t *Dt,
                                 size_t items, hipStream_t s);
 // Key switching: out[item][l] += sum_i [C2]_{q_i} rlk_i[l] for l = 0, 1.

@@ -24,18 +24,22 @@ __device__ __forceinline__ uint64_t ldc(const uint64_t *p) {
 
 // ---------------------------------------------------------------- exact path --
 
+// The exact path runs for a tiny fraction of the coefficients: its loops stay
+// rolled so that it does not raise the register count (and so the occupancy)
+// of the fast path that shares the kernel.
+
 // Garner digits d of X (residues r in basis M): X = sum_b d_b prod_{a<b} m_a.
 template <int MB>
 __device__ __forceinline__ void mrc_digits(const MrcConst &M, const uint64_t (&r)[MB],
                                            uint64_t (&d)[MB]) {
     const int K = (int)M.K;
-#pragma unroll
+#pragma unroll 1
     for (int b = 0; b < MB; b++) {
         d[b] = 0;
         if (b < K) {
             const uint64_t mb = M.m[b];
             uint64_t v = r[b];
-#pragma unroll
+#pragma unroll 1
             for (int a = 0; a < MB; a++) {
                 if (a < b) {
                     const uint64_t da = mul_shoup(d[a], 1, M.one_p[b], mb);
@@ -52,7 +56,7 @@ __device__ __forceinline__ void mrc_digits(const MrcConst &M, const uint64_t (&r
 template <int MB>
 __device__ __forceinline__ bool mrc_gt_half(const MrcConst &M, const uint64_t (&d)[MB]) {
     int res = 0;
-#pragma unroll
+#pragma unroll 1
     for (int b = MB - 1; b >= 0; b--) {
         if (b < (int)M.K && res == 0) {
             const uint64_t h = M.half_digit[b];
@@ -67,7 +71,7 @@ template <int MB>
 __device__ __forceinline__ uint64_t mrc_eval(const MrcConst &M, const uint64_t (&d)[MB], int j) {
     const uint64_t p = M.target[j], op = M.tgt_one_p[j];
     uint64_t acc = 0;
-#pragma unroll
+#pragma unroll 1
     for (int b = MB - 1; b >= 0; b--) {
         if (b < (int)M.K) {
             acc = mul_shoup(acc, M.m_mod_t[b][j], M.m_mod_t_p[b][j], p);
@@ -133,7 +137,7 @@ __global__ __launch_bounds__(256) void k_lift(DevCtx c, const uint64_t *__restri
         uint64_t dg[MK];
         mrc_digits<MK>(M, x, dg);
         const bool gt = mrc_gt_half<MK>(M, dg);
-#pragma unroll
+#pragma unroll 1
         for (int j = 0; j < MKP; j++) {
             if (j < kp) {
                 uint64_t r = mrc_eval<MK>(M, dg, j);
@@ -236,7 +240,7 @@ __global__ __launch_bounds__(256) void k_scale(DevCtx c, const uint64_t *__restr
     }
     mrc_digits<MK>(MQ, yq, dgq);
     uint64_t cp[MKP], dgp[MKP];
-#pragma unroll
+#pragma unroll 1
     for (int j = 0; j < MKP; j++) {
         cp[j] = 0;
         if (j < kp) {
@@ -248,7 +252,7 @@ __global__ __launch_bounds__(256) void k_scale(DevCtx c, const uint64_t *__restr
     }
     mrc_digits<MKP>(MP, cp, dgp);
     const bool gt = mrc_gt_half<MKP>(MP, dgp);
-#pragma unroll
+#pragma unroll 1
     for (int i = 0; i < MK; i++) {
         if (i < k) {
             uint64_t r = mrc_eval<MKP>(MP, dgp, i);

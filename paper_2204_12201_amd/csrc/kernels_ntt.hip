@@ -4,6 +4,10 @@
 //  k_fwd_ext       forward transform of the extended inputs of a product
 //  k_tensor_intt   tensor component (Montgomery products of transformed
 //                  inputs, computed on load) followed by the inverse transform
+//                  (the product path for small batches: more workgroups)
+//  k_mul_tensor    product of two ciphertexts: forward transforms of the four
+//                  input polynomials and the three inverse-transformed tensor
+//                  components in one pass
 //  k_square_tensor squaring: forward transforms of both input polynomials and
 //                  the three inverse-transformed tensor components in one pass
 //  k_relin_fused   key switching: digit transforms, inner product with the key
@@ -138,6 +142,126 @@ __global__ __launch_bounds__(Geo<L>::T) void k_tensor_intt(DevCtx c, const uint6
     uint64_t *dst = Dt + ((item * 3 + comp) * K + limb) * (size_t)n;
 #pragma unroll
     for (int s = 0; s < 16; s++) dst[natural_index<L>(tid, s)] = mul_shoup(x[s], P.ninvm, P.ninvm_p, q);
+}
+
+// Product of two ciphertexts, transform phase fused: grid (K limbs, items).
+// For limb l of item it transforms a0, a1, b0, b1 (Q limbs from the inputs, P
+// limbs from the lift in E), forms d0 = a0 b0, d1 = a0 b1 + a1 b0, d2 = a1 b1
+// (Montgomery products) and inverse transforms each into Dt[item][comp][l].
+// Two rows live in registers; A1, a1 b1 and a0 b1 are parked (transform
+// domain) in the item's own output rows, which this workgroup alone touches.
+// With whole waves, each of a0 and b0 is copied into LDS while the transform
+// before it finishes (prefetch_row_lds).
+template <int L>
+__global__ __launch_bounds__(Geo<L>::T) void k_mul_tensor(DevCtx c, const uint64_t *__restrict__ a,
+                                                         const uint64_t *__restrict__ b,
+                                                         const uint64_t *__restrict__ E,
+                                                         uint64_t *__restrict__ Dt) {
+    __shared__ uint64_t lds[Geo<L>::lds_words];
+    constexpr int n = Geo<L>::N;
+    constexpr bool PREFETCH = Geo<L>::T >= 64;
+    const uint32_t tid = threadIdx.x;
+    const int limb = blockIdx.x;
+    const size_t item = blockIdx.y;
+    const int k = c.k, K = c.K;
+    const PrimeConst &P = c.pc[limb];
+    const uint64_t q = P.q, qi = P.qinv_neg, q2 = q << 1, q4 = q << 2;
+    const Tw *tw = c.tw + (size_t)limb * n;
+    const Tw *itw = c.itw + (size_t)limb * n;
+    const uint64_t *src[4];
+#pragma unroll
+    for (int poly = 0; poly < 4; poly++)
+        src[poly] = limb < k ? (poly < 2 ? a + ((item * 2 + poly) * k + limb) * (size_t)n
+                                         : b + ((item * 2 + poly - 2) * k + limb) * (size_t)n)
+                             : E + ((item * 4 + poly) * K + limb) * (size_t)n;
+    uint64_t *d0 = Dt + ((item * 3 + 0) * K + limb) * (size_t)n;
+    uint64_t *d1 = Dt + ((item * 3 + 1) * K + limb) * (size_t)n;
+    uint64_t *d2 = Dt + ((item * 3 + 2) * K + limb) * (size_t)n;
+    uint64_t x[16], y[16];
+    // A1 and B1
+    const uint32_t t0 = fresh(tid);
+#pragma unroll
+    for (int s = 0; s < 16; s++) x[s] = src[1][natural_index<L>(t0, s)];
+#pragma unroll
+    for (int s = 0; s < 16; s++) y[s] = src[3][natural_index<L>(t0, s)];
+    asm volatile("" ::: "memory");
+    ntt_fwd_regs<L>(x, lds, tid, tw, q);
+    auto pre_a0 = [&]() {
+        if constexpr (PREFETCH) prefetch_row_lds<L>(lds, src[0], fresh(tid));
+    };
+    ntt_fwd_regs<L, 4, true>(y, lds, tid, tw, q, pre_a0);
+    // park A1 in d1 and a1 b1 in d2; B1 stays in y
+    const uint32_t t1 = fresh(tid);
+#pragma unroll
+    for (int s = 0; s < 16; s++) {
+        const uint32_t idx = bitrev_layout_index<L>(t1, s);
+        const uint64_t a1 = csub(csub(x[s], q4), q2);
+        y[s] = csub(csub(y[s], q4), q2);
+        d1[idx] = a1;
+        d2[idx] = mont_mul_lazy(a1, y[s], q, qi);
+    }
+    asm volatile("" ::: "memory");
+    // A0
+    const uint32_t t2 = fresh(tid);
+    if (PREFETCH) {
+        prefetch_wait();
+#pragma unroll
+        for (int s = 0; s < 16; s++) x[s] = prefetched(lds, t2, s);
+    } else {
+#pragma unroll
+        for (int s = 0; s < 16; s++) x[s] = src[0][natural_index<L>(t2, s)];
+    }
+    auto pre_b0 = [&]() {
+        if constexpr (PREFETCH) prefetch_row_lds<L>(lds, src[2], fresh(tid));
+    };
+    ntt_fwd_regs<L, 4, true>(x, lds, tid, tw, q, pre_b0);
+    // park a0 b1 in d0; A0 stays in x
+    const uint32_t t3 = fresh(tid);
+#pragma unroll
+    for (int s = 0; s < 16; s++) {
+        x[s] = csub(csub(x[s], q4), q2);
+        d0[bitrev_layout_index<L>(t3, s)] = mont_mul_lazy(x[s], y[s], q, qi);
+    }
+    asm volatile("" ::: "memory");
+    // B0
+    const uint32_t t4 = fresh(tid);
+    if (PREFETCH) {
+        prefetch_wait();
+#pragma unroll
+        for (int s = 0; s < 16; s++) y[s] = prefetched(lds, t4, s);
+    } else {
+#pragma unroll
+        for (int s = 0; s < 16; s++) y[s] = src[2][natural_index<L>(t4, s)];
+    }
+    ntt_fwd_regs<L>(y, lds, tid, tw, q);
+    // d0 = a0 b0 in x, d1 = a1 b0 + a0 b1 in y (every thread rereads only the
+    // positions it parked)
+    const uint32_t t5 = fresh(tid);
+#pragma unroll
+    for (int s = 0; s < 16; s++) {
+        const uint32_t idx = bitrev_layout_index<L>(t5, s);
+        const uint64_t b0 = csub(csub(y[s], q4), q2);
+        y[s] = mont_mul_lazy(d1[idx], b0, q, qi) + d0[idx];  // < 4q
+        x[s] = mont_mul_lazy(x[s], b0, q, qi);
+    }
+    asm volatile("" ::: "memory");
+    ntt_inv_regs<L>(x, lds, tid, itw, q);
+    const uint32_t t6 = fresh(tid);
+#pragma unroll
+    for (int s = 0; s < 16; s++) d0[natural_index<L>(t6, s)] = mul_shoup(x[s], P.ninvm, P.ninvm_p, q);
+    // d2's parked product, read while d1 is transformed
+    const uint32_t t7 = fresh(tid);
+#pragma unroll
+    for (int s = 0; s < 16; s++) x[s] = d2[bitrev_layout_index<L>(t7, s)];
+    asm volatile("" ::: "memory");
+    ntt_inv_regs<L>(y, lds, tid, itw, q);
+    const uint32_t t8 = fresh(tid);
+#pragma unroll
+    for (int s = 0; s < 16; s++) d1[natural_index<L>(t8, s)] = mul_shoup(y[s], P.ninvm, P.ninvm_p, q);
+    ntt_inv_regs<L>(x, lds, tid, itw, q);
+    const uint32_t t9 = fresh(tid);
+#pragma unroll
+    for (int s = 0; s < 16; s++) d2[natural_index<L>(t9, s)] = mul_shoup(x[s], P.ninvm, P.ninvm_p, q);
 }
 
 // Squaring, transform phase fused: grid (K limbs, items).  For limb l of item
@@ -341,6 +465,12 @@ struct NttL {
                                dim3(Geo<L>::T), 0, s, c, E, Dt);
         return hipGetLastError();
     }
+    static hipError_t mul_tensor(const DevCtx &c, const uint64_t *a, const uint64_t *b, const uint64_t *E,
+                                 uint64_t *Dt, size_t items, hipStream_t s) {
+        hipLaunchKernelGGL(k_mul_tensor<L>, dim3(c.K, (unsigned)items), dim3(Geo<L>::T), 0, s, c, a, b, E,
+                           Dt);
+        return hipGetLastError();
+    }
     static hipError_t square_tensor(const DevCtx &c, const uint64_t *a, const uint64_t *E, uint64_t *Dt,
                                     size_t items, hipStream_t s) {
         hipLaunchKernelGGL(k_square_tensor<L>, dim3(c.K, (unsigned)items), dim3(Geo<L>::T), 0, s, c, a, E,
@@ -393,6 +523,12 @@ hipError_t launch_tensor_intt(const DevCtx &c, const uint64_t *E, uint64_t *Dt, 
                               size_t items, hipStream_t s) {
     if (items == 0) return hipSuccess;
     FHE_DISPATCH_L(c.L, tensor(c, E, Dt, square, items, s));
+}
+
+hipError_t launch_mul_tensor(const DevCtx &c, const uint64_t *a, const uint64_t *b, const uint64_t *E,
+                             uint64_t *Dt, size_t items, hipStream_t s) {
+    if (items == 0) return hipSuccess;
+    FHE_DISPATCH_L(c.L, mul_tensor(c, a, b, E, Dt, items, s));
 }
 
 hipError_t launch_square_tensor(const DevCtx &c, const uint64_t *a, const uint64_t *E, uint64_t *Dt,

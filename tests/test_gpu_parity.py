@@ -135,6 +135,28 @@ def test_mul_relin_small_all_words(dev, n, bits, k, t, enc):
         assert (sq[j] == want_sq).all() and (sq2[j] == want_sq).all(), f"square {j}"
 
 
+@pytest.mark.parametrize("n,bits,k", [(1024, 36, 3), (2048, 40, 2)])
+def test_mul_relin_fused_batch_all_words(dev, n, bits, k):
+    """Batches large enough for the fused product kernel (and squaring): every
+    word of every product against the oracle.  n = 1024 runs the transforms
+    with one wave per row (and the LDS prefetch inside that wave), n = 2048
+    with two."""
+    qs = bfv.ntt_primes(n, bits, k)
+    P, km, pk, rlk, ctx, rlk_d = setup(n, qs, 65537, "slots", 13)
+    K = k + ctx.aux_primes
+    count = -(-512 // K) + 3
+    say(f"mul_relin fused n={n} k={k} K={K} x{count}")
+    a = inputs.uniform_ciphertexts(n, qs, count, 13, "a")
+    b = inputs.uniform_ciphertexts(n, qs, count, 13, "b")
+    out = down(ctx.mul_relin(rlk_d, up(a), up(b)))
+    da = up(a)
+    sq = down(ctx.mul_relin(rlk_d, da, da))
+    for j in range(count):
+        assert (out[j] == bfv.mul_relin(P, a[j], b[j], rlk)).all(), f"product {j}"
+        if j % 7 == 0:
+            assert (sq[j] == bfv.mul_relin(P, a[j], a[j], rlk)).all(), f"square {j}"
+
+
 def test_exact_path_boundary_inputs(dev):
     """Coefficients on the centring boundary (q-1)/2, (q+1)/2 and products whose
     t D / q sits next to a half-integer force the exact mixed-radix path; the
