@@ -10,9 +10,11 @@ HBM (encrypted on the device) before the timed region.
 
 Prints one JSON line with the metric (ciphertext mul+relin per second inside
 the bridge), conversions/s, per-step p50/p99, the plain-vs-batched mul+relin
-comparison at n = 16384 (one pair per call vs one batched call), the roofline
-of the dominant kernel (timed live with HIP events on the launch stream), and
-the CPU oracle timed on a bounded sample of the same work.
+comparison at n = 16384 (one pair per call vs one batched call, for several
+batch sizes), the transform kernel alone at n = 4096 / 8192 / 16384, products
+at n = 4096, the roofline of the dominant kernel (timed live with HIP events on
+the launch stream), and the CPU oracle timed on a bounded sample of the same
+work.
 """
 from __future__ import annotations
 
@@ -34,14 +36,15 @@ METRIC = "ct mul+relin/s at n=16384 (batched vs plain GPU), bridge conversions/s
 # Peak figures (MI355X, gfx950): 256 CUs x 128 32-bit lanes at 2.4 GHz issue
 # 78.6 T simple VALU lane-ops/s (the fp32 vector peak of 157.3 TFLOP/s counts an
 # FMA as two); 32-bit integer multiplies (v_mul_lo_u32, v_mul_hi_u32,
-# v_mad_u64_u32) issue at half that rate on gfx950.  A lazy 64-bit Shoup
-# butterfly on 32-bit lanes needs at least 10 multiplies (4 for the high half of
-# a*w', 3 each for the low halves of a*w and of quotient*q) and 18 simple ops
-# (64-bit adds, subtracts, compares and selects): 10*2 + 18 = 38 full-rate issue
-# slots, so the butterfly roofline is 78.6e12 / 38 = 2.07e12 butterflies/s.
+# v_mad_u64_u32) issue at half that rate on gfx950.  The lazy 64-bit butterfly
+# used here (Shoup product with a three-multiply quotient estimate) needs at
+# least 9 multiplies (3 for the estimate, 3 each for the low halves of a*w and of
+# quotient*q) and 18 full-rate slots of 64-bit adds, subtracts and the
+# conditional subtraction: 9*2 + 18 = 36 issue slots, so the butterfly roofline
+# is 78.6e12 / 36 = 2.18e12 butterflies/s.
 CUS, LANES_PER_CU, CLOCK = 256, 128, 2.4e9
 VALU_LANE_OPS = CUS * LANES_PER_CU * CLOCK
-SLOTS_PER_BFLY = 10 * 2 + 18
+SLOTS_PER_BFLY = 9 * 2 + 18
 PEAK_BFLY = VALU_LANE_OPS / SLOTS_PER_BFLY
 HBM_PEAK = 8.0e12
 
@@ -211,6 +214,11 @@ def main():
             n, qs, 65537, "slots"), fhe=fhe, inputs=inputs, torch=torch)
         print("[bench] plain vs batched done", file=sys.stderr, flush=True)
 
+    if not args.no_plain:
+        out["ntt_rows"] = ntt_rows_leg(fhe, inputs, torch)
+        out["c0_n4096"] = c0_leg(fhe, inputs, torch)
+        print("[bench] transform rows and n=4096 products done", file=sys.stderr, flush=True)
+
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inputs)
         print("[bench] cpu baseline done", file=sys.stderr, flush=True)
@@ -278,6 +286,61 @@ def plain_vs_batched(ctx_factory, fhe, inputs, torch, B=256, single_calls=200,
             "plain_mul_relin_per_s": plain, "batched_over_plain": batched / plain,
             "single_call_p50_ms": percentile(lat_ms, 50), "single_call_p99_ms": percentile(lat_ms, 99),
             "batched_kernel_ms": kern, "sweep": rows}
+
+
+def ntt_rows_leg(fhe, inputs, torch, reps=4):
+    """The transform kernel alone: forward then inverse transform of 128 MiB of
+    rows per launch (uniform residues; 4096 / 2048 / 1024 rows at n = 4096 /
+    8192 / 16384) with the configured primes; rows/s, butterflies/s and
+    algorithmic HBM bytes (each row read and written once, 16 bytes per
+    coefficient) against the ALU and HBM peaks."""
+    res = []
+    for key in ("bfv_n4096", "bfv_n8192", "bfv_n16384"):
+        cfg = inputs.CONFIGS[key]
+        n, qs = cfg["n"], cfg["q"]
+        k = len(qs)
+        ctx = fhe.Context(n, qs, cfg["t"], cfg["encoding"])
+        count = -(-(16384 * 1024 // n) // k)
+        polys = fhe.from_numpy_u64(inputs.uniform_ciphertexts(n, qs, count, 6, "ntt")[:, 0], "cuda")
+        ctx.ntt(polys)
+        ctx.ntt(polys, inverse=True)
+        torch.cuda.synchronize()
+        ctx.reset_kernel_stats()
+        ctx.set_timing(True)
+        for _ in range(reps):
+            ctx.ntt(polys)
+            ctx.ntt(polys, inverse=True)
+        torch.cuda.synchronize()
+        ctx.set_timing(False)
+        ms, launches = ctx.kernel_stats()["ntt_rows"]
+        rows = count * k * launches
+        rows_s = rows / (ms / 1e3)
+        bfly_s = rows_s * (n // 2) * int(math.log2(n))
+        bytes_s = rows_s * n * 16
+        res.append({"n": n, "rows_per_launch": count * k, "rows_per_s": rows_s, "tbutterfly_per_s": bfly_s / 1e12,
+                    "alu_frac": bfly_s / PEAK_BFLY, "gb_per_s": bytes_s / 1e9, "hbm_frac": bytes_s / HBM_PEAK})
+    return res
+
+
+def c0_leg(fhe, inputs, torch, reps=5):
+    """n = 4096, three 36-bit primes, t = 65537: 64 products of uniform
+    ciphertexts per call (the plain BFV workload's shape)."""
+    cfg = inputs.CONFIGS["bfv_n4096"]
+    n, qs, count = cfg["n"], cfg["q"], cfg["count"]
+    ctx = fhe.Context(n, qs, cfg["t"], cfg["encoding"])
+    km = inputs.key_material(n, qs, 0)
+    pk, rlk = ctx.keygen(km["s"], km["pk_a"], km["pk_e"], km["rlk_a"], km["rlk_e"])
+    a = fhe.from_numpy_u64(inputs.uniform_ciphertexts(n, qs, count, 3, "a"), "cuda")
+    b = fhe.from_numpy_u64(inputs.uniform_ciphertexts(n, qs, count, 3, "b"), "cuda")
+    out = ctx.empty_ct(count)
+    ctx.mul_relin(rlk, a, b, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.mul_relin(rlk, a, b, out=out)
+    torch.cuda.synchronize()
+    return {"n": n, "k": len(qs), "t": cfg["t"], "count": count,
+            "mul_relin_per_s": count * reps / (time.perf_counter() - t0)}
 
 
 def cpu_baseline(inputs):

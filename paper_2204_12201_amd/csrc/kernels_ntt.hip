@@ -36,35 +36,69 @@ __device__ __forceinline__ void load_bitrev(uint64_t (&x)[16], const uint64_t *_
     for (int s = 0; s < 16; s++) x[s] = src[bitrev_layout_index<L>(tid, s)];
 }
 
-// mode: NttMode (kernels.hpp)
-template <int L>
+// mode: NttMode (kernels.hpp).  Rows row0, row0 + gridDim.x, ... of data:
+// the workgroups stay resident and fetch their next row while the current one
+// is transformed (forward with whole waves: into LDS by prefetch_row_lds;
+// otherwise into registers).
+template <int L, bool FWD>
 __global__ __launch_bounds__(Geo<L>::T) void k_ntt_rows(DevCtx c, uint64_t *__restrict__ data,
-                                                       int kmod, int limb_off, int mode) {
+                                                       size_t nrows, int kmod, int limb_off, int mode) {
     __shared__ uint64_t lds[Geo<L>::lds_words];
     constexpr int n = Geo<L>::N;
+    constexpr bool DMA = FWD && Geo<L>::T >= 64;
     const uint32_t tid = threadIdx.x;
-    const size_t row = blockIdx.x;
-    const int limb = (int)(row % kmod) + limb_off;
-    const PrimeConst &P = c.pc[limb];
-    const uint64_t q = P.q;
-    uint64_t *ptr = data + row * n;
+    size_t row = blockIdx.x;
     uint64_t x[16];
-    if (mode == NTT_FWD || mode == NTT_FWD_NINVM) {
-        load_natural<L>(x, ptr, tid);
-        ntt_fwd_regs<L>(x, lds, tid, c.tw + (size_t)limb * n, q);
-#pragma unroll
-        for (int s = 0; s < 16; s++) {
-            uint64_t v = canon8(x[s], q);
-            if (mode == NTT_FWD_NINVM) v = mul_shoup(v, P.ninvm, P.ninvm_p, q);
-            ptr[bitrev_layout_index<L>(tid, s)] = v;
+    if constexpr (FWD) load_natural<L>(x, data + row * n, tid);
+    else load_bitrev<L>(x, data + row * n, tid);
+    for (; row < nrows; row += gridDim.x) {
+        const int limb = (int)(row % kmod) + limb_off;
+        const PrimeConst &P = c.pc[limb];
+        const uint64_t q = P.q;
+        uint64_t *ptr = data + row * n;
+        const size_t next = row + gridDim.x;
+        uint64_t nx[16];
+        if constexpr (DMA) {
+            auto hook = [&]() {
+                if (next < nrows) prefetch_row_lds<L>(lds, data + next * n, fresh(tid));
+            };
+            ntt_fwd_regs<L, 4, true>(x, lds, tid, c.tw + (size_t)limb * n, q, hook);
+        } else {
+            if (next < nrows) {
+                if constexpr (FWD) load_natural<L>(nx, data + next * n, fresh(tid));
+                else load_bitrev<L>(nx, data + next * n, fresh(tid));
+            }
+            if constexpr (FWD) ntt_fwd_regs<L>(x, lds, tid, c.tw + (size_t)limb * n, q);
+            else ntt_inv_regs<L>(x, lds, tid, c.itw + (size_t)limb * n, q);
         }
-    } else {
-        load_bitrev<L>(x, ptr, tid);
-        ntt_inv_regs<L>(x, lds, tid, c.itw + (size_t)limb * n, q);
-        const uint64_t w = mode == NTT_INV ? P.ninv : P.ninvm;
-        const uint64_t wp = mode == NTT_INV ? P.ninv_p : P.ninvm_p;
+        const uint32_t t1 = fresh(tid);
+        if constexpr (FWD) {
 #pragma unroll
-        for (int s = 0; s < 16; s++) ptr[natural_index<L>(tid, s)] = mul_shoup(x[s], w, wp, q);
+            for (int s = 0; s < 16; s++) {
+                uint64_t v = canon8(x[s], q);
+                if (mode == NTT_FWD_NINVM) v = mul_shoup(v, P.ninvm, P.ninvm_p, q);
+                ptr[bitrev_layout_index<L>(t1, s)] = v;
+            }
+        } else {
+            const uint64_t w = mode == NTT_INV ? P.ninv : P.ninvm;
+            const uint64_t wp = mode == NTT_INV ? P.ninv_p : P.ninvm_p;
+#pragma unroll
+            for (int s = 0; s < 16; s++) ptr[natural_index<L>(t1, s)] = mul_shoup(x[s], w, wp, q);
+            // the inverse ends on the workgroup-wide exchange and the next row
+            // starts with a wave-local one in the same buffer
+            __syncthreads();
+        }
+        if (next < nrows) {
+            if constexpr (DMA) {
+                prefetch_wait();
+                const uint32_t t0 = fresh(tid);
+#pragma unroll
+                for (int s = 0; s < 16; s++) x[s] = prefetched(lds, t0, s);
+            } else {
+#pragma unroll
+                for (int s = 0; s < 16; s++) x[s] = nx[s];
+            }
+        }
     }
 }
 
@@ -443,11 +477,30 @@ __global__ __launch_bounds__(Geo<L>::T) void k_relin_fused(DevCtx c, const uint6
 
 template <int L>
 struct NttL {
+    template <bool FWD>
+    static hipError_t rows_dir(const DevCtx &c, uint64_t *data, size_t nrows, int kmod, int off, int mode,
+                               hipStream_t s) {
+        // one resident pass of workgroups over the chip (row loop inside)
+        static int per_chip = 0;
+        if (per_chip == 0) {
+            int nb = 0, dev = 0, cus = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ntt_rows<L, FWD>, Geo<L>::T, 0) !=
+                    hipSuccess ||
+                hipGetDevice(&dev) != hipSuccess ||
+                hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+                nb < 1 || cus < 1)
+                return hipErrorInvalidValue;
+            per_chip = nb * cus;
+        }
+        const size_t grid = nrows < (size_t)per_chip ? nrows : (size_t)per_chip;
+        hipLaunchKernelGGL((k_ntt_rows<L, FWD>), dim3((unsigned)grid), dim3(Geo<L>::T), 0, s, c, data, nrows,
+                           kmod, off, mode);
+        return hipGetLastError();
+    }
     static hipError_t rows(const DevCtx &c, uint64_t *data, size_t nrows, int kmod, int off, int mode,
                            hipStream_t s) {
-        hipLaunchKernelGGL(k_ntt_rows<L>, dim3((unsigned)nrows), dim3(Geo<L>::T), 0, s, c, data, kmod,
-                           off, mode);
-        return hipGetLastError();
+        if (mode == NTT_FWD || mode == NTT_FWD_NINVM) return rows_dir<true>(c, data, nrows, kmod, off, mode, s);
+        return rows_dir<false>(c, data, nrows, kmod, off, mode, s);
     }
     static hipError_t fwd_ext(const DevCtx &c, const uint64_t *a, const uint64_t *b, uint64_t *E,
                               int npoly, size_t items, hipStream_t s) {
