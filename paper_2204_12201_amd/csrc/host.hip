@@ -924,8 +924,25 @@ fhe_status fhe_bridge_to_bits(fhe_ctx *c, const uint64_t *rlk, const uint64_t *x
     for (size_t g0 = 0; g0 < count; g0 += G) {
         const size_t gc = count - g0 < G ? count - g0 : G;
         const size_t chains = gc * T;
-        FHE_TRY(run(c, KK_BRIDGE, st, [&] { return launch_bridge_init(d, x + g0 * ctw, y, gc, T, st); }));
-        for (int sq = 0; sq < squarings; sq++) FHE_TRY(mul_relin_impl(c, rlk, y, y, y, chains, ws2, st));
+        // First squaring, shared by the T chains of an input (kernels_conv.hip):
+        // the input's own square up to the key switching, then per chain the
+        // corrected components 0 and 1 plus the shared key-switching output.
+        const uint64_t *xg = x + g0 * ctw;
+        const size_t n = c->n, K = c->K, k = c->k;
+        uint64_t *E1 = (uint64_t *)ws2;
+        uint64_t *D1 = E1 + gc * 2 * K * n;
+        uint64_t *C21 = D1 + gc * 3 * K * n;
+        uint64_t *R1 = C21 + gc * k * n;
+        uint64_t *gam = R1 + gc * 2 * k * n;
+        FHE_TRY(run(c, KK_LIFT, st, [&] { return launch_lift(d, xg, xg, E1, 2, gc, st); }));
+        FHE_TRY(run(c, KK_SQUARE_TENSOR, st, [&] { return launch_square_tensor(d, xg, E1, D1, gc, st); }));
+        FHE_TRY(run(c, KK_SCALE, st, [&] { return launch_scale(d, D1, nullptr, C21, gc, st, 2, 1); }));
+        FHE_HIP(hipMemsetAsync(R1, 0, gc * 2 * k * n * sizeof(uint64_t), st));
+        FHE_TRY(run(c, KK_RELIN_FUSED, st, [&] { return launch_relin_fused(d, C21, rlk, R1, gc, st); }));
+        FHE_TRY(run(c, KK_BRIDGE, st, [&] { return launch_bridge_gamma(d, xg, E1, gam, chains, T, st); }));
+        FHE_TRY(run(c, KK_SCALE, st,
+                    [&] { return launch_scale_chain(d, D1, xg, E1, gam, R1, y, chains, T, st); }));
+        for (int sq = 1; sq < squarings; sq++) FHE_TRY(mul_relin_impl(c, rlk, y, y, y, chains, ws2, st));
         uint64_t *eqp = eq ? eq + g0 * T * ctw : nullptr;
         FHE_TRY(run(c, KK_BRIDGE, st, [&] {
             return launch_bridge_combine(d, y, bits + g0 * nbits * ctw, eqp, gc, T, (int)nbits, st);

@@ -70,7 +70,15 @@ hipError_t launch_relin_fused(const DevCtx &c, const uint64_t *C2, const uint64_
 hipError_t launch_lift(const DevCtx &c, const uint64_t *a, const uint64_t *b, uint64_t *E, int npoly,
                        size_t items, hipStream_t s);
 hipError_t launch_scale(const DevCtx &c, const uint64_t *Dt, uint64_t *out, uint64_t *C2,
-                        size_t items, hipStream_t s);
+                        size_t items, hipStream_t s, int comp0 = 0, int ncomp = 3);
+// Shared first squaring of the bridge chains (kernels_conv.hip, k_bridge_gamma
+// and k_scale_chain): per-chain constant-coefficient corrections, then the
+// chains' components 0 and 1 from the inputs' tensor plus key-switching output.
+hipError_t launch_bridge_gamma(const DevCtx &c, const uint64_t *x, const uint64_t *E, uint64_t *gam,
+                               size_t chains, int tcount, hipStream_t s);
+hipError_t launch_scale_chain(const DevCtx &c, const uint64_t *Dt, const uint64_t *x, const uint64_t *E,
+                              const uint64_t *gam, const uint64_t *R, uint64_t *y, size_t chains, int tcount,
+                              hipStream_t s);
 hipError_t launch_decrypt_scale(const DevCtx &c, const uint64_t *X, uint64_t *pt, size_t count,
                                 hipStream_t s);
 // op: 0 add, 1 sub, 2 neg (b unused)
@@ -91,9 +99,6 @@ hipError_t launch_key_b(const DevCtx &c, const uint64_t *prod, const uint64_t *e
 // ct[j] = (prod[0][j] + e[j][0] + Delta m_j, prod[1][j] + e[j][1]); prod [2][count][k][n]
 hipError_t launch_encrypt_finish(const DevCtx &c, const uint64_t *prod, const int32_t *e,
                                  const uint64_t *pt, uint64_t *ct, size_t count, hipStream_t s);
-// y[j*tcount + c] = x[j] - Delta*c (constant coefficient of c0)
-hipError_t launch_bridge_init(const DevCtx &c, const uint64_t *x, uint64_t *y, size_t count,
-                              int tcount, hipStream_t s);
 hipError_t launch_bridge_combine(const DevCtx &c, const uint64_t *y, uint64_t *bits, uint64_t *eq,
                                  size_t count, int tcount, int nbits, hipStream_t s);
 hipError_t launch_horner(const DevCtx &c, const uint64_t *bits, int nbits, uint64_t *out,

@@ -83,28 +83,14 @@ __device__ __forceinline__ uint64_t mrc_eval(const MrcConst &M, const uint64_t (
 
 // ---------------------------------------------------------------- lift ------
 
-// Extended rows of the inputs: for every coefficient of poly `blockIdx.y` of
-// item `blockIdx.z`, the centred lift x~ in (-q/2, q/2) written modulo each
-// P prime into E[item][poly][k + j]:
-//   x~ = sum_i y_i qhat_i - beta q,  y_i = [x_i qhat_i^-1]_{q_i},  beta = round(sum_i y_i / q_i).
-// EX: the basis sizes are exactly MK and MKP (loops without per-term branches).
-template <int MK, int MKP, bool EX>
-__global__ __launch_bounds__(256) void k_lift(DevCtx c, const uint64_t *__restrict__ a,
-                                              const uint64_t *__restrict__ b,
-                                              uint64_t *__restrict__ E, int npoly) {
-    const int n = c.n, k = EX ? MK : c.k, kp = EX ? MKP : c.kp, K = EX ? MK + MKP : c.K;
-    const int coef = blockIdx.x * 256 + threadIdx.x;
-    if (coef >= n) return;
-    const int poly = blockIdx.y;
-    const size_t item = blockIdx.z;
-    const uint64_t *src = poly < 2 ? a + (item * 2 + poly) * (size_t)k * n
-                                   : b + (item * 2 + poly - 2) * (size_t)k * n;
-    uint64_t *dst = E + ((item * npoly + poly) * K + k) * (size_t)n;
+// Centred lift of one coefficient given by its residues x in Q:
+//   x~ = sum_i y_i qhat_i - beta q,  y_i = [x_i qhat_i^-1]_{q_i},  beta = round(sum_i y_i / q_i),
+// in (-q/2, q/2); put(j, r) receives r = x~ mod p_j for every P prime.
+template <int MK, int MKP, bool EX, class Put>
+__device__ __forceinline__ void lift_coef(const DevCtx &c, const uint64_t (&x)[MK], Put put) {
+    const int k = EX ? MK : c.k, kp = EX ? MKP : c.kp;
     const ConvConst &cc = *c.cc;
-
-    uint64_t x[MK], y[MK];
-#pragma unroll
-    for (int i = 0; i < MK; i++) x[i] = i < k ? src[(size_t)i * n + coef] : 0;
+    uint64_t y[MK];
     double e = 0.0;
 #pragma unroll
     for (int i = 0; i < MK; i++) {
@@ -128,7 +114,7 @@ __global__ __launch_bounds__(256) void k_lift(DevCtx c, const uint64_t *__restri
                 for (int i = 0; i < MK; i++)
                     if (i < k) acc3_mac(acc, y[i], ldc(m + i));
                 acc3_mac(acc, beta, ldc(m + k));
-                dst[(size_t)j * n + coef] = acc_reduce_mont(acc3_value(acc), cc.p[j], cc.p_qinv[j], cc.p_one[j]);
+                put(j, acc_reduce_mont(acc3_value(acc), cc.p[j], cc.p_qinv[j], cc.p_one[j]));
             }
         }
     } else {
@@ -142,10 +128,32 @@ __global__ __launch_bounds__(256) void k_lift(DevCtx c, const uint64_t *__restri
             if (j < kp) {
                 uint64_t r = mrc_eval<MK>(M, dg, j);
                 if (gt) r = sub_mod(r, M.M_mod_t[j], cc.p[j]);
-                dst[(size_t)j * n + coef] = r;
+                put(j, r);
             }
         }
     }
+}
+
+// Extended rows of the inputs: for every coefficient of poly `blockIdx.y` of
+// item `blockIdx.z`, the centred lift x~ in (-q/2, q/2) written modulo each
+// P prime into E[item][poly][k + j].
+// EX: the basis sizes are exactly MK and MKP (loops without per-term branches).
+template <int MK, int MKP, bool EX>
+__global__ __launch_bounds__(256) void k_lift(DevCtx c, const uint64_t *__restrict__ a,
+                                              const uint64_t *__restrict__ b,
+                                              uint64_t *__restrict__ E, int npoly) {
+    const int n = c.n, k = EX ? MK : c.k, K = EX ? MK + MKP : c.K;
+    const int coef = blockIdx.x * 256 + threadIdx.x;
+    if (coef >= n) return;
+    const int poly = blockIdx.y;
+    const size_t item = blockIdx.z;
+    const uint64_t *src = poly < 2 ? a + (item * 2 + poly) * (size_t)k * n
+                                   : b + (item * 2 + poly - 2) * (size_t)k * n;
+    uint64_t *dst = E + ((item * npoly + poly) * K + k) * (size_t)n;
+    uint64_t x[MK];
+#pragma unroll
+    for (int i = 0; i < MK; i++) x[i] = i < k ? src[(size_t)i * n + coef] : 0;
+    lift_coef<MK, MKP, EX>(c, x, [&](int j, uint64_t r) { dst[(size_t)j * n + coef] = r; });
 }
 
 // ------------------------------------------------------- scale and round ----
@@ -155,25 +163,13 @@ __global__ __launch_bounds__(256) void k_lift(DevCtx c, const uint64_t *__restri
 // Step 1 (in P):   C_{p_j} = [t q^-1 D_{p_j} + h q^-1 + v - sum_i y_i q_i^-1]_{p_j},
 //                  y_i = [(t D_{q_i} + h) qhat_i^-1]_{q_i}, v = floor(sum_i y_i / q_i).
 // Step 2 (P -> Q): centred conversion of C, which satisfies |C| < P/2.
-template <int MK, int MKP, bool EX>
-__global__ __launch_bounds__(256) void k_scale(DevCtx c, const uint64_t *__restrict__ Dt,
-                                               uint64_t *__restrict__ out,
-                                               uint64_t *__restrict__ C2) {
-    const int n = c.n, k = EX ? MK : c.k, kp = EX ? MKP : c.kp, K = EX ? MK + MKP : c.K;
-    const int coef = blockIdx.x * 256 + threadIdx.x;
-    if (coef >= n) return;
-    const int comp = blockIdx.y;
-    const size_t item = blockIdx.z;
-    const uint64_t *src = Dt + (item * 3 + comp) * (size_t)K * n;
-    uint64_t *dst = comp < 2 ? out + (item * 2 + comp) * (size_t)k * n : C2 + item * (size_t)k * n;
+// One coefficient of round(t D / q): D given by its residues dq in Q and dp
+// in P (canonical); put(i, r) receives r = C mod q_i.
+template <int MK, int MKP, bool EX, class Put>
+__device__ __forceinline__ void scale_coef(const DevCtx &c, const uint64_t (&dq)[MK], const uint64_t (&dp)[MKP],
+                                           Put put) {
+    const int k = EX ? MK : c.k, kp = EX ? MKP : c.kp;
     const ConvConst &cc = *c.cc;
-
-    uint64_t dq[MK], dp[MKP];
-#pragma unroll
-    for (int i = 0; i < MK; i++) dq[i] = i < k ? src[(size_t)i * n + coef] : 0;
-#pragma unroll
-    for (int j = 0; j < MKP; j++) dp[j] = j < kp ? src[(size_t)(k + j) * n + coef] : 0;
-
     uint64_t y[MK];
     double e = 0.0;
 #pragma unroll
@@ -222,7 +218,7 @@ __global__ __launch_bounds__(256) void k_scale(DevCtx c, const uint64_t *__restr
                 for (int j = 0; j < MKP; j++)
                     if (j < kp) acc3_mac(acc, z[j], ldc(m + j));
                 acc3_mac(acc, beta, ldc(m + kp));
-                dst[(size_t)i * n + coef] = acc_reduce_mont(acc3_value(acc), cc.q[i], cc.q_qinv[i], cc.q_one[i]);
+                put(i, acc_reduce_mont(acc3_value(acc), cc.q[i], cc.q_qinv[i], cc.q_one[i]));
             }
         }
         return;
@@ -257,9 +253,150 @@ __global__ __launch_bounds__(256) void k_scale(DevCtx c, const uint64_t *__restr
         if (i < k) {
             uint64_t r = mrc_eval<MKP>(MP, dgp, i);
             if (gt) r = sub_mod(r, MP.M_mod_t[i], cc.q[i]);
-            dst[(size_t)i * n + coef] = r;
+            put(i, r);
         }
     }
+}
+
+
+// Component comp0 + blockIdx.y of item blockIdx.z: components 0 and 1 go to
+// out (a ciphertext), component 2 to C2.
+template <int MK, int MKP, bool EX>
+__global__ __launch_bounds__(256) void k_scale(DevCtx c, const uint64_t *__restrict__ Dt,
+                                               uint64_t *__restrict__ out,
+                                               uint64_t *__restrict__ C2, int comp0) {
+    const int n = c.n, k = EX ? MK : c.k, kp = EX ? MKP : c.kp, K = EX ? MK + MKP : c.K;
+    const int coef = blockIdx.x * 256 + threadIdx.x;
+    if (coef >= n) return;
+    const int comp = comp0 + (int)blockIdx.y;
+    const size_t item = blockIdx.z;
+    const uint64_t *src = Dt + (item * 3 + comp) * (size_t)K * n;
+    uint64_t *dst = comp < 2 ? out + (item * 2 + comp) * (size_t)k * n : C2 + item * (size_t)k * n;
+    uint64_t dq[MK], dp[MKP];
+#pragma unroll
+    for (int i = 0; i < MK; i++) dq[i] = i < k ? src[(size_t)i * n + coef] : 0;
+#pragma unroll
+    for (int j = 0; j < MKP; j++) dp[j] = j < kp ? src[(size_t)(k + j) * n + coef] : 0;
+    scale_coef<MK, MKP, EX>(c, dq, dp, [&](int i, uint64_t r) { dst[(size_t)i * n + coef] = r; });
+}
+
+// First squaring of the bridge chains, shared work.  Chain c of input j is
+// y_c = x_j - (Delta c, 0); its centred lift differs from that of x_j only by
+// an integer gamma_c in the constant coefficient of the first polynomial, so
+// its exact tensor is
+//   D0(y_c) = D0(x_j) + 2 gamma_c x~0 + gamma_c^2,  D1(y_c) = D1(x_j) + 2 gamma_c x~1,
+//   D2(y_c) = D2(x_j)
+// (x~ the centred lift of x_j over Q and P).  k_scale_chain rebuilds D0, D1 of
+// the chain from x_j's tensor and rounds them; D2, and with it the key
+// switching, is computed once per input.
+//
+// gamma table per chain and prime l of Q then P: [2 gamma 2^64 mod p_l,
+// gamma^2 mod p_l] (the first a Montgomery multiplier).
+
+// (hi 2^64 + lo) mod p for p < 2^62, by 64 doubling steps (setup only).
+__device__ uint64_t mod128_slow(uint64_t hi, uint64_t lo, uint64_t p) {
+    uint64_t r = hi % p;
+    for (int b = 63; b >= 0; b--) {
+        r = (r << 1) | ((lo >> b) & 1u);
+        if (r >= p) r -= p;
+    }
+    return r;
+}
+
+__device__ uint64_t mulmod_slow(uint64_t a, uint64_t b, uint64_t p) {
+    uint64_t lo, hi;
+    mul128(a, b, lo, hi);
+    return mod128_slow(hi, lo, p);
+}
+
+// One thread per chain (input j = chain / tcount, c = chain % tcount).  x: the
+// inputs [count][2][k][n]; E: their lift [count][2][K][n] (P rows).
+template <int MK, int MKP, bool EX>
+__global__ __launch_bounds__(64) void k_bridge_gamma(DevCtx c, const uint64_t *__restrict__ x,
+                                                     const uint64_t *__restrict__ E,
+                                                     uint64_t *__restrict__ gam, size_t chains, int tcount) {
+    const size_t chain = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    if (chain >= chains) return;
+    const int n = c.n, k = EX ? MK : c.k, kp = EX ? MKP : c.kp, K = EX ? MK + MKP : c.K;
+    const size_t j = chain / tcount;
+    const uint64_t cv = chain % tcount;
+    const ConvConst &cc = *c.cc;
+    uint64_t *g = gam + chain * 2 * (size_t)K;
+    uint64_t x0[MK];
+#pragma unroll
+    for (int i = 0; i < MK; i++) {
+        x0[i] = 0;
+        if (i < k) {
+            const uint64_t q = cc.q[i];
+            const uint64_t dc = mul_shoup(cv % q, cc.delta_q[i], cc.delta_qs[i], q);
+            x0[i] = sub_mod(x[(j * 2) * (size_t)k * n + (size_t)i * n], dc, q);
+            const uint64_t gm = dc ? q - dc : 0;  // gamma mod q_i = -Delta c
+            const uint64_t r1 = (uint64_t)0 - cc.q_one[i] * q;  // 2^64 mod q (< q)
+            g[2 * i] = mulmod_slow(add_mod(gm, gm, q), r1, q);
+            g[2 * i + 1] = mulmod_slow(gm, gm, q);
+        }
+    }
+    lift_coef<MK, MKP, EX>(c, x0, [&](int jp, uint64_t r) {
+        const uint64_t p = cc.p[jp];
+        const uint64_t gm = sub_mod(r, E[(j * 2) * (size_t)K * n + (size_t)(k + jp) * n], p);
+        const uint64_t r1 = (uint64_t)0 - cc.p_one[jp] * p;
+        g[2 * (k + jp)] = mulmod_slow(add_mod(gm, gm, p), r1, p);
+        g[2 * (k + jp) + 1] = mulmod_slow(gm, gm, p);
+    });
+    (void)kp;
+}
+
+// Components 0 and 1 (blockIdx.y) of the first squaring of chain blockIdx.z:
+// D rebuilt from the input's tensor Dt [count][3][K][n], its lift x~ (Q rows
+// from x, P rows from E) and the gamma table; the rounded value plus the input's
+// key-switching output R [count][2][k][n] is the chain's ciphertext in y.
+template <int MK, int MKP, bool EX>
+__global__ __launch_bounds__(256) void k_scale_chain(DevCtx c, const uint64_t *__restrict__ Dt,
+                                                     const uint64_t *__restrict__ x,
+                                                     const uint64_t *__restrict__ E,
+                                                     const uint64_t *__restrict__ gam,
+                                                     const uint64_t *__restrict__ R,
+                                                     uint64_t *__restrict__ y, int tcount) {
+    const int n = c.n, k = EX ? MK : c.k, kp = EX ? MKP : c.kp, K = EX ? MK + MKP : c.K;
+    const int coef = blockIdx.x * 256 + threadIdx.x;
+    if (coef >= n) return;
+    const int comp = blockIdx.y;
+    const size_t chain = blockIdx.z, j = chain / tcount;
+    const ConvConst &cc = *c.cc;
+    const uint64_t *src = Dt + (j * 3 + comp) * (size_t)K * n;
+    const uint64_t *xq = x + (j * 2 + comp) * (size_t)k * n;
+    const uint64_t *xp = E + (j * 2 + comp) * (size_t)K * n;
+    const uint64_t *g = gam + chain * 2 * (size_t)K;
+    const bool sq = comp == 0 && coef == 0;
+    uint64_t dq[MK], dp[MKP];
+#pragma unroll
+    for (int i = 0; i < MK; i++) {
+        dq[i] = 0;
+        if (i < k) {
+            const uint64_t q = cc.q[i];
+            uint64_t v = src[(size_t)i * n + coef] + mont_mul_lazy(xq[(size_t)i * n + coef], ldc(g + 2 * i), q,
+                                                                   cc.q_qinv[i]);
+            if (sq) v += ldc(g + 2 * i + 1);
+            dq[i] = csub(csub(v, q << 1), q);  // < 4q before
+        }
+    }
+#pragma unroll
+    for (int jp = 0; jp < MKP; jp++) {
+        dp[jp] = 0;
+        if (jp < kp) {
+            const uint64_t p = cc.p[jp];
+            const int l = k + jp;
+            uint64_t v = src[(size_t)l * n + coef] + mont_mul_lazy(xp[(size_t)l * n + coef], ldc(g + 2 * l), p,
+                                                                   cc.p_qinv[jp]);
+            if (sq) v += ldc(g + 2 * l + 1);
+            dp[jp] = csub(csub(v, p << 1), p);
+        }
+    }
+    const uint64_t *r = R + (j * 2 + comp) * (size_t)k * n;
+    uint64_t *dst = y + (chain * 2 + comp) * (size_t)k * n;
+    scale_coef<MK, MKP, EX>(c, dq, dp, [&](int i, uint64_t v) {
+        dst[(size_t)i * n + coef] = add_mod(v, r[(size_t)i * n + coef], cc.q[i]);
+    });
 }
 
 // -------------------------------------------------------- decryption ------
@@ -389,26 +526,6 @@ __global__ void k_encrypt_finish(DevCtx c, const uint64_t *__restrict__ prod,
     }
 }
 
-// y[j*T + c] = x[j] with Delta*c subtracted from c0's constant coefficient.
-__global__ void k_bridge_init(DevCtx c, const uint64_t *__restrict__ x, uint64_t *__restrict__ y,
-                              size_t count, int tcount) {
-    const size_t n = c.n, k = c.k, ctw = 2 * k * n;
-    const size_t total = count * tcount * ctw;
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total;
-         i += (size_t)gridDim.x * blockDim.x) {
-        const size_t w = i % ctw, chain = i / ctw;
-        const size_t j = chain / tcount, cc = chain % tcount;
-        uint64_t v = x[j * ctw + w];
-        const size_t coef = w % n, row = w / n;
-        if (coef == 0 && row < k) {
-            const uint64_t q = c.pc[row].q;
-            const uint64_t dc = mul_shoup(cc % q, c.cc->delta_q[row], c.cc->delta_qs[row], q);
-            v = sub_mod(v, dc, q);
-        }
-        y[i] = v;
-    }
-}
-
 // eq_c = Delta [coefficient 0 of c0] - y_c;  bits_b = sum_{c in [1,T), bit b of c} eq_c.
 constexpr int FHE_MAXNB = 20;
 __global__ __launch_bounds__(256) void k_bridge_combine(DevCtx c, const uint64_t *__restrict__ y,
@@ -501,9 +618,30 @@ struct LiftL {
 template <int MK, int MKP, bool EX>
 struct ScaleL {
     static hipError_t run(const DevCtx &c, const uint64_t *Dt, uint64_t *out, uint64_t *C2,
-                          size_t items, hipStream_t s) {
-        dim3 grid((c.n + 255) / 256, 3, (unsigned)items);
-        hipLaunchKernelGGL((k_scale<MK, MKP, EX>), grid, dim3(256), 0, s, c, Dt, out, C2);
+                          size_t items, int comp0, int ncomp, hipStream_t s) {
+        dim3 grid((c.n + 255) / 256, ncomp, (unsigned)items);
+        hipLaunchKernelGGL((k_scale<MK, MKP, EX>), grid, dim3(256), 0, s, c, Dt, out, C2, comp0);
+        return hipGetLastError();
+    }
+};
+
+template <int MK, int MKP, bool EX>
+struct GammaL {
+    static hipError_t run(const DevCtx &c, const uint64_t *x, const uint64_t *E, uint64_t *gam,
+                          size_t chains, int tcount, hipStream_t s) {
+        hipLaunchKernelGGL((k_bridge_gamma<MK, MKP, EX>), dim3((unsigned)((chains + 63) / 64)), dim3(64), 0, s,
+                           c, x, E, gam, chains, tcount);
+        return hipGetLastError();
+    }
+};
+
+template <int MK, int MKP, bool EX>
+struct ScaleChainL {
+    static hipError_t run(const DevCtx &c, const uint64_t *Dt, const uint64_t *x, const uint64_t *E,
+                          const uint64_t *gam, const uint64_t *R, uint64_t *y, size_t chains, int tcount,
+                          hipStream_t s) {
+        dim3 grid((c.n + 255) / 256, 2, (unsigned)chains);
+        hipLaunchKernelGGL((k_scale_chain<MK, MKP, EX>), grid, dim3(256), 0, s, c, Dt, x, E, gam, R, y, tcount);
         return hipGetLastError();
     }
 };
@@ -517,9 +655,22 @@ hipError_t launch_lift(const DevCtx &c, const uint64_t *a, const uint64_t *b, ui
 }
 
 hipError_t launch_scale(const DevCtx &c, const uint64_t *Dt, uint64_t *out, uint64_t *C2,
-                        size_t items, hipStream_t s) {
+                        size_t items, hipStream_t s, int comp0, int ncomp) {
     if (items == 0) return hipSuccess;
-    return by_class<ScaleL>(c.k, c.kp, c, Dt, out, C2, items, s);
+    return by_class<ScaleL>(c.k, c.kp, c, Dt, out, C2, items, comp0, ncomp, s);
+}
+
+hipError_t launch_bridge_gamma(const DevCtx &c, const uint64_t *x, const uint64_t *E, uint64_t *gam,
+                               size_t chains, int tcount, hipStream_t s) {
+    if (chains == 0) return hipSuccess;
+    return by_class<GammaL>(c.k, c.kp, c, x, E, gam, chains, tcount, s);
+}
+
+hipError_t launch_scale_chain(const DevCtx &c, const uint64_t *Dt, const uint64_t *x, const uint64_t *E,
+                              const uint64_t *gam, const uint64_t *R, uint64_t *y, size_t chains, int tcount,
+                              hipStream_t s) {
+    if (chains == 0) return hipSuccess;
+    return by_class<ScaleChainL>(c.k, c.kp, c, Dt, x, E, gam, R, y, chains, tcount, s);
 }
 
 hipError_t launch_decrypt_scale(const DevCtx &c, const uint64_t *X, uint64_t *pt, size_t count,
@@ -579,14 +730,6 @@ hipError_t launch_encrypt_finish(const DevCtx &c, const uint64_t *prod, const in
     if (words == 0) return hipSuccess;
     hipLaunchKernelGGL(k_encrypt_finish, dim3(grid_for(words)), dim3(256), 0, s, c, prod, e, pt, ct,
                        count);
-    return hipGetLastError();
-}
-
-hipError_t launch_bridge_init(const DevCtx &c, const uint64_t *x, uint64_t *y, size_t count,
-                              int tcount, hipStream_t s) {
-    const size_t words = count * tcount * 2 * c.k * (size_t)c.n;
-    if (words == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_bridge_init, dim3(grid_for(words)), dim3(256), 0, s, c, x, y, count, tcount);
     return hipGetLastError();
 }
 
