@@ -14,7 +14,8 @@ Prints one JSON line with the metric (bridge conversions per second), the
 executed ciphertext mul+relin per second, per-step p50/p99, the plain-vs-batched mul+relin
 comparison at n = 16384 (one pair per call vs one batched call, for several
 batch sizes), the transform kernel alone at n = 4096 / 8192 / 16384, products
-at n = 4096, the roofline of the dominant kernel (timed live with HIP events on
+at n = 4096, 1024 products of mixed ring sizes (per-size calls vs one
+multi-context call), depth-4 squaring chains (eager vs HIP graph), the roofline of the dominant kernel (timed live with HIP events on
 the launch stream), and the CPU oracle timed on a bounded sample of the same
 work.
 """
@@ -224,6 +225,9 @@ def main():
         out["ntt_rows"] = ntt_rows_leg(fhe, inputs, torch)
         out["c0_n4096"] = c0_leg(fhe, inputs, torch)
         print("[bench] transform rows and n=4096 products done", file=sys.stderr, flush=True)
+        out["mixed_sizes"] = mixed_leg(fhe, inputs, torch)
+        out["square_chain_n16384"] = chain_leg(fhe, inputs, torch)
+        print("[bench] mixed sizes and squaring chains done", file=sys.stderr, flush=True)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inputs)
@@ -347,6 +351,64 @@ def c0_leg(fhe, inputs, torch, reps=5):
     torch.cuda.synchronize()
     return {"n": n, "k": len(qs), "t": cfg["t"], "count": count,
             "mul_relin_per_s": count * reps / (time.perf_counter() - t0)}
+
+
+def mixed_leg(fhe, inputs, torch, reps=3):
+    """1024 ciphertext pairs of mixed ring sizes (342 at n=4096 with three 36-bit
+    primes, 341 at n=8192 with five 43-bit, 341 at n=16384 with eight 55-bit;
+    t = 65537): three per-size calls one after the other against one
+    fhe_mul_relin_multi call whose parts overlap on the device."""
+    parts = []
+    for key, count in (("bfv_n4096", 342), ("bfv_n8192", 341), ("bfv_n16384", 341)):
+        cfg = inputs.CONFIGS[key]
+        n, qs = cfg["n"], cfg["q"]
+        ctx = fhe.Context(n, qs, cfg["t"], cfg["encoding"])
+        km = inputs.key_material(n, qs, 5)
+        _, rlk = ctx.keygen(km["s"], km["pk_a"], km["pk_e"], km["rlk_a"], km["rlk_e"])
+        a = fhe.from_numpy_u64(inputs.uniform_ciphertexts(n, qs, count, 5, "a"), "cuda")
+        b = fhe.from_numpy_u64(inputs.uniform_ciphertexts(n, qs, count, 5, "b"), "cuda")
+        parts.append((ctx, rlk, a, b, ctx.empty_ct(count)))
+    total = sum(p[2].shape[0] for p in parts)
+    for ctx, rlk, a, b, out in parts:
+        ctx.mul_relin(rlk, a, b, out=out)
+    fhe.mul_relin_multi(parts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for ctx, rlk, a, b, out in parts:
+            ctx.mul_relin(rlk, a, b, out=out)
+    torch.cuda.synchronize()
+    seq = total * reps / (time.perf_counter() - t0)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fhe.mul_relin_multi(parts)
+    torch.cuda.synchronize()
+    multi = total * reps / (time.perf_counter() - t0)
+    return {"pairs": {"4096": 342, "8192": 341, "16384": 341}, "t": 65537,
+            "sequential_mul_relin_per_s": seq, "multi_mul_relin_per_s": multi}
+
+
+def chain_leg(fhe, inputs, torch, count=64, depth=4, reps=3):
+    """Depth-4 squaring chains at n = 16384 (eight 55-bit primes, t = 65537) on
+    64 ciphertexts: four eager mul_relin calls against the replayed HIP graph of
+    fhe_square_chain."""
+    cfg = inputs.CONFIGS["bfv_n16384"]
+    n, qs = cfg["n"], cfg["q"]
+    ctx = fhe.Context(n, qs, cfg["t"], cfg["encoding"])
+    km = inputs.key_material(n, qs, 6)
+    _, rlk = ctx.keygen(km["s"], km["pk_a"], km["pk_e"], km["rlk_a"], km["rlk_e"])
+    x = fhe.from_numpy_u64(inputs.uniform_ciphertexts(n, qs, count, 6, "x"), "cuda")
+    res = {}
+    for name, graph in (("eager", False), ("graph", True)):
+        ctx.square_chain(rlk, x, depth, graph=graph)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ctx.square_chain(rlk, x, depth, graph=graph)
+        torch.cuda.synchronize()
+        res[f"{name}_mul_relin_per_s"] = count * depth * reps / (time.perf_counter() - t0)
+    res.update({"n": n, "count": count, "depth": depth})
+    return res
 
 
 def cpu_baseline(inputs):

@@ -176,6 +176,36 @@ fhe_status fhe_mul_relin(fhe_ctx *ctx, const uint64_t *rlk_dev, const uint64_t *
                          const uint64_t *b, uint64_t *out, size_t count, void *ws,
                          size_t ws_bytes, hipStream_t stream);
 
+/* Several product batches, possibly of different contexts (ring sizes,
+ * primes), in one call: part i computes what fhe_mul_relin(parts[i].ctx, ...)
+ * computes.  Each part runs on its context's own stream (created on first use,
+ * default priority), which first waits for the work already queued on `stream`;
+ * `stream` then waits for all parts, so parts of different contexts overlap on
+ * the device.  The call returns once everything is enqueued.  Parts must not
+ * share outputs or workspaces (FHE_EINVAL, checked before anything is
+ * enqueued); parts of one context run one after the other.  All contexts must
+ * be on the current device.  Arguments as for fhe_mul_relin (each ws sized for
+ * its part). */
+typedef struct {
+    fhe_ctx *ctx;
+    const uint64_t *rlk_dev, *a, *b;
+    uint64_t *out;
+    size_t count;
+    void *ws;
+    size_t ws_bytes;
+} fhe_mul_part;
+fhe_status fhe_mul_relin_multi(const fhe_mul_part *parts, size_t nparts, hipStream_t stream);
+
+/* Repeated squaring in place: x[j] <- x[j]^(2^depth), i.e. depth calls of
+ * fhe_mul_relin(x, x, x) (same words), for j < count.  graph != 0 records the
+ * launch sequence once into a HIP graph kept by the context, keyed by
+ * (rlk_dev, x, ws, count, depth), and replays it on later calls with the same
+ * key (the graph holds those addresses: the buffers must stay allocated while
+ * the context lives).  Per-launch timing or validation makes the call run
+ * eagerly.  ws: FHE_OP_SQUARE_RELIN bytes for count. */
+fhe_status fhe_square_chain(fhe_ctx *ctx, const uint64_t *rlk_dev, uint64_t *x, uint32_t depth,
+                            size_t count, void *ws, size_t ws_bytes, int graph, hipStream_t stream);
+
 /* The paper's SecureMod -> SecureUint conversion for prime t (Section 3.2.3):
  * for each input x[j] (device [count][2][k][n]) and each c in [0, t):
  *   y = x - c (sub_plain_const), y = y^(t-1) by repeated squaring

@@ -197,6 +197,18 @@ struct fhe_ctx {
     std::vector<hipEvent_t> free_events;
     double total_ms[KK_COUNT] = {};
     uint64_t launches[KK_COUNT] = {};
+    // own stream (default priority) and fork/join events for fhe_mul_relin_multi,
+    // and the graphs of fhe_square_chain; created on first use
+    hipStream_t aux = nullptr;
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+    struct ChainGraph {
+        const void *rlk, *x, *ws;
+        size_t count;
+        uint32_t depth;
+        hipGraph_t g;
+        hipGraphExec_t ge;
+    };
+    std::vector<ChainGraph> graphs;
 };
 
 namespace {
@@ -328,6 +340,14 @@ fhe_status alloc_copy(void **dst, const void *src, size_t bytes) {
 }
 
 void release(fhe_ctx *c) {
+    for (auto &cg : c->graphs) {
+        hipGraphExecDestroy(cg.ge);
+        hipGraphDestroy(cg.g);
+    }
+    c->graphs.clear();
+    if (c->fork_ev) hipEventDestroy(c->fork_ev);
+    if (c->join_ev) hipEventDestroy(c->join_ev);
+    if (c->aux) hipStreamDestroy(c->aux);
     void *ptrs[] = {c->d_pc, c->d_tw, c->d_itw, c->d_cc, c->d_mrc_q, c->d_mrc_p, c->d_counters};
     for (void *p : ptrs)
         if (p) hipFree(p);
@@ -894,6 +914,104 @@ fhe_status fhe_mul_relin(fhe_ctx *c, const uint64_t *rlk, const uint64_t *a, con
     FHE_TRY(check_canonical(c, a, count * 2 * c->k, c->k, 0, st));
     if (!square) FHE_TRY(check_canonical(c, b, count * 2 * c->k, c->k, 0, st));
     return mul_relin_impl(c, rlk, a, b, out, count, ws, st);
+}
+
+static fhe_status ensure_aux(fhe_ctx *c) {
+    if (c->aux) return FHE_OK;
+    if (hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess) {
+        c->aux = nullptr;
+        return FHE_EDEVICE;
+    }
+    if (hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming) != hipSuccess)
+        return FHE_EDEVICE;
+    return FHE_OK;
+}
+
+static fhe_status mul_args_ok(fhe_ctx *c, const uint64_t *rlk, const uint64_t *a, const uint64_t *b,
+                              uint64_t *out, size_t count, void *ws, size_t ws_bytes) {
+    if (!c) return FHE_EINVAL;
+    if (count == 0) return FHE_OK;
+    if (!rlk || !a || !b || !out || !ws) return FHE_EINVAL;
+    const size_t bytes = count * ct_words(c) * 8;
+    if (out != a && overlaps(out, a, bytes)) return FHE_EINVAL;
+    if (out != b && overlaps(out, b, bytes)) return FHE_EINVAL;
+    if (ws_bytes < fhe_workspace_bytes(c, a == b ? FHE_OP_SQUARE_RELIN : FHE_OP_MUL_RELIN, count))
+        return FHE_EWORKSPACE;
+    return FHE_OK;
+}
+
+fhe_status fhe_mul_relin_multi(const fhe_mul_part *parts, size_t nparts, hipStream_t st) {
+    if (nparts == 0) return FHE_OK;
+    if (!parts) return FHE_EINVAL;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return FHE_EDEVICE;
+    for (size_t i = 0; i < nparts; i++) {
+        const fhe_mul_part &p = parts[i];
+        FHE_TRY(mul_args_ok(p.ctx, p.rlk_dev, p.a, p.b, p.out, p.count, p.ws, p.ws_bytes));
+        if (p.ctx->device != dev) return FHE_EINVAL;
+        for (size_t j = 0; j < i; j++) {
+            const fhe_mul_part &o = parts[j];
+            if (p.count && o.count &&
+                (overlaps2(p.out, p.count * ct_words(p.ctx) * 8, o.out, o.count * ct_words(o.ctx) * 8) ||
+                 (p.ws == o.ws)))
+                return FHE_EINVAL;
+        }
+        FHE_TRY(ensure_aux(p.ctx));
+    }
+    hipEvent_t fork = parts[0].ctx->fork_ev;
+    FHE_HIP(hipEventRecord(fork, st));
+    for (size_t i = 0; i < nparts; i++) {
+        const fhe_mul_part &p = parts[i];
+        if (p.count == 0) continue;
+        fhe_ctx *c = p.ctx;
+        FHE_HIP(hipStreamWaitEvent(c->aux, fork, 0));
+        FHE_TRY(check_canonical(c, p.a, p.count * 2 * c->k, c->k, 0, c->aux));
+        if (p.a != p.b) FHE_TRY(check_canonical(c, p.b, p.count * 2 * c->k, c->k, 0, c->aux));
+        FHE_TRY(mul_relin_impl(c, p.rlk_dev, p.a, p.b, p.out, p.count, p.ws, c->aux));
+        FHE_HIP(hipEventRecord(c->join_ev, c->aux));
+    }
+    for (size_t i = 0; i < nparts; i++)
+        if (parts[i].count) FHE_HIP(hipStreamWaitEvent(st, parts[i].ctx->join_ev, 0));
+    return FHE_OK;
+}
+
+fhe_status fhe_square_chain(fhe_ctx *c, const uint64_t *rlk, uint64_t *x, uint32_t depth, size_t count,
+                            void *ws, size_t ws_bytes, int graph, hipStream_t st) {
+    FHE_TRY(mul_args_ok(c, rlk, x, x, x, count, ws, ws_bytes));
+    if (count == 0 || depth == 0) return FHE_OK;
+    FHE_TRY(check_canonical(c, x, count * 2 * c->k, c->k, 0, st));
+    // eager when not asked for a graph, and when validation (memsets) or
+    // per-launch timing (events) is on
+    if (!graph || c->validate || c->timing) {
+        for (uint32_t d = 0; d < depth; d++) FHE_TRY(mul_relin_impl(c, rlk, x, x, x, count, ws, st));
+        return FHE_OK;
+    }
+    for (auto &cg : c->graphs)
+        if (cg.rlk == rlk && cg.x == x && cg.ws == ws && cg.count == count && cg.depth == depth) {
+            FHE_HIP(hipGraphLaunch(cg.ge, st));
+            return FHE_OK;
+        }
+    // record the launches on the context's own stream (capture executes
+    // nothing), then run the graph on the caller's stream
+    FHE_TRY(ensure_aux(c));
+    FHE_HIP(hipStreamBeginCapture(c->aux, hipStreamCaptureModeRelaxed));
+    fhe_status rec = FHE_OK;
+    for (uint32_t d = 0; d < depth && rec == FHE_OK; d++) rec = mul_relin_impl(c, rlk, x, x, x, count, ws, c->aux);
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(c->aux, &g);
+    if (rec != FHE_OK || ec != hipSuccess || !g) {
+        if (g) hipGraphDestroy(g);
+        return rec != FHE_OK ? rec : FHE_EDEVICE;
+    }
+    hipGraphExec_t ge = nullptr;
+    if (hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) != hipSuccess) {
+        hipGraphDestroy(g);
+        return FHE_EDEVICE;
+    }
+    c->graphs.push_back({rlk, x, ws, count, depth, g, ge});
+    FHE_HIP(hipGraphLaunch(ge, st));
+    return FHE_OK;
 }
 
 fhe_status fhe_bridge_to_bits(fhe_ctx *c, const uint64_t *rlk, const uint64_t *x, uint32_t nbits,

@@ -35,6 +35,13 @@ class _Params(ctypes.Structure):
                 ("q", ctypes.POINTER(ctypes.c_uint64)), ("encoding", ctypes.c_uint32)]
 
 
+class MulPart(ctypes.Structure):
+    """One part of fhe_mul_relin_multi (include/fhe.h)."""
+    _fields_ = [("ctx", ctypes.c_void_p), ("rlk_dev", ctypes.c_void_p), ("a", ctypes.c_void_p),
+                ("b", ctypes.c_void_p), ("out", ctypes.c_void_p), ("count", ctypes.c_size_t),
+                ("ws", ctypes.c_void_p), ("ws_bytes", ctypes.c_size_t)]
+
+
 _lib = None
 
 # (name, restype, argtypes); c_void_p stands for pointers and the stream.
@@ -60,6 +67,8 @@ _SIGS = [
     ("fhe_add_plain_const", _I, [_P, _P, _U64, _P, _Z, _P]),
     ("fhe_sub_plain_const", _I, [_P, _P, _U64, _P, _Z, _P]),
     ("fhe_mul_relin", _I, [_P, _P, _P, _P, _P, _Z, _P, _Z, _P]),
+    ("fhe_mul_relin_multi", _I, [ctypes.POINTER(MulPart), _Z, _P]),
+    ("fhe_square_chain", _I, [_P, _P, _P, _U32, _Z, _P, _Z, _I, _P]),
     ("fhe_bridge_to_bits", _I, [_P, _P, _P, _U32, _P, _P, _Z, _P, _Z, _P]),
     ("fhe_bits_to_mod", _I, [_P, _P, _U32, _P, _Z, _P]),
     ("fhe_ntt", _I, [_P, _I, _P, _Z, _P]),
@@ -272,6 +281,22 @@ class Context:
                                    ws.numel(), _stream()), "fhe_mul_relin")
         return out
 
+    def square_chain(self, rlk, x, depth: int, graph: bool = False):
+        """x <- x^(2^depth) in place (device [count][2][k][n]); graph: record
+        the launches once into a HIP graph and replay it on later calls with
+        the same buffers (the workspace is kept per (count, depth) for that)."""
+        import torch
+        count = x.shape[0]
+        key = ("chain", count, depth)
+        need = lib().fhe_workspace_bytes(self._h, OP_SQUARE_RELIN, count)
+        ws = self._ws.get(key)
+        if ws is None or ws.numel() < need:
+            ws = torch.empty(max(need, 8), dtype=torch.uint8, device=self.device)
+            self._ws[key] = ws
+        _check(lib().fhe_square_chain(self._h, _dptr(rlk), _dptr(x), depth, count, _dptr(ws), ws.numel(),
+                                      1 if graph else 0, _stream()), "fhe_square_chain")
+        return x
+
     def bridge_to_bits(self, rlk, x, nbits: int, with_eq: bool = False):
         import torch
         count = x.shape[0]
@@ -317,3 +342,23 @@ class Context:
         v = ctypes.c_uint64()
         _check(lib().fhe_fallback_count(self._h, ctypes.byref(v)), "fhe_fallback_count")
         return v.value
+
+
+def mul_relin_multi(parts):
+    """parts: list of (Context, rlk, a, b, out) with device tensors; every part
+    gets its own workspace.  One fhe_mul_relin_multi call on the current
+    stream; returns the list of outputs.  The workspaces are released to
+    torch's allocator on return: the current stream waits for every part, and
+    the allocator hands a freed block only to later work on that stream."""
+    import torch
+    arr = (MulPart * len(parts))()
+    keep = []
+    for i, (ctx, rlk, a, b, out) in enumerate(parts):
+        count = a.shape[0]
+        op = OP_SQUARE_RELIN if a.data_ptr() == b.data_ptr() else OP_MUL_RELIN
+        need = lib().fhe_workspace_bytes(ctx._h, op, count)
+        ws = torch.empty(max(need, 8), dtype=torch.uint8, device=ctx.device)
+        keep.append(ws)
+        arr[i] = MulPart(ctx._h, _dptr(rlk), _dptr(a), _dptr(b), _dptr(out), count, _dptr(ws), ws.numel())
+    _check(lib().fhe_mul_relin_multi(arr, len(parts), _stream()), "fhe_mul_relin_multi")
+    return [p[4] for p in parts]

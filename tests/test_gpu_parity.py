@@ -157,6 +157,67 @@ def test_mul_relin_fused_batch_all_words(dev, n, bits, k):
             assert (sq[j] == bfv.mul_relin(P, a[j], a[j], rlk)).all(), f"square {j}"
 
 
+def test_mul_relin_multi_mixed_sizes(dev):
+    """One fhe_mul_relin_multi call over parts of three contexts (n = 4096,
+    8192, 16384 with their configured primes, t = 65537; one n=4096 part large
+    enough for the fused product kernel): every output equals the single-call
+    result word for word, and the first product of each part equals the
+    oracle's."""
+    import torch
+    parts, want_single, oracle_checks = [], [], []
+    for key, count, seed in (("bfv_n4096", 40, 31), ("bfv_n8192", 5, 32), ("bfv_n16384", 3, 33),
+                             ("bfv_n4096", 6, 34)):
+        cfg = inputs.CONFIGS[key]
+        n, qs, t = cfg["n"], cfg["q"], cfg["t"]
+        P, km, pk, rlk, ctx, rlk_d = setup(n, qs, t, "slots", seed)
+        a = inputs.uniform_ciphertexts(n, qs, count, seed, "a")
+        b = inputs.uniform_ciphertexts(n, qs, count, seed, "b")
+        da, db = up(a), up(b)
+        want_single.append(down(ctx.mul_relin(rlk_d, da, db)))
+        parts.append((ctx, rlk_d, da, db, ctx.empty_ct(count)))
+        oracle_checks.append((P, a[0], b[0], rlk))
+    say("mul_relin_multi n=4096/8192/16384/4096")
+    outs = fhe.mul_relin_multi(parts)
+    for i, o in enumerate(outs):
+        assert (down(o) == want_single[i]).all(), f"part {i}"
+        P, a0, b0, rlk = oracle_checks[i]
+        assert (want_single[i][0] == bfv.mul_relin(P, a0, b0, rlk)).all(), f"part {i} oracle"
+    torch.cuda.synchronize()
+
+
+def test_square_chain_graph_replays(dev):
+    """x^(2^3) by the graph-captured squaring chain equals three eager squarings
+    (and the oracle on one ciphertext); the graph is replayed three times on
+    reset inputs with unrelated eager work and synchronisation in between."""
+    import torch
+    cfg = inputs.CONFIGS["bfv_n4096"]
+    n, qs, t = cfg["n"], cfg["q"], cfg["t"]
+    P, km, pk, rlk, ctx, rlk_d = setup(n, qs, t, "slots", 41)
+    count, depth = 8, 3
+    x0 = inputs.uniform_ciphertexts(n, qs, count, 41, "x")
+    xe = up(x0)
+    for _ in range(depth):
+        ctx.mul_relin(rlk_d, xe, xe, out=xe)
+    want = down(xe)
+    y = x0[0]
+    for _ in range(depth):
+        y = bfv.mul_relin(P, y, y, rlk)
+    assert (want[0] == y).all()
+    say("square_chain graph n=4096 x8 depth 3")
+    xg = up(x0)
+    src = up(x0)
+    junk = up(inputs.uniform_ciphertexts(n, qs, 2, 42, "j"))
+    for rep in range(4):
+        xg.copy_(src)
+        ctx.add(junk, junk, out=junk)  # eager work between replays
+        torch.cuda.synchronize()
+        ctx.square_chain(rlk_d, xg, depth, graph=True)
+        assert (down(xg) == want).all(), f"graph run {rep}"
+    xg.copy_(src)
+    ctx.square_chain(rlk_d, xg, depth, graph=False)
+    assert (down(xg) == want).all(), "eager chain"
+
+
 def test_exact_path_boundary_inputs(dev):
     """Coefficients on the centring boundary (q-1)/2, (q+1)/2 and products whose
     t D / q sits next to a half-integer force the exact mixed-radix path; the
