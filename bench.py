@@ -15,7 +15,8 @@ executed ciphertext mul+relin per second, per-step p50/p99, the plain-vs-batched
 comparison at n = 16384 (one pair per call vs one batched call, for several
 batch sizes), the transform kernel alone at n = 4096 / 8192 / 16384, products
 at n = 4096, 1024 products of mixed ring sizes (per-size calls vs one
-multi-context call), depth-4 squaring chains (eager vs HIP graph), the roofline of the dominant kernel (timed live with HIP events on
+multi-context call), depth-4 squaring chains (eager vs HIP graph), the
+continuous-batching serving loop (Poisson arrivals, p50/p99), the roofline of the dominant kernel (timed live with HIP events on
 the launch stream), and the CPU oracle timed on a bounded sample of the same
 work.
 """
@@ -105,6 +106,8 @@ def main():
     ap.add_argument("--inputs", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="length of the Poisson arrival window of the serving leg")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB device-to-device copy first (HBM counter scale)")
     args = ap.parse_args()
@@ -228,6 +231,8 @@ def main():
         out["mixed_sizes"] = mixed_leg(fhe, inputs, torch)
         out["square_chain_n16384"] = chain_leg(fhe, inputs, torch)
         print("[bench] mixed sizes and squaring chains done", file=sys.stderr, flush=True)
+        out["serving"] = serving_leg(fhe, inputs, torch, seconds=args.serve_seconds)
+        print("[bench] serving loop done", file=sys.stderr, flush=True)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inputs)
@@ -409,6 +414,60 @@ def chain_leg(fhe, inputs, torch, count=64, depth=4, reps=3):
         res[f"{name}_mul_relin_per_s"] = count * depth * reps / (time.perf_counter() - t0)
     res.update({"n": n, "count": count, "depth": depth})
     return res
+
+
+def serving_leg(fhe, inputs, torch, seconds=10.0, rate=200.0, seed=7):
+    """Continuous batching (paper_2204_12201_amd/serving.py): Poisson arrivals at
+    `rate` requests/s for `seconds`, 5 products at n = 8192 (t = 65537) for every
+    3 p = 17 bridge conversions at n = 16384 (the survey's serving mix without
+    its imputation share); keys resident, 32 GiB in-flight budget.  Throughput
+    and p50/p99 latency from arrival to completion, per kind and overall."""
+    from paper_2204_12201_amd import serving
+    c8 = inputs.CONFIGS["bfv_n8192"]
+    ctx8 = fhe.Context(c8["n"], c8["q"], c8["t"], "slots")
+    km8 = inputs.key_material(c8["n"], c8["q"], seed)
+    _, rlk8 = ctx8.keygen(km8["s"], km8["pk_a"], km8["pk_e"], km8["rlk_a"], km8["rlk_e"])
+    cb = inputs.CONFIGS["bridge_n16384"]
+    ctxb = fhe.Context(cb["n"], cb["q"], cb["t"], "coeff")
+    kmb = inputs.key_material(cb["n"], cb["q"], seed)
+    pkb, rlkb = ctxb.keygen(kmb["s"], kmb["pk_a"], kmb["pk_e"], kmb["rlk_a"], kmb["rlk_e"])
+    pool = 64
+    a = fhe.from_numpy_u64(inputs.uniform_ciphertexts(c8["n"], c8["q"], pool, seed, "a"), "cuda")
+    b = fhe.from_numpy_u64(inputs.uniform_ciphertexts(c8["n"], c8["q"], pool, seed, "b"), "cuda")
+    xs = inputs.bridge_values(cb["t"], pool, seed)
+    pts = np.zeros((pool, cb["n"]), dtype=np.uint64)
+    pts[:, 0] = xs
+    r = inputs.encryption_randomness(cb["n"], pool, seed)
+    xb = ctxb.encrypt(pkb, pts, r["u"], r["e"])
+    # warm both lanes (workspaces, kernels)
+    ctx8.mul_relin(rlk8, a[:64], b[:64])
+    ctxb.bridge_to_bits(rlkb, xb[:8], cb["nbits"])
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(seed)
+    t, reqs, i = 0.0, [], 0
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t >= seconds:
+            break
+        if rng.random() < 5.0 / 8.0:
+            j = i % pool
+            reqs.append(serving.Request(rid=i, kind="mul", arrival=t, x=a[j:j + 1], y=b[j:j + 1]))
+        else:
+            j = i % pool
+            reqs.append(serving.Request(rid=i, kind="bridge", arrival=t, x=xb[j:j + 1]))
+        i += 1
+    srv = serving.Server([serving.Lane("mul_n8192", ctx8, rlk8, "mul", max_batch=256),
+                          serving.Lane("bridge_n16384", ctxb, rlkb, "bridge", max_batch=32, nbits=cb["nbits"])],
+                         budget_bytes=32 << 30)
+    for q in reqs:
+        q.kind = "mul_n8192" if q.kind == "mul" else "bridge_n16384"
+    t0 = time.perf_counter()
+    done = srv.run(reqs)
+    el = time.perf_counter() - t0
+    out = serving.summary(done, el)
+    out.update({"offered_rate_req_per_s": rate, "seconds": seconds, "wall_s": el,
+                "peak_in_flight_gib": srv.peak_bytes / 2**30, "max_concurrent_lanes": srv.max_concurrent})
+    return out
 
 
 def cpu_baseline(inputs):

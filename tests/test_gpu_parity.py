@@ -218,6 +218,58 @@ def test_square_chain_graph_replays(dev):
     assert (down(xg) == want).all(), "eager chain"
 
 
+def test_serving_results_identical_alone_and_in_mix(dev):
+    """The continuous-batching loop: products at n = 8192 (t = 65537) and p = 17
+    bridge conversions at n = 16384 arriving interleaved; every request's result
+    equals the same request computed alone, batches formed, and the two kinds
+    were in flight together."""
+    import torch
+    from paper_2204_12201_amd import serving
+    c8 = inputs.CONFIGS["bfv_n8192"]
+    ctx8 = fhe.Context(c8["n"], c8["q"], c8["t"], "slots")
+    km8 = inputs.key_material(c8["n"], c8["q"], 51)
+    _, rlk8 = ctx8.keygen(km8["s"], km8["pk_a"], km8["pk_e"], km8["rlk_a"], km8["rlk_e"])
+    cb = inputs.CONFIGS["bridge_n16384"]
+    ctxb = fhe.Context(cb["n"], cb["q"], cb["t"], "coeff")
+    kmb = inputs.key_material(cb["n"], cb["q"], 52)
+    pkb, rlkb = ctxb.keygen(kmb["s"], kmb["pk_a"], kmb["pk_e"], kmb["rlk_a"], kmb["rlk_e"])
+    nm, nb = 24, 6
+    a = up(inputs.uniform_ciphertexts(c8["n"], c8["q"], nm, 51, "a"))
+    b = up(inputs.uniform_ciphertexts(c8["n"], c8["q"], nm, 51, "b"))
+    xs = inputs.bridge_values(cb["t"], nb, 52)
+    pts = np.zeros((nb, cb["n"]), dtype=np.uint64)
+    pts[:, 0] = xs
+    r = inputs.encryption_randomness(cb["n"], nb, 52)
+    xb = ctxb.encrypt(pkb, pts, r["u"], r["e"])
+    torch.cuda.synchronize()
+    reqs = []
+    for i in range(nm):
+        reqs.append(serving.Request(rid=i, kind="mul", arrival=0.0001 * i, x=a[i:i + 1], y=b[i:i + 1]))
+    for i in range(nb):  # arrivals faster than service: later requests queue and batch
+        reqs.append(serving.Request(rid=100 + i, kind="bridge", arrival=0.0002 * i + 0.00005, x=xb[i:i + 1]))
+    reqs.sort(key=lambda q: q.arrival)
+    srv = serving.Server([serving.Lane("mul", ctx8, rlk8, "mul", max_batch=64),
+                          serving.Lane("bridge", ctxb, rlkb, "bridge", max_batch=8, nbits=5)],
+                         budget_bytes=32 << 30)
+    say("serving loop: 24 products n=8192 + 6 bridge conversions n=16384")
+    done = srv.run(reqs)
+    torch.cuda.synchronize()
+    assert len(done) == nm + nb
+    assert max(q.batch for q in done) > 1
+    assert srv.max_concurrent >= 2
+    for q in done:
+        if q.kind == "mul":
+            alone = ctx8.mul_relin(rlk8, q.x, q.y)
+        else:
+            alone = ctxb.bridge_to_bits(rlkb, q.x, 5)
+        assert (down(q.result) == down(alone)).all(), q.rid
+    dec = ctxb.decrypt(kmb["s"], torch.cat([q.result for q in done if q.kind == "bridge"]).reshape(-1, 2, 8, cb["n"]))
+    got = dec.reshape(nb, 5, cb["n"])[:, :, 0]
+    order = [q.rid - 100 for q in done if q.kind == "bridge"]
+    for row, i in zip(got, order):
+        assert [int(v) for v in row] == [(int(xs[i]) >> bit) & 1 for bit in range(5)], i
+
+
 def test_exact_path_boundary_inputs(dev):
     """Coefficients on the centring boundary (q-1)/2, (q+1)/2 and products whose
     t D / q sits next to a half-integer force the exact mixed-radix path; the
