@@ -583,6 +583,26 @@ fhe_status fhe_ctx_create(const fhe_params *p, int hip_device, fhe_ctx **out) {
         const uint64_t pmod = prod_mod(ps, qs[i]);
         cc->p2q_m[i][c->kp] = mont((qs[i] - pmod) % qs[i], qs[i]);
     }
+    // bounds of the multiply-accumulates (every operand canonical; overflow
+    // counts at most the basis size)
+    auto fits = [](u128 T, uint64_t m) { return (uint64_t)(T >> 64) <= 2 * m - 2; };
+    cc->fast_lift = cc->fast_scale_p = cc->fast_p2q = 1;
+    for (uint32_t j = 0; j < c->kp; j++) {
+        const uint64_t pm = ps[j] - 1;
+        u128 T = 0;
+        for (uint32_t i = 0; i < k; i++) T += (u128)(qs[i] - 1) * pm;
+        const u128 Tl = T + (u128)k * pm;
+        const u128 Ts = T + (u128)pm * pm + (u128)k * pm + pm;
+        if (!fits(Tl, ps[j])) cc->fast_lift = 0;
+        if (!fits(Ts, ps[j])) cc->fast_scale_p = 0;
+    }
+    for (uint32_t i = 0; i < k; i++) {
+        const uint64_t qm = qs[i] - 1;
+        u128 T = 0;
+        for (uint32_t j = 0; j < c->kp; j++) T += (u128)(ps[j] - 1) * qm;
+        T += (u128)c->kp * qm;
+        if (!fits(T, qs[i])) cc->fast_p2q = 0;
+    }
     cc->h_t = half_mod(qs, t);
     cc->qinv_t = hinv(q_mod_t, t);
     cc->qinv_ts = shoup(cc->qinv_t, t);

@@ -114,7 +114,8 @@ __device__ __forceinline__ void lift_coef(const DevCtx &c, const uint64_t (&x)[M
                 for (int i = 0; i < MK; i++)
                     if (i < k) acc3_mac(acc, y[i], ldc(m + i));
                 acc3_mac(acc, beta, ldc(m + k));
-                put(j, acc_reduce_mont(acc3_value(acc), cc.p[j], cc.p_qinv[j], cc.p_one[j]));
+                put(j, cc.fast_lift ? acc_reduce_mont_small(acc3_value(acc), cc.p[j], cc.p_qinv[j])
+                                     : acc_reduce_mont(acc3_value(acc), cc.p[j], cc.p_qinv[j], cc.p_one[j]));
             }
         }
     } else {
@@ -199,7 +200,9 @@ __device__ __forceinline__ void scale_coef(const DevCtx &c, const uint64_t (&dq)
             acc3_mac(acc, dp[j], ldc(m + k));
             acc3_mac(acc, v, ldc(m + k + 1));
             acc3_add(acc, ldc(m + k + 2));
-            const uint64_t r = acc_reduce_mont(acc3_value(acc), cc.p[j], cc.p_qinv[j], cc.p_one[j]);  // C_{p_j}
+            const uint64_t r = cc.fast_scale_p  // C_{p_j}
+                                   ? acc_reduce_mont_small(acc3_value(acc), cc.p[j], cc.p_qinv[j])
+                                   : acc_reduce_mont(acc3_value(acc), cc.p[j], cc.p_qinv[j], cc.p_one[j]);
             z[j] = mul_shoup(r, cc.phinv[j], cc.phinv_p[j], cc.p[j]);
             e2 = fma((double)z[j], cc.inv_p[j], e2);
         }
@@ -218,7 +221,8 @@ __device__ __forceinline__ void scale_coef(const DevCtx &c, const uint64_t (&dq)
                 for (int j = 0; j < MKP; j++)
                     if (j < kp) acc3_mac(acc, z[j], ldc(m + j));
                 acc3_mac(acc, beta, ldc(m + kp));
-                put(i, acc_reduce_mont(acc3_value(acc), cc.q[i], cc.q_qinv[i], cc.q_one[i]));
+                put(i, cc.fast_p2q ? acc_reduce_mont_small(acc3_value(acc), cc.q[i], cc.q_qinv[i])
+                                  : acc_reduce_mont(acc3_value(acc), cc.q[i], cc.q_qinv[i], cc.q_one[i]));
             }
         }
         return;

@@ -163,6 +163,14 @@ __device__ __forceinline__ Acc128 acc3_value(const Acc3 &A) {
 }
 #endif
 
+// (acc) 2^-64 mod q in [0, q) when acc.hi <= 2q - 2: REDC gives hi + mulhi(m, q)
+// + [lo != 0] < hi + q + 1 <= 3q - 1, then two conditional subtractions.
+FHE_HD uint64_t acc_reduce_mont_small(const Acc128 &a, uint64_t q, uint64_t qinv_neg) {
+    uint64_t r = redc_lazy(a.hi, a.lo, q, qinv_neg);
+    r = csub(r, q << 1);
+    return csub(r, q);
+}
+
 // (acc) 2^-64 mod q in [0, q) for any 128-bit acc: the high word is first
 // reduced below 2q by a Shoup multiplication by 1 (one_p = floor(2^64 / q)),
 // which keeps the REDC input below 2q 2^64; REDC then lands in [0, 3q).

@@ -45,6 +45,10 @@ struct MrcConst {
 struct ConvConst {
     uint32_t k, kp;
     uint64_t t;
+    // 1 when every multiply-accumulate of the conversion stays below 2^64 (2 m - 1)
+    // for its target prime m, so one Montgomery reduction (below 3m) suffices
+    // without first reducing the high word: lift Q -> P, scale in P, P -> Q.
+    uint32_t fast_lift, fast_scale_p, fast_p2q, pad_fast;
     // basis primes and their reduction helpers
     uint64_t q[FHE_MAXK], q_qinv[FHE_MAXK], q_one[FHE_MAXK];     // Q: prime, -q^-1 mod 2^64, floor(2^64/q)
     uint64_t p[FHE_MAXKP], p_qinv[FHE_MAXKP], p_one[FHE_MAXKP];  // P: likewise
