@@ -419,9 +419,9 @@ def chain_leg(fhe, inputs, torch, count=64, depth=4, reps=3):
 def serving_leg(fhe, inputs, torch, seconds=10.0, rate=200.0, seed=7):
     """Continuous batching (paper_2204_12201_amd/serving.py): Poisson arrivals at
     `rate` requests/s for `seconds`, 5 products at n = 8192 (t = 65537) for every
-    3 p = 17 bridge conversions at n = 16384 (the survey's serving mix without
-    its imputation share); keys resident, 32 GiB in-flight budget.  Throughput
-    and p50/p99 latency from arrival to completion, per kind and overall."""
+    3 p = 17 bridge conversions at n = 16384; keys resident, 32 GiB in-flight
+    budget.  Throughput and p50/p99 latency from arrival to completion, per kind
+    and overall."""
     from paper_2204_12201_amd import serving
     c8 = inputs.CONFIGS["bfv_n8192"]
     ctx8 = fhe.Context(c8["n"], c8["q"], c8["t"], "slots")
