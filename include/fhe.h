@@ -216,7 +216,9 @@ fhe_status fhe_square_chain(fhe_ctx *ctx, const uint64_t *rlk_dev, uint64_t *x, 
  * Requires coefficient encoding, t prime, t - 1 a power of two, and
  * 2^nbits >= t (else FHE_EUNSUPPORTED / FHE_EINVAL).  Inputs should encrypt
  * constant polynomials (the equality test is coefficient-wise only for
- * those); the words are defined for any input.  ws: FHE_OP_BRIDGE bytes. */
+ * those); the words are defined for any input.  With eq == NULL the test
+ * c = 0, which enters no bit, is not evaluated (same bits).
+ * ws: FHE_OP_BRIDGE bytes. */
 fhe_status fhe_bridge_to_bits(fhe_ctx *ctx, const uint64_t *rlk_dev, const uint64_t *x,
                               uint32_t nbits, uint64_t *bits, uint64_t *eq, size_t count,
                               void *ws, size_t ws_bytes, hipStream_t stream);

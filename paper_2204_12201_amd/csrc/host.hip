@@ -1052,6 +1052,8 @@ fhe_status fhe_bridge_to_bits(fhe_ctx *c, const uint64_t *rlk, const uint64_t *x
         return FHE_EINVAL;
     FHE_TRY(check_canonical(c, x, count * 2 * c->k, c->k, 0, st));
     const int T = (int)c->t;
+    // without eq outputs the test c = 0 contributes to no bit and is skipped
+    const int c0 = eq ? 0 : 1, Tc = T - c0;
     int squarings = 0;
     while ((1ull << squarings) < c->t - 1) squarings++;
     const size_t G = bridge_group(c);
@@ -1061,8 +1063,8 @@ fhe_status fhe_bridge_to_bits(fhe_ctx *c, const uint64_t *rlk, const uint64_t *x
     const DevCtx &d = c->dev;
     for (size_t g0 = 0; g0 < count; g0 += G) {
         const size_t gc = count - g0 < G ? count - g0 : G;
-        const size_t chains = gc * T;
-        // First squaring, shared by the T chains of an input (kernels_conv.hip):
+        const size_t chains = gc * Tc;
+        // First squaring, shared by the chains of an input (kernels_conv.hip):
         // the input's own square up to the key switching, then per chain the
         // corrected components 0 and 1 plus the shared key-switching output.
         const uint64_t *xg = x + g0 * ctw;
@@ -1077,13 +1079,13 @@ fhe_status fhe_bridge_to_bits(fhe_ctx *c, const uint64_t *rlk, const uint64_t *x
         FHE_TRY(run(c, KK_SCALE, st, [&] { return launch_scale(d, D1, nullptr, C21, gc, st, 2, 1); }));
         FHE_HIP(hipMemsetAsync(R1, 0, gc * 2 * k * n * sizeof(uint64_t), st));
         FHE_TRY(run(c, KK_RELIN_FUSED, st, [&] { return launch_relin_fused(d, C21, rlk, R1, gc, st); }));
-        FHE_TRY(run(c, KK_BRIDGE, st, [&] { return launch_bridge_gamma(d, xg, E1, gam, chains, T, st); }));
+        FHE_TRY(run(c, KK_BRIDGE, st, [&] { return launch_bridge_gamma(d, xg, E1, gam, chains, Tc, c0, st); }));
         FHE_TRY(run(c, KK_SCALE, st,
-                    [&] { return launch_scale_chain(d, D1, xg, E1, gam, R1, y, chains, T, st); }));
+                    [&] { return launch_scale_chain(d, D1, xg, E1, gam, R1, y, chains, Tc, st); }));
         for (int sq = 1; sq < squarings; sq++) FHE_TRY(mul_relin_impl(c, rlk, y, y, y, chains, ws2, st));
         uint64_t *eqp = eq ? eq + g0 * T * ctw : nullptr;
         FHE_TRY(run(c, KK_BRIDGE, st, [&] {
-            return launch_bridge_combine(d, y, bits + g0 * nbits * ctw, eqp, gc, T, (int)nbits, st);
+            return launch_bridge_combine(d, y, bits + g0 * nbits * ctw, eqp, gc, Tc, (int)nbits, c0, st);
         }));
     }
     return FHE_OK;

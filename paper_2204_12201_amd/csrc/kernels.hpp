@@ -75,7 +75,7 @@ hipError_t launch_scale(const DevCtx &c, const uint64_t *Dt, uint64_t *out, uint
 // and k_scale_chain): per-chain constant-coefficient corrections, then the
 // chains' components 0 and 1 from the inputs' tensor plus key-switching output.
 hipError_t launch_bridge_gamma(const DevCtx &c, const uint64_t *x, const uint64_t *E, uint64_t *gam,
-                               size_t chains, int tcount, hipStream_t s);
+                               size_t chains, int tcount, int c0, hipStream_t s);
 hipError_t launch_scale_chain(const DevCtx &c, const uint64_t *Dt, const uint64_t *x, const uint64_t *E,
                               const uint64_t *gam, const uint64_t *R, uint64_t *y, size_t chains, int tcount,
                               hipStream_t s);
@@ -100,7 +100,7 @@ hipError_t launch_key_b(const DevCtx &c, const uint64_t *prod, const uint64_t *e
 hipError_t launch_encrypt_finish(const DevCtx &c, const uint64_t *prod, const int32_t *e,
                                  const uint64_t *pt, uint64_t *ct, size_t count, hipStream_t s);
 hipError_t launch_bridge_combine(const DevCtx &c, const uint64_t *y, uint64_t *bits, uint64_t *eq,
-                                 size_t count, int tcount, int nbits, hipStream_t s);
+                                 size_t count, int tcount, int nbits, int c0, hipStream_t s);
 hipError_t launch_horner(const DevCtx &c, const uint64_t *bits, int nbits, uint64_t *out,
                          size_t count, hipStream_t s);
 // flag[0] |= 1 if some word of rows [nrows][n] (limb = row % kmod + off) is >= its prime

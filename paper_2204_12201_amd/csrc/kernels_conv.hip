@@ -313,17 +313,18 @@ __device__ uint64_t mulmod_slow(uint64_t a, uint64_t b, uint64_t p) {
     return mod128_slow(hi, lo, p);
 }
 
-// One thread per chain (input j = chain / tcount, c = chain % tcount).  x: the
-// inputs [count][2][k][n]; E: their lift [count][2][K][n] (P rows).
+// One thread per chain (input j = chain / tcount, c = c0 + chain % tcount).
+// x: the inputs [count][2][k][n]; E: their lift [count][2][K][n] (P rows).
 template <int MK, int MKP, bool EX>
 __global__ __launch_bounds__(64) void k_bridge_gamma(DevCtx c, const uint64_t *__restrict__ x,
                                                      const uint64_t *__restrict__ E,
-                                                     uint64_t *__restrict__ gam, size_t chains, int tcount) {
+                                                     uint64_t *__restrict__ gam, size_t chains, int tcount,
+                                                     int c0) {
     const size_t chain = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
     if (chain >= chains) return;
     const int n = c.n, k = EX ? MK : c.k, kp = EX ? MKP : c.kp, K = EX ? MK + MKP : c.K;
     const size_t j = chain / tcount;
-    const uint64_t cv = chain % tcount;
+    const uint64_t cv = c0 + chain % tcount;
     const ConvConst &cc = *c.cc;
     uint64_t *g = gam + chain * 2 * (size_t)K;
     uint64_t x0[MK];
@@ -531,11 +532,12 @@ __global__ void k_encrypt_finish(DevCtx c, const uint64_t *__restrict__ prod,
 }
 
 // eq_c = Delta [coefficient 0 of c0] - y_c;  bits_b = sum_{c in [1,T), bit b of c} eq_c.
+// y holds chains c = c0 .. c0 + tcount - 1 of every input (c0 = 0 or 1).
 constexpr int FHE_MAXNB = 20;
 __global__ __launch_bounds__(256) void k_bridge_combine(DevCtx c, const uint64_t *__restrict__ y,
                                                         uint64_t *__restrict__ bits,
                                                         uint64_t *__restrict__ eq, int tcount,
-                                                        int nbits) {
+                                                        int nbits, int c0) {
     const int n = c.n, k = c.k;
     const int coef = blockIdx.x * 256 + threadIdx.x;
     if (coef >= n) return;
@@ -550,12 +552,13 @@ __global__ __launch_bounds__(256) void k_bridge_combine(DevCtx c, const uint64_t
     for (int b = 0; b < FHE_MAXNB; b++) acc[b] = 0;
     const size_t off = (size_t)row * n + coef;
     for (int cc = 0; cc < tcount; cc++) {
+        const int cv = c0 + cc;
         const uint64_t yv = y[(j * tcount + cc) * ctw + off];
         const uint64_t ev = sub_mod(one, yv, q);
         if (eq) eq[(j * tcount + cc) * ctw + off] = ev;
 #pragma unroll
         for (int b = 0; b < FHE_MAXNB; b++)
-            if (b < nbits && ((cc >> b) & 1)) acc[b] = add_mod(acc[b], ev, q);
+            if (b < nbits && ((cv >> b) & 1)) acc[b] = add_mod(acc[b], ev, q);
     }
 #pragma unroll
     for (int b = 0; b < FHE_MAXNB; b++)
@@ -632,9 +635,9 @@ struct ScaleL {
 template <int MK, int MKP, bool EX>
 struct GammaL {
     static hipError_t run(const DevCtx &c, const uint64_t *x, const uint64_t *E, uint64_t *gam,
-                          size_t chains, int tcount, hipStream_t s) {
+                          size_t chains, int tcount, int c0, hipStream_t s) {
         hipLaunchKernelGGL((k_bridge_gamma<MK, MKP, EX>), dim3((unsigned)((chains + 63) / 64)), dim3(64), 0, s,
-                           c, x, E, gam, chains, tcount);
+                           c, x, E, gam, chains, tcount, c0);
         return hipGetLastError();
     }
 };
@@ -665,9 +668,9 @@ hipError_t launch_scale(const DevCtx &c, const uint64_t *Dt, uint64_t *out, uint
 }
 
 hipError_t launch_bridge_gamma(const DevCtx &c, const uint64_t *x, const uint64_t *E, uint64_t *gam,
-                               size_t chains, int tcount, hipStream_t s) {
+                               size_t chains, int tcount, int c0, hipStream_t s) {
     if (chains == 0) return hipSuccess;
-    return by_class<GammaL>(c.k, c.kp, c, x, E, gam, chains, tcount, s);
+    return by_class<GammaL>(c.k, c.kp, c, x, E, gam, chains, tcount, c0, s);
 }
 
 hipError_t launch_scale_chain(const DevCtx &c, const uint64_t *Dt, const uint64_t *x, const uint64_t *E,
@@ -738,11 +741,11 @@ hipError_t launch_encrypt_finish(const DevCtx &c, const uint64_t *prod, const in
 }
 
 hipError_t launch_bridge_combine(const DevCtx &c, const uint64_t *y, uint64_t *bits, uint64_t *eq,
-                                 size_t count, int tcount, int nbits, hipStream_t s) {
+                                 size_t count, int tcount, int nbits, int c0, hipStream_t s) {
     if (count == 0) return hipSuccess;
     if (nbits > FHE_MAXNB) return hipErrorInvalidValue;
     dim3 grid((c.n + 255) / 256, 2 * c.k, (unsigned)count);
-    hipLaunchKernelGGL(k_bridge_combine, grid, dim3(256), 0, s, c, y, bits, eq, tcount, nbits);
+    hipLaunchKernelGGL(k_bridge_combine, grid, dim3(256), 0, s, c, y, bits, eq, tcount, nbits, c0);
     return hipGetLastError();
 }
 

@@ -405,6 +405,8 @@ def test_bridge_small_all_words(dev):
         assert (dec[j, :, 1:] == 0).all()
     rec = ctx.bits_to_mod(up(bits))
     assert [int(v) for v in ctx.decrypt(km["s"], rec)[:, 0]] == xs
+    # without eq outputs the c = 0 test is skipped: same bits
+    assert (down(ctx.bridge_to_bits(rlk_d, up(cts), 5)) == bits).all()
 
 
 def test_bridge_full_size_sampled(dev):
@@ -426,6 +428,7 @@ def test_bridge_full_size_sampled(dev):
     cts = down(ct_d)
     bits, eq = ctx.bridge_to_bits(rlk_d, ct_d, 5, with_eq=True)
     bits_h, eq_h = down(bits), down(eq)
+    assert (down(ctx.bridge_to_bits(rlk_d, ct_d, 5)) == bits_h).all()  # c = 0 skipped
     for (j, c) in [(0, int(xs[0])), (1, (int(xs[1]) + 3) % t)]:
         assert (eq_h[j, c] == bfv.bridge_eq(P, cts[j], rlk, c)).all(), (j, c)
     for j in (0, 7):
