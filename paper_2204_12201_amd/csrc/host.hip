@@ -438,23 +438,30 @@ fhe_status fhe_ctx_create(const fhe_params *p, int hip_device, fhe_ctx **out) {
     }
     if (p->encoding == FHE_ENC_SLOTS && (!is_prime_u64(p->t) || p->t % (2ull * n) != 1)) return FHE_EPARAM;
 
-    // Auxiliary primes: the largest primes below 2^61 that are 1 mod 2n and not
-    // in Q, until P > 4 t n q (the scaled tensor is then unique modulo P).
-    std::vector<uint64_t> ps;
+    // Auxiliary primes: the largest primes below a cap that are 1 mod 2n and
+    // not in Q, until P > 4 t n q (the scaled tensor is then unique modulo P).
+    // The cap is 2^58 when that takes no more primes than the cap 2^61: primes
+    // below 2^64 / (4 (L + 1)) let the transforms skip conditional subtractions.
     const double need = std::log2((double)p->t) + std::log2((double)n) + log2q + 2.0;
-    double have = 0;
     const uint64_t step = 2ull * n;
-    uint64_t cand = ((1ull << 61) - 2) / step * step + 1;
-    while (have < need) {
-        if (ps.size() >= (size_t)FHE_MAXKP || cand < (1ull << 59)) return FHE_EPARAM;
-        bool inq = false;
-        for (uint64_t qi : qs) inq |= (qi == cand);
-        if (!inq && is_prime_u64(cand) && hgcd(p->t, cand) == 1) {
-            ps.push_back(cand);
-            have += std::log2((double)cand);
+    auto aux_primes = [&](uint64_t cap, std::vector<uint64_t> &ps) {
+        double have = 0;
+        uint64_t cand = (cap - 2) / step * step + 1;
+        while (have < need) {
+            if (ps.size() >= (size_t)FHE_MAXKP || cand < (cap >> 2)) return false;
+            bool inq = false;
+            for (uint64_t qi : qs) inq |= (qi == cand);
+            if (!inq && is_prime_u64(cand) && hgcd(p->t, cand) == 1) {
+                ps.push_back(cand);
+                have += std::log2((double)cand);
+            }
+            cand -= step;
         }
-        cand -= step;
-    }
+        return true;
+    };
+    std::vector<uint64_t> ps, ps_small;
+    if (!aux_primes(1ull << 61, ps)) return FHE_EPARAM;
+    if (aux_primes(1ull << 58, ps_small) && ps_small.size() <= ps.size()) ps.swap(ps_small);
 
     fhe_ctx *c = new fhe_ctx();
     c->n = n;
@@ -648,9 +655,16 @@ fhe_status fhe_ctx_create(const fhe_params *p, int hip_device, fhe_ctx **out) {
     d.mrc_q = (const MrcConst *)c->d_mrc_q;
     d.mrc_p = (const MrcConst *)c->d_mrc_p;
     d.fallback = (unsigned long long *)c->d_counters;
-    d.lazy_q = 1;
-    for (uint32_t i = 0; i < k; i++)
-        if (c->primes[i] >= UINT64_MAX / (4ull * (c->L + 1))) d.lazy_q = 0;
+    d.lazy_q = d.lazy_all = 1;
+    d.lazy_limbs = 0;
+    for (uint32_t i = 0; i < c->K; i++) {
+        if (c->primes[i] < UINT64_MAX / (4ull * (c->L + 1))) {
+            d.lazy_limbs |= 1ull << i;
+        } else {
+            d.lazy_all = 0;
+            if (i < k) d.lazy_q = 0;
+        }
+    }
     // default chunk: about 8 GiB of product workspace
     size_t per = item_words_mul(c, false) * 8;
     c->default_limit = ((size_t)8 << 30) / per;

@@ -20,6 +20,8 @@ struct DevCtx {
     const MrcConst *mrc_p;  // basis P -> targets Q
     unsigned long long *fallback;  // count of coefficients that took the exact path
     int lazy_q;             // every Q prime below 2^64 / (4 (L + 1)): lazy digit transforms
+    int lazy_all;           // every prime of Q and P below 2^64 / (4 (L + 1)): lazy transforms
+    uint64_t lazy_limbs;    // bit l: prime l (Q then P) below 2^64 / (4 (L + 1))
 };
 
 // Kernel kinds (timing and profiling names).

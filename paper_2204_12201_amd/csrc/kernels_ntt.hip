@@ -36,11 +36,18 @@ __device__ __forceinline__ void load_bitrev(uint64_t (&x)[16], const uint64_t *_
     for (int s = 0; s < 16; s++) x[s] = src[bitrev_layout_index<L>(tid, s)];
 }
 
+// Canonical residue of any 64-bit value: Shoup multiplication by 1.
+__device__ __forceinline__ uint64_t canon_any(uint64_t x, uint64_t q, uint64_t one_p) {
+    return mul_shoup(x, 1, one_p, q);
+}
+
 // mode: NttMode (kernels.hpp).  Rows row0, row0 + gridDim.x, ... of data:
 // the workgroups stay resident and fetch their next row while the current one
 // is transformed (forward with whole waves: into LDS by prefetch_row_lds;
-// otherwise into registers).
-template <int L, bool FWD>
+// otherwise into registers).  LZ: every prime below 2^64 / (4 (L + 1)): the
+// forward transform skips its conditional subtractions and the inverse half of
+// them.
+template <int L, bool FWD, bool LZ>
 __global__ __launch_bounds__(Geo<L>::T) void k_ntt_rows(DevCtx c, uint64_t *__restrict__ data,
                                                        size_t nrows, int kmod, int limb_off, int mode) {
     __shared__ uint64_t lds[Geo<L>::lds_words];
@@ -62,21 +69,22 @@ __global__ __launch_bounds__(Geo<L>::T) void k_ntt_rows(DevCtx c, uint64_t *__re
             auto hook = [&]() {
                 if (next < nrows) prefetch_row_lds<L>(lds, data + next * n, fresh(tid));
             };
-            ntt_fwd_regs<L, 4, true>(x, lds, tid, c.tw + (size_t)limb * n, q, hook);
+            ntt_fwd_regs<L, 4, !LZ>(x, lds, tid, c.tw + (size_t)limb * n, q, hook);
         } else {
             if (next < nrows) {
                 if constexpr (FWD) load_natural<L>(nx, data + next * n, fresh(tid));
                 else load_bitrev<L>(nx, data + next * n, fresh(tid));
             }
-            if constexpr (FWD) ntt_fwd_regs<L>(x, lds, tid, c.tw + (size_t)limb * n, q);
-            else ntt_inv_regs<L>(x, lds, tid, c.itw + (size_t)limb * n, q);
+            if constexpr (FWD) ntt_fwd_regs<L, 4, !LZ>(x, lds, tid, c.tw + (size_t)limb * n, q);
+            else ntt_inv_regs<L, 4, LZ>(x, lds, tid, c.itw + (size_t)limb * n, q);
         }
         const uint32_t t1 = fresh(tid);
         if constexpr (FWD) {
 #pragma unroll
             for (int s = 0; s < 16; s++) {
-                uint64_t v = canon8(x[s], q);
-                if (mode == NTT_FWD_NINVM) v = mul_shoup(v, P.ninvm, P.ninvm_p, q);
+                uint64_t v;
+                if (mode == NTT_FWD_NINVM) v = mul_shoup(x[s], P.ninvm, P.ninvm_p, q);
+                else v = LZ ? canon_any(x[s], q, P.one_p) : canon8(x[s], q);
                 ptr[bitrev_layout_index<L>(t1, s)] = v;
             }
         } else {
@@ -105,7 +113,7 @@ __global__ __launch_bounds__(Geo<L>::T) void k_ntt_rows(DevCtx c, uint64_t *__re
 // Rows (item, poly, limb), grid (K, npoly, items).  Q limbs come from the
 // input ciphertexts, P limbs from E (written there by the lift); the forward
 // transforms land in E[item][poly][limb], canonical.
-template <int L>
+template <int L, bool LZ>
 __global__ __launch_bounds__(Geo<L>::T) void k_fwd_ext(DevCtx c, const uint64_t *__restrict__ a,
                                                       const uint64_t *__restrict__ b,
                                                       uint64_t *__restrict__ E, int npoly) {
@@ -115,7 +123,7 @@ __global__ __launch_bounds__(Geo<L>::T) void k_fwd_ext(DevCtx c, const uint64_t 
     const int limb = blockIdx.x, poly = blockIdx.y;
     const size_t item = blockIdx.z;
     const int k = c.k, K = c.K;
-    const uint64_t q = c.pc[limb].q;
+    const uint64_t q = c.pc[limb].q, one_p = c.pc[limb].one_p;
     uint64_t *dst = E + ((item * npoly + poly) * K + limb) * (size_t)n;
     const uint64_t *src;
     if (limb < k)
@@ -125,15 +133,16 @@ __global__ __launch_bounds__(Geo<L>::T) void k_fwd_ext(DevCtx c, const uint64_t 
         src = dst;
     uint64_t x[16];
     load_natural<L>(x, src, tid);
-    ntt_fwd_regs<L>(x, lds, tid, c.tw + (size_t)limb * n, q);
+    ntt_fwd_regs<L, 4, !LZ>(x, lds, tid, c.tw + (size_t)limb * n, q);
 #pragma unroll
-    for (int s = 0; s < 16; s++) dst[bitrev_layout_index<L>(tid, s)] = canon8(x[s], q);
+    for (int s = 0; s < 16; s++)
+        dst[bitrev_layout_index<L>(tid, s)] = LZ ? canon_any(x[s], q, one_p) : canon8(x[s], q);
 }
 
 // grid (K, 3, items): component comp of the tensor of item, limb `limb`.
 // Montgomery products carry a factor 2^-64, removed with n^-1 by the final
 // multiplication by n^-1 2^64.
-template <int L, bool SQ>
+template <int L, bool SQ, bool LZ>
 __global__ __launch_bounds__(Geo<L>::T) void k_tensor_intt(DevCtx c, const uint64_t *__restrict__ E,
                                                           uint64_t *__restrict__ Dt) {
     __shared__ uint64_t lds[Geo<L>::lds_words];
@@ -172,10 +181,20 @@ __global__ __launch_bounds__(Geo<L>::T) void k_tensor_intt(DevCtx c, const uint6
         }
         x[s] = csub(v, q2);  // [0, 2q)
     }
-    ntt_inv_regs<L>(x, lds, tid, c.itw + (size_t)limb * n, q);
+    ntt_inv_regs<L, 4, LZ>(x, lds, tid, c.itw + (size_t)limb * n, q);
     uint64_t *dst = Dt + ((item * 3 + comp) * K + limb) * (size_t)n;
 #pragma unroll
     for (int s = 0; s < 16; s++) dst[natural_index<L>(tid, s)] = mul_shoup(x[s], P.ninvm, P.ninvm_p, q);
+}
+
+// A forward transform output as a Montgomery operand: below 4q (LZ: from
+// below 4 (L + 1) q by a Shoup multiplication by 1) or below 2q (from below 8q
+// by two conditional subtractions).  Two such operands multiply to less than
+// q 2^64 for q < 2^60.
+template <bool LZ>
+__device__ __forceinline__ uint64_t fwd_operand(uint64_t v, uint64_t q, uint64_t one_p) {
+    if constexpr (LZ) return mul_shoup_lazy4(v, 1, one_p, q);
+    else return csub(csub(v, q << 2), q << 1);
 }
 
 // Product of two ciphertexts, transform phase fused: grid (K limbs, items).
@@ -186,7 +205,7 @@ __global__ __launch_bounds__(Geo<L>::T) void k_tensor_intt(DevCtx c, const uint6
 // domain) in the item's own output rows, which this workgroup alone touches.
 // With whole waves, each of a0 and b0 is copied into LDS while the transform
 // before it finishes (prefetch_row_lds).
-template <int L>
+template <int L, bool LZ>
 __global__ __launch_bounds__(Geo<L>::T) void k_mul_tensor(DevCtx c, const uint64_t *__restrict__ a,
                                                          const uint64_t *__restrict__ b,
                                                          const uint64_t *__restrict__ E,
@@ -199,7 +218,7 @@ __global__ __launch_bounds__(Geo<L>::T) void k_mul_tensor(DevCtx c, const uint64
     const size_t item = blockIdx.y;
     const int k = c.k, K = c.K;
     const PrimeConst &P = c.pc[limb];
-    const uint64_t q = P.q, qi = P.qinv_neg, q2 = q << 1, q4 = q << 2;
+    const uint64_t q = P.q, qi = P.qinv_neg, one_p = P.one_p;
     const Tw *tw = c.tw + (size_t)limb * n;
     const Tw *itw = c.itw + (size_t)limb * n;
     const uint64_t *src[4];
@@ -219,18 +238,18 @@ __global__ __launch_bounds__(Geo<L>::T) void k_mul_tensor(DevCtx c, const uint64
 #pragma unroll
     for (int s = 0; s < 16; s++) y[s] = src[3][natural_index<L>(t0, s)];
     asm volatile("" ::: "memory");
-    ntt_fwd_regs<L>(x, lds, tid, tw, q);
+    ntt_fwd_regs<L, 4, !LZ>(x, lds, tid, tw, q);
     auto pre_a0 = [&]() {
         if constexpr (PREFETCH) prefetch_row_lds<L>(lds, src[0], fresh(tid));
     };
-    ntt_fwd_regs<L, 4, true>(y, lds, tid, tw, q, pre_a0);
+    ntt_fwd_regs<L, 4, !LZ>(y, lds, tid, tw, q, pre_a0);
     // park A1 in d1 and a1 b1 in d2; B1 stays in y
     const uint32_t t1 = fresh(tid);
 #pragma unroll
     for (int s = 0; s < 16; s++) {
         const uint32_t idx = bitrev_layout_index<L>(t1, s);
-        const uint64_t a1 = csub(csub(x[s], q4), q2);
-        y[s] = csub(csub(y[s], q4), q2);
+        const uint64_t a1 = fwd_operand<LZ>(x[s], q, one_p);
+        y[s] = fwd_operand<LZ>(y[s], q, one_p);
         d1[idx] = a1;
         d2[idx] = mont_mul_lazy(a1, y[s], q, qi);
     }
@@ -248,12 +267,12 @@ __global__ __launch_bounds__(Geo<L>::T) void k_mul_tensor(DevCtx c, const uint64
     auto pre_b0 = [&]() {
         if constexpr (PREFETCH) prefetch_row_lds<L>(lds, src[2], fresh(tid));
     };
-    ntt_fwd_regs<L, 4, true>(x, lds, tid, tw, q, pre_b0);
+    ntt_fwd_regs<L, 4, !LZ>(x, lds, tid, tw, q, pre_b0);
     // park a0 b1 in d0; A0 stays in x
     const uint32_t t3 = fresh(tid);
 #pragma unroll
     for (int s = 0; s < 16; s++) {
-        x[s] = csub(csub(x[s], q4), q2);
+        x[s] = fwd_operand<LZ>(x[s], q, one_p);
         d0[bitrev_layout_index<L>(t3, s)] = mont_mul_lazy(x[s], y[s], q, qi);
     }
     asm volatile("" ::: "memory");
@@ -267,19 +286,19 @@ __global__ __launch_bounds__(Geo<L>::T) void k_mul_tensor(DevCtx c, const uint64
 #pragma unroll
         for (int s = 0; s < 16; s++) y[s] = src[2][natural_index<L>(t4, s)];
     }
-    ntt_fwd_regs<L>(y, lds, tid, tw, q);
+    ntt_fwd_regs<L, 4, !LZ>(y, lds, tid, tw, q);
     // d0 = a0 b0 in x, d1 = a1 b0 + a0 b1 in y (every thread rereads only the
     // positions it parked)
     const uint32_t t5 = fresh(tid);
 #pragma unroll
     for (int s = 0; s < 16; s++) {
         const uint32_t idx = bitrev_layout_index<L>(t5, s);
-        const uint64_t b0 = csub(csub(y[s], q4), q2);
+        const uint64_t b0 = fwd_operand<LZ>(y[s], q, one_p);
         y[s] = mont_mul_lazy(d1[idx], b0, q, qi) + d0[idx];  // < 4q
         x[s] = mont_mul_lazy(x[s], b0, q, qi);
     }
     asm volatile("" ::: "memory");
-    ntt_inv_regs<L>(x, lds, tid, itw, q);
+    ntt_inv_regs<L, 4, LZ>(x, lds, tid, itw, q);
     const uint32_t t6 = fresh(tid);
 #pragma unroll
     for (int s = 0; s < 16; s++) d0[natural_index<L>(t6, s)] = mul_shoup(x[s], P.ninvm, P.ninvm_p, q);
@@ -288,11 +307,11 @@ __global__ __launch_bounds__(Geo<L>::T) void k_mul_tensor(DevCtx c, const uint64
 #pragma unroll
     for (int s = 0; s < 16; s++) x[s] = d2[bitrev_layout_index<L>(t7, s)];
     asm volatile("" ::: "memory");
-    ntt_inv_regs<L>(y, lds, tid, itw, q);
+    ntt_inv_regs<L, 4, LZ>(y, lds, tid, itw, q);
     const uint32_t t8 = fresh(tid);
 #pragma unroll
     for (int s = 0; s < 16; s++) d1[natural_index<L>(t8, s)] = mul_shoup(y[s], P.ninvm, P.ninvm_p, q);
-    ntt_inv_regs<L>(x, lds, tid, itw, q);
+    ntt_inv_regs<L, 4, LZ>(x, lds, tid, itw, q);
     const uint32_t t9 = fresh(tid);
 #pragma unroll
     for (int s = 0; s < 16; s++) d2[natural_index<L>(t9, s)] = mul_shoup(x[s], P.ninvm, P.ninvm_p, q);
@@ -305,7 +324,7 @@ __global__ __launch_bounds__(Geo<L>::T) void k_mul_tensor(DevCtx c, const uint64
 // live in registers: a0 is loaded while a1 is transformed; d1 (transform
 // domain) is parked in its own output row, which this workgroup alone touches,
 // and read back while d2 is inverse transformed.
-template <int L>
+template <int L, bool LZ>
 __global__ __launch_bounds__(Geo<L>::T) void k_square_tensor(DevCtx c, const uint64_t *__restrict__ a,
                                                             const uint64_t *__restrict__ E,
                                                             uint64_t *__restrict__ Dt) {
@@ -316,7 +335,7 @@ __global__ __launch_bounds__(Geo<L>::T) void k_square_tensor(DevCtx c, const uin
     const size_t item = blockIdx.y;
     const int k = c.k, K = c.K;
     const PrimeConst &P = c.pc[limb];
-    const uint64_t q = P.q, qi = P.qinv_neg, q2 = q << 1, q4 = q << 2;
+    const uint64_t q = P.q, qi = P.qinv_neg, one_p = P.one_p;
     const Tw *tw = c.tw + (size_t)limb * n;
     const Tw *itw = c.itw + (size_t)limb * n;
     const uint64_t *src0, *src1;
@@ -337,22 +356,22 @@ __global__ __launch_bounds__(Geo<L>::T) void k_square_tensor(DevCtx c, const uin
 #pragma unroll
     for (int s = 0; s < 16; s++) y[s] = src0[natural_index<L>(t1, s)];
     asm volatile("" ::: "memory");
-    ntt_fwd_regs<L>(x, lds, tid, tw, q);  // A1
+    ntt_fwd_regs<L, 4, !LZ>(x, lds, tid, tw, q);  // A1
 #pragma unroll
-    for (int s = 0; s < 16; s++) x[s] = csub(csub(x[s], q4), q2);  // [0, 2q)
-    ntt_fwd_regs<L>(y, lds, tid, tw, q);  // A0
+    for (int s = 0; s < 16; s++) x[s] = fwd_operand<LZ>(x[s], q, one_p);
+    ntt_fwd_regs<L, 4, !LZ>(y, lds, tid, tw, q);  // A0
     // d1 = 2 A0 A1 parked in d1; d0 = A0^2 in y, d2 = A1^2 in x (all below 4q)
     const uint32_t t2 = fresh(tid);
 #pragma unroll
     for (int s = 0; s < 16; s++) {
-        const uint64_t a0 = csub(csub(y[s], q4), q2);
+        const uint64_t a0 = fwd_operand<LZ>(y[s], q, one_p);
         const uint64_t m = mont_mul_lazy(a0, x[s], q, qi);
         d1[bitrev_layout_index<L>(t2, s)] = m + m;
         y[s] = mont_mul_lazy(a0, a0, q, qi);
         x[s] = mont_mul_lazy(x[s], x[s], q, qi);
     }
     asm volatile("" ::: "memory");
-    ntt_inv_regs<L>(y, lds, tid, itw, q);
+    ntt_inv_regs<L, 4, LZ>(y, lds, tid, itw, q);
     const uint32_t t3 = fresh(tid);
 #pragma unroll
     for (int s = 0; s < 16; s++) d0[natural_index<L>(t3, s)] = mul_shoup(y[s], P.ninvm, P.ninvm_p, q);
@@ -361,11 +380,11 @@ __global__ __launch_bounds__(Geo<L>::T) void k_square_tensor(DevCtx c, const uin
 #pragma unroll
     for (int s = 0; s < 16; s++) y[s] = d1[bitrev_layout_index<L>(t4, s)];
     asm volatile("" ::: "memory");
-    ntt_inv_regs<L>(x, lds, tid, itw, q);
+    ntt_inv_regs<L, 4, LZ>(x, lds, tid, itw, q);
     const uint32_t t5 = fresh(tid);
 #pragma unroll
     for (int s = 0; s < 16; s++) d2[natural_index<L>(t5, s)] = mul_shoup(x[s], P.ninvm, P.ninvm_p, q);
-    ntt_inv_regs<L>(y, lds, tid, itw, q);
+    ntt_inv_regs<L, 4, LZ>(y, lds, tid, itw, q);
     const uint32_t t6 = fresh(tid);
 #pragma unroll
     for (int s = 0; s < 16; s++) d1[natural_index<L>(t6, s)] = mul_shoup(y[s], P.ninvm, P.ninvm_p, q);
@@ -382,7 +401,8 @@ __global__ __launch_bounds__(Geo<L>::T) void k_square_tensor(DevCtx c, const uin
 // share of digit i + 1 into its own LDS block (prefetch_row_lds).  LAZY: every
 // q_j is below 2^64 / (4 (L + 1)), so the digit transforms skip the
 // conditional subtractions (digits below 4 (L + 1) q_j, still a valid
-// Montgomery operand against key entries below q_j).
+// Montgomery operand against key entries below q_j) and the inverse transforms
+// half of theirs (accumulators below 8q_j).
 template <int L, bool LAZY>
 __global__ __launch_bounds__(Geo<L>::T) void k_relin_fused(DevCtx c, const uint64_t *__restrict__ C2,
                                                           const uint64_t *__restrict__ rlk,
@@ -459,32 +479,32 @@ __global__ __launch_bounds__(Geo<L>::T) void k_relin_fused(DevCtx c, const uint6
     }
     uint64_t *o0 = out + (item * 2 * k + j) * (size_t)n;
     uint64_t *o1 = out + ((item * 2 + 1) * k + j) * (size_t)n;
-    ntt_inv_regs<L>(acc0, lds, tid, c.itw + (size_t)j * n, q);
+    ntt_inv_regs<L, 4, LAZY>(acc0, lds, tid, c.itw + (size_t)j * n, q);
     const uint32_t t2 = fresh(tid);
 #pragma unroll
     for (int s = 0; s < 16; s++) {
         const uint32_t idx = natural_index<L>(t2, s);
-        o0[idx] = add_mod(csub(csub(acc0[s], q2), q), o0[idx], q);
+        o0[idx] = add_mod(canon8(acc0[s], q), o0[idx], q);
     }
-    ntt_inv_regs<L>(acc1, lds, tid, c.itw + (size_t)j * n, q);
+    ntt_inv_regs<L, 4, LAZY>(acc1, lds, tid, c.itw + (size_t)j * n, q);
     const uint32_t t3 = fresh(tid);
 #pragma unroll
     for (int s = 0; s < 16; s++) {
         const uint32_t idx = natural_index<L>(t3, s);
-        o1[idx] = add_mod(csub(csub(acc1[s], q2), q), o1[idx], q);
+        o1[idx] = add_mod(canon8(acc1[s], q), o1[idx], q);
     }
 }
 
 template <int L>
 struct NttL {
-    template <bool FWD>
+    template <bool FWD, bool LZ>
     static hipError_t rows_dir(const DevCtx &c, uint64_t *data, size_t nrows, int kmod, int off, int mode,
                                hipStream_t s) {
         // one resident pass of workgroups over the chip (row loop inside)
         static int per_chip = 0;
         if (per_chip == 0) {
             int nb = 0, dev = 0, cus = 0;
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ntt_rows<L, FWD>, Geo<L>::T, 0) !=
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ntt_rows<L, FWD, LZ>, Geo<L>::T, 0) !=
                     hipSuccess ||
                 hipGetDevice(&dev) != hipSuccess ||
                 hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
@@ -493,41 +513,59 @@ struct NttL {
             per_chip = nb * cus;
         }
         const size_t grid = nrows < (size_t)per_chip ? nrows : (size_t)per_chip;
-        hipLaunchKernelGGL((k_ntt_rows<L, FWD>), dim3((unsigned)grid), dim3(Geo<L>::T), 0, s, c, data, nrows,
-                           kmod, off, mode);
+        hipLaunchKernelGGL((k_ntt_rows<L, FWD, LZ>), dim3((unsigned)grid), dim3(Geo<L>::T), 0, s, c, data,
+                           nrows, kmod, off, mode);
         return hipGetLastError();
     }
     static hipError_t rows(const DevCtx &c, uint64_t *data, size_t nrows, int kmod, int off, int mode,
                            hipStream_t s) {
-        if (mode == NTT_FWD || mode == NTT_FWD_NINVM) return rows_dir<true>(c, data, nrows, kmod, off, mode, s);
-        return rows_dir<false>(c, data, nrows, kmod, off, mode, s);
+        const bool fwd = mode == NTT_FWD || mode == NTT_FWD_NINVM;
+        const uint64_t span = (kmod >= 64 ? ~0ull : (1ull << kmod) - 1) << off;
+        if ((c.lazy_limbs & span) == span)
+            return fwd ? rows_dir<true, true>(c, data, nrows, kmod, off, mode, s)
+                       : rows_dir<false, true>(c, data, nrows, kmod, off, mode, s);
+        return fwd ? rows_dir<true, false>(c, data, nrows, kmod, off, mode, s)
+                   : rows_dir<false, false>(c, data, nrows, kmod, off, mode, s);
     }
     static hipError_t fwd_ext(const DevCtx &c, const uint64_t *a, const uint64_t *b, uint64_t *E,
                               int npoly, size_t items, hipStream_t s) {
-        hipLaunchKernelGGL(k_fwd_ext<L>, dim3(c.K, npoly, (unsigned)items), dim3(Geo<L>::T), 0, s, c, a,
-                           b, E, npoly);
+        const dim3 grid(c.K, npoly, (unsigned)items);
+        if (c.lazy_all)
+            hipLaunchKernelGGL((k_fwd_ext<L, true>), grid, dim3(Geo<L>::T), 0, s, c, a, b, E, npoly);
+        else
+            hipLaunchKernelGGL((k_fwd_ext<L, false>), grid, dim3(Geo<L>::T), 0, s, c, a, b, E, npoly);
         return hipGetLastError();
+    }
+    template <bool SQ>
+    static void tensor_sq(const DevCtx &c, const uint64_t *E, uint64_t *Dt, size_t items, hipStream_t s) {
+        const dim3 grid(c.K, 3, (unsigned)items);
+        if (c.lazy_all)
+            hipLaunchKernelGGL((k_tensor_intt<L, SQ, true>), grid, dim3(Geo<L>::T), 0, s, c, E, Dt);
+        else
+            hipLaunchKernelGGL((k_tensor_intt<L, SQ, false>), grid, dim3(Geo<L>::T), 0, s, c, E, Dt);
     }
     static hipError_t tensor(const DevCtx &c, const uint64_t *E, uint64_t *Dt, bool sq, size_t items,
                              hipStream_t s) {
-        if (sq)
-            hipLaunchKernelGGL((k_tensor_intt<L, true>), dim3(c.K, 3, (unsigned)items), dim3(Geo<L>::T),
-                               0, s, c, E, Dt);
-        else
-            hipLaunchKernelGGL((k_tensor_intt<L, false>), dim3(c.K, 3, (unsigned)items),
-                               dim3(Geo<L>::T), 0, s, c, E, Dt);
+        if (sq) tensor_sq<true>(c, E, Dt, items, s);
+        else tensor_sq<false>(c, E, Dt, items, s);
         return hipGetLastError();
     }
     static hipError_t mul_tensor(const DevCtx &c, const uint64_t *a, const uint64_t *b, const uint64_t *E,
                                  uint64_t *Dt, size_t items, hipStream_t s) {
-        hipLaunchKernelGGL(k_mul_tensor<L>, dim3(c.K, (unsigned)items), dim3(Geo<L>::T), 0, s, c, a, b, E,
-                           Dt);
+        const dim3 grid(c.K, (unsigned)items);
+        if (c.lazy_all)
+            hipLaunchKernelGGL((k_mul_tensor<L, true>), grid, dim3(Geo<L>::T), 0, s, c, a, b, E, Dt);
+        else
+            hipLaunchKernelGGL((k_mul_tensor<L, false>), grid, dim3(Geo<L>::T), 0, s, c, a, b, E, Dt);
         return hipGetLastError();
     }
     static hipError_t square_tensor(const DevCtx &c, const uint64_t *a, const uint64_t *E, uint64_t *Dt,
                                     size_t items, hipStream_t s) {
-        hipLaunchKernelGGL(k_square_tensor<L>, dim3(c.K, (unsigned)items), dim3(Geo<L>::T), 0, s, c, a, E,
-                           Dt);
+        const dim3 grid(c.K, (unsigned)items);
+        if (c.lazy_all)
+            hipLaunchKernelGGL((k_square_tensor<L, true>), grid, dim3(Geo<L>::T), 0, s, c, a, E, Dt);
+        else
+            hipLaunchKernelGGL((k_square_tensor<L, false>), grid, dim3(Geo<L>::T), 0, s, c, a, E, Dt);
         return hipGetLastError();
     }
     static hipError_t relin_fused(const DevCtx &c, const uint64_t *C2, const uint64_t *rlk, uint64_t *out,

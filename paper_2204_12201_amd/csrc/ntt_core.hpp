@@ -23,8 +23,11 @@
 // [0, 8q), inverse values in [0, 4q), so primes must stay below 2^61.  For
 // primes below 2^64 / (4 (L + 1)) the forward transform can also drop the
 // conditional subtraction (REDUCE = false): a stage then raises the bound by at
-// most 4q, and a row entering below 4q leaves below 4 (L + 1) q.  Twiddles are
-// (w, floor(w 2^64 / q)) pairs.
+// most 4q, and a row entering below 4q leaves below 4 (L + 1) q.  For primes
+// below 2^60 the inverse can skip half of its conditional subtractions (SEMI):
+// a sum output may stay below 8q, and is only reduced when both of its inputs
+// were sums themselves (see gs_bfly_semi).  Twiddles are (w, floor(w 2^64 / q))
+// pairs.
 #pragma once
 #include <hip/hip_runtime.h>
 #include "modarith.hpp"
@@ -98,6 +101,20 @@ __device__ __forceinline__ void gs_bfly(uint64_t &X, uint64_t &Y, uint64_t w, ui
     Y = mul_shoup_lazy4(x - y + q4, w, wp, q);
 }
 
+// Inverse butterfly with a two-class bound (16q < 2^64): X, Y below b, where b
+// = 8q if they are sum outputs of the previous level (BIG) and b = 4q
+// otherwise.  The sum x + y is below 2b: reduced by 8q only when BIG, so every
+// sum output stays below 8q; the difference x - y + b is below 2b and its
+// product lands in [0, 4q).
+template <bool BIG>
+__device__ __forceinline__ void gs_bfly_semi(uint64_t &X, uint64_t &Y, uint64_t w, uint64_t wp,
+                                             uint64_t q, uint64_t b) {
+    uint64_t x = X, y = Y;
+    const uint64_t s = x + y;
+    X = BIG ? csub(s, b) : s;
+    Y = mul_shoup_lazy4(x - y + b, w, wp, q);
+}
+
 // Twiddle i.  UNIFORM: the index is the same in every lane of the wave; the
 // table is then read through the constant address space, which lets the
 // compiler use scalar loads (merged into wide ones, one wait per pass) instead
@@ -140,12 +157,17 @@ __device__ __forceinline__ void fwd_pass(uint64_t (&x)[1 << LE], int tid, const 
     }
 }
 
-template <int L, int LE, int P>
+// SEMI: the level of bit b (b = r - 1 - u) pairs elements whose lower bits
+// agree, so both were sum outputs of the previous level exactly when bit b - 1
+// of their slot is 0.  The first level of a pass takes the bound its input
+// had: below 4q for the transform's input, below 8q after an exchange.
+template <int L, int LE, int P, bool SEMI>
 __device__ __forceinline__ void inv_pass(uint64_t (&x)[1 << LE], int tid, const Tw *__restrict__ tw,
                                          uint64_t q) {
     constexpr int r = Geo<L, LE>::R(P), lo = Geo<L, LE>::LO(P), LT = Geo<L, LE>::LT;
     constexpr int R = 1 << r, G = (1 << LE) >> r, l0 = LE * P;
-    const uint64_t q4 = q << 2;
+    constexpr bool FIRST = P == Geo<L, LE>::NPASS - 1;
+    const uint64_t q4 = q << 2, q8 = q << 3;
 #pragma unroll
     for (int g = 0; g < G; g++) {
         const uint32_t F = fixed_bits<L, LE, P>((uint32_t)tid, (uint32_t)g);
@@ -160,7 +182,14 @@ __device__ __forceinline__ void inv_pass(uint64_t (&x)[1 << LE], int tid, const 
 #pragma unroll
                 for (int w = 0; w < half; w++) {
                     const int e0 = (v << (r - u)) | w;
-                    gs_bfly(x[g * R + e0], x[g * R + e0 + half], W.w, W.wp, q, q4);
+                    uint64_t &X = x[g * R + e0], &Y = x[g * R + e0 + half];
+                    if constexpr (SEMI) {
+                        const bool big = u == r - 1 ? !FIRST : ((w >> (r - 2 - u)) & 1) == 0;
+                        if (big) gs_bfly_semi<true>(X, Y, W.w, W.wp, q, q8);
+                        else gs_bfly_semi<false>(X, Y, W.w, W.wp, q, q4);
+                    } else {
+                        gs_bfly(X, Y, W.w, W.wp, q, q4);
+                    }
                 }
             }
         }
@@ -227,13 +256,13 @@ __device__ __forceinline__ void fwd_from(uint64_t (&x)[1 << LE], uint64_t *lds, 
     }
 }
 
-template <int L, int LE, int P>
+template <int L, int LE, int P, bool SEMI>
 __device__ __forceinline__ void inv_from(uint64_t (&x)[1 << LE], uint64_t *lds, int tid,
                                          const Tw *__restrict__ tw, uint64_t q) {
-    inv_pass<L, LE, P>(x, tid, tw, q);
+    inv_pass<L, LE, P, SEMI>(x, tid, tw, q);
     if constexpr (P > 0) {
         exchange<L, LE, P, P - 1>(lds, x, tid);
-        inv_from<L, LE, P - 1>(x, lds, tid, tw, q);
+        inv_from<L, LE, P - 1, SEMI>(x, lds, tid, tw, q);
     }
 }
 
@@ -248,11 +277,12 @@ __device__ __forceinline__ void ntt_fwd_regs(uint64_t (&x)[1 << LE], uint64_t *l
 }
 
 // Inverse transform (without the 1/n factor) of a row held in last-pass
-// layout, values < 4q.  Leaves natural order in pass-0 layout, values < 4q.
-template <int L, int LE = 4>
+// layout, values < 4q.  Leaves natural order in pass-0 layout, values < 4q,
+// or < 8q with SEMI (for q < 2^60).
+template <int L, int LE = 4, bool SEMI = false>
 __device__ __forceinline__ void ntt_inv_regs(uint64_t (&x)[1 << LE], uint64_t *lds, int tid,
                                              const Tw *__restrict__ tw, uint64_t q) {
-    inv_from<L, LE, Geo<L, LE>::NPASS - 1>(x, lds, (int)fresh(tid), tw, q);
+    inv_from<L, LE, Geo<L, LE>::NPASS - 1, SEMI>(x, lds, (int)fresh(tid), tw, q);
 }
 
 // Global index helpers for the two register layouts.

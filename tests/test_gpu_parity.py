@@ -135,12 +135,13 @@ def test_mul_relin_small_all_words(dev, n, bits, k, t, enc):
         assert (sq[j] == want_sq).all() and (sq2[j] == want_sq).all(), f"square {j}"
 
 
-@pytest.mark.parametrize("n,bits,k", [(1024, 36, 3), (2048, 40, 2)])
+@pytest.mark.parametrize("n,bits,k", [(1024, 36, 3), (2048, 40, 2), (1024, 60, 2)])
 def test_mul_relin_fused_batch_all_words(dev, n, bits, k):
     """Batches large enough for the fused product kernel (and squaring): every
     word of every product against the oracle.  n = 1024 runs the transforms
     with one wave per row (and the LDS prefetch inside that wave), n = 2048
-    with two."""
+    with two.  60-bit primes take the transforms with every conditional
+    subtraction (the others skip them)."""
     qs = bfv.ntt_primes(n, bits, k)
     P, km, pk, rlk, ctx, rlk_d = setup(n, qs, 65537, "slots", 13)
     K = k + ctx.aux_primes
