@@ -321,9 +321,9 @@ __global__ __launch_bounds__(Geo<L>::T) void k_mul_tensor(DevCtx c, const uint64
 // it transforms a0 and a1 (Q limbs straight from the ciphertext, P limbs from
 // the lift in E), then forms d0 = a0^2, d1 = 2 a0 a1, d2 = a1^2 (Montgomery
 // products) and inverse transforms each into Dt[item][comp][l].  Two rows
-// live in registers: a0 is loaded while a1 is transformed; d1 (transform
-// domain) is parked in its own output row, which this workgroup alone touches,
-// and read back while d2 is inverse transformed.
+// live in registers: a0 and a1 are transformed side by side (one twiddle load
+// for both); d1 (transform domain) is parked in its own output row, which this
+// workgroup alone touches, and read back while d2 is inverse transformed.
 template <int L, bool LZ>
 __global__ __launch_bounds__(Geo<L>::T) void k_square_tensor(DevCtx c, const uint64_t *__restrict__ a,
                                                             const uint64_t *__restrict__ E,
@@ -356,19 +356,17 @@ __global__ __launch_bounds__(Geo<L>::T) void k_square_tensor(DevCtx c, const uin
 #pragma unroll
     for (int s = 0; s < 16; s++) y[s] = src0[natural_index<L>(t1, s)];
     asm volatile("" ::: "memory");
-    ntt_fwd_regs<L, 4, !LZ>(x, lds, tid, tw, q);  // A1
-#pragma unroll
-    for (int s = 0; s < 16; s++) x[s] = fwd_operand<LZ>(x[s], q, one_p);
-    ntt_fwd_regs<L, 4, !LZ>(y, lds, tid, tw, q);  // A0
+    ntt_fwd_regs2<L, 4, !LZ>(x, y, lds, tid, tw, q);  // A1, A0
     // d1 = 2 A0 A1 parked in d1; d0 = A0^2 in y, d2 = A1^2 in x (all below 4q)
     const uint32_t t2 = fresh(tid);
 #pragma unroll
     for (int s = 0; s < 16; s++) {
+        const uint64_t a1 = fwd_operand<LZ>(x[s], q, one_p);
         const uint64_t a0 = fwd_operand<LZ>(y[s], q, one_p);
-        const uint64_t m = mont_mul_lazy(a0, x[s], q, qi);
+        const uint64_t m = mont_mul_lazy(a0, a1, q, qi);
         d1[bitrev_layout_index<L>(t2, s)] = m + m;
         y[s] = mont_mul_lazy(a0, a0, q, qi);
-        x[s] = mont_mul_lazy(x[s], x[s], q, qi);
+        x[s] = mont_mul_lazy(a1, a1, q, qi);
     }
     asm volatile("" ::: "memory");
     ntt_inv_regs<L, 4, LZ>(y, lds, tid, itw, q);

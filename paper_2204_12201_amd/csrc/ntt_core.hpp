@@ -285,6 +285,117 @@ __device__ __forceinline__ void ntt_inv_regs(uint64_t (&x)[1 << LE], uint64_t *l
     inv_from<L, LE, Geo<L, LE>::NPASS - 1, SEMI>(x, lds, (int)fresh(tid), tw, q);
 }
 
+// ---- two rows of the same prime at once --------------------------------
+// The passes below transform two rows held in registers side by side: every
+// twiddle is loaded once for both, and the two rows' butterflies give the
+// scheduler independent work.  The exchanges stay one row at a time (the LDS
+// holds one row).
+
+template <int L, int LE, int P, bool REDUCE>
+__device__ __forceinline__ void fwd_pass2(uint64_t (&x)[1 << LE], uint64_t (&y)[1 << LE], int tid,
+                                          const Tw *__restrict__ tw, uint64_t q) {
+    constexpr int r = Geo<L, LE>::R(P), lo = Geo<L, LE>::LO(P), LT = Geo<L, LE>::LT;
+    constexpr int R = 1 << r, G = (1 << LE) >> r, l0 = LE * P;
+    const uint64_t q4 = q << 2;
+#pragma unroll
+    for (int g = 0; g < G; g++) {
+        const uint32_t F = fixed_bits<L, LE, P>((uint32_t)tid, (uint32_t)g);
+        uint32_t H = F >> lo;
+        if constexpr (lo >= 6 || LT <= lo) H = __builtin_amdgcn_readfirstlane(H);
+#pragma unroll
+        for (int u = 0; u < r; u++) {
+            const int half = R >> (u + 1);
+#pragma unroll
+            for (int v = 0; v < (1 << u); v++) {
+                const Tw W = load_tw<(lo >= 6 || LT <= lo)>(tw, (1u << (l0 + u)) + (H << u) + v);
+#pragma unroll
+                for (int w = 0; w < half; w++) {
+                    const int e0 = (v << (r - u)) | w;
+                    ct_bfly<REDUCE>(x[g * R + e0], x[g * R + e0 + half], W.w, W.wp, q, q4);
+                    ct_bfly<REDUCE>(y[g * R + e0], y[g * R + e0 + half], W.w, W.wp, q, q4);
+                }
+            }
+        }
+    }
+}
+
+template <int L, int LE, int P, bool SEMI>
+__device__ __forceinline__ void inv_pass2(uint64_t (&x)[1 << LE], uint64_t (&y)[1 << LE], int tid,
+                                          const Tw *__restrict__ tw, uint64_t q) {
+    constexpr int r = Geo<L, LE>::R(P), lo = Geo<L, LE>::LO(P), LT = Geo<L, LE>::LT;
+    constexpr int R = 1 << r, G = (1 << LE) >> r, l0 = LE * P;
+    constexpr bool FIRST = P == Geo<L, LE>::NPASS - 1;
+    const uint64_t q4 = q << 2, q8 = q << 3;
+#pragma unroll
+    for (int g = 0; g < G; g++) {
+        const uint32_t F = fixed_bits<L, LE, P>((uint32_t)tid, (uint32_t)g);
+        uint32_t H = F >> lo;
+        if constexpr (lo >= 6 || LT <= lo) H = __builtin_amdgcn_readfirstlane(H);
+#pragma unroll
+        for (int u = r - 1; u >= 0; u--) {
+            const int half = R >> (u + 1);
+#pragma unroll
+            for (int v = 0; v < (1 << u); v++) {
+                const Tw W = load_tw<(lo >= 6 || LT <= lo)>(tw, (1u << (l0 + u)) + (H << u) + v);
+#pragma unroll
+                for (int w = 0; w < half; w++) {
+                    const int e0 = (v << (r - u)) | w;
+                    uint64_t &X0 = x[g * R + e0], &Y0 = x[g * R + e0 + half];
+                    uint64_t &X1 = y[g * R + e0], &Y1 = y[g * R + e0 + half];
+                    if constexpr (SEMI) {
+                        const bool big = u == r - 1 ? !FIRST : ((w >> (r - 2 - u)) & 1) == 0;
+                        if (big) {
+                            gs_bfly_semi<true>(X0, Y0, W.w, W.wp, q, q8);
+                            gs_bfly_semi<true>(X1, Y1, W.w, W.wp, q, q8);
+                        } else {
+                            gs_bfly_semi<false>(X0, Y0, W.w, W.wp, q, q4);
+                            gs_bfly_semi<false>(X1, Y1, W.w, W.wp, q, q4);
+                        }
+                    } else {
+                        gs_bfly(X0, Y0, W.w, W.wp, q, q4);
+                        gs_bfly(X1, Y1, W.w, W.wp, q, q4);
+                    }
+                }
+            }
+        }
+    }
+}
+
+template <int L, int LE, int P, bool REDUCE>
+__device__ __forceinline__ void fwd_from2(uint64_t (&x)[1 << LE], uint64_t (&y)[1 << LE], uint64_t *lds,
+                                          int tid, const Tw *__restrict__ tw, uint64_t q) {
+    fwd_pass2<L, LE, P, REDUCE>(x, y, tid, tw, q);
+    if constexpr (P + 1 < Geo<L, LE>::NPASS) {
+        exchange<L, LE, P, P + 1>(lds, x, tid);
+        exchange<L, LE, P, P + 1>(lds, y, tid);
+        fwd_from2<L, LE, P + 1, REDUCE>(x, y, lds, tid, tw, q);
+    }
+}
+
+template <int L, int LE, int P, bool SEMI>
+__device__ __forceinline__ void inv_from2(uint64_t (&x)[1 << LE], uint64_t (&y)[1 << LE], uint64_t *lds,
+                                          int tid, const Tw *__restrict__ tw, uint64_t q) {
+    inv_pass2<L, LE, P, SEMI>(x, y, tid, tw, q);
+    if constexpr (P > 0) {
+        exchange<L, LE, P, P - 1>(lds, x, tid);
+        exchange<L, LE, P, P - 1>(lds, y, tid);
+        inv_from2<L, LE, P - 1, SEMI>(x, y, lds, tid, tw, q);
+    }
+}
+
+// ntt_fwd_regs / ntt_inv_regs of two rows of one prime.
+template <int L, int LE = 4, bool REDUCE = true>
+__device__ __forceinline__ void ntt_fwd_regs2(uint64_t (&x)[1 << LE], uint64_t (&y)[1 << LE], uint64_t *lds,
+                                              int tid, const Tw *__restrict__ tw, uint64_t q) {
+    fwd_from2<L, LE, 0, REDUCE>(x, y, lds, (int)fresh(tid), tw, q);
+}
+
+template <int L, int LE = 4, bool SEMI = false>
+__device__ __forceinline__ void ntt_inv_regs2(uint64_t (&x)[1 << LE], uint64_t (&y)[1 << LE], uint64_t *lds,
+                                              int tid, const Tw *__restrict__ tw, uint64_t q) {
+    inv_from2<L, LE, Geo<L, LE>::NPASS - 1, SEMI>(x, y, lds, (int)fresh(tid), tw, q);
+}
+
 // Global index helpers for the two register layouts.
 template <int L, int LE = 4>
 __device__ __forceinline__ uint32_t natural_index(uint32_t tid, int s) {  // pass-0 layout, slot s
