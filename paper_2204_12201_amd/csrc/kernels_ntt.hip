@@ -369,7 +369,7 @@ __global__ __launch_bounds__(Geo<L>::T) void k_square_tensor(DevCtx c, const uin
         x[s] = mont_mul_lazy(a1, a1, q, qi);
     }
     asm volatile("" ::: "memory");
-    ntt_inv_regs<L, 4, LZ>(y, lds, tid, itw, q);
+    ntt_inv_regs2<L, 4, LZ>(y, x, lds, tid, itw, q);
     const uint32_t t3 = fresh(tid);
 #pragma unroll
     for (int s = 0; s < 16; s++) d0[natural_index<L>(t3, s)] = mul_shoup(y[s], P.ninvm, P.ninvm_p, q);
@@ -377,11 +377,10 @@ __global__ __launch_bounds__(Geo<L>::T) void k_square_tensor(DevCtx c, const uin
     const uint32_t t4 = fresh(tid);
 #pragma unroll
     for (int s = 0; s < 16; s++) y[s] = d1[bitrev_layout_index<L>(t4, s)];
-    asm volatile("" ::: "memory");
-    ntt_inv_regs<L, 4, LZ>(x, lds, tid, itw, q);
     const uint32_t t5 = fresh(tid);
 #pragma unroll
     for (int s = 0; s < 16; s++) d2[natural_index<L>(t5, s)] = mul_shoup(x[s], P.ninvm, P.ninvm_p, q);
+    asm volatile("" ::: "memory");
     ntt_inv_regs<L, 4, LZ>(y, lds, tid, itw, q);
     const uint32_t t6 = fresh(tid);
 #pragma unroll
