@@ -24,6 +24,9 @@ paper's introduction):
   repeated-squaring pow; bit j = sum over c in [1, t) with bit j of c set of
   eq_c (the eq_c are one-hot, so the bit-level sum has no carries).
 * Recompose (paper, Section 3.2.1, Horner listing): r = b_{S-1}; r = r + r + b_i.
+* Weighted sums (the case study's modular stage, Section 4.4): out[m] =
+  sum_j w_mj ct_j mod q.  Gates (Section 3.1's expressions over {0, 1}), and
+  from them a ripple comparison and a one-hot argmax.
 
 Where the paper is silent this oracle takes: Delta = floor(q/t); one key
 switching digit per RNS prime, [C2]_{q_i} in [0, q_i), with the CRT idempotent
@@ -463,6 +466,87 @@ def bridge_to_bits(P: Params, ct_x, rlk, nbits: int, counter: Counter | None = N
     Returns (bits [nbits][2][k][n], eqs [t][2][k][n])."""
     eqs = [bridge_eq(P, ct_x, rlk, c, counter) for c in range(P.t)]
     return bridge_bits(P, eqs, nbits), np.stack(eqs)
+
+
+# ----------------------------------------------------------------------------
+# Modular linear stage and the bit-level side
+# ----------------------------------------------------------------------------
+
+def weighted_sum(P: Params, cts, W) -> np.ndarray:
+    """out[m] = sum_j W[m][j] cts[j] (mod q), word by word: the integer-weighted
+    sums of the case study's modular stage (paper Section 4.4).  Plain
+    definition: Python integers, reduced once per output."""
+    X = np.asarray(cts, dtype=np.uint64).astype(object)
+    out = np.zeros((len(W), 2, P.k, P.n), dtype=np.uint64)
+    for m, row in enumerate(W):
+        acc = np.zeros((2, P.k, P.n), dtype=object)
+        for j, w in enumerate(row):
+            if int(w):
+                acc = acc + int(w) * X[j]
+        for i, qi in enumerate(P.qs):
+            out[m, :, i, :] = np.array([[int(v) % qi for v in acc[l, i]] for l in range(2)],
+                                       dtype=np.uint64)
+    return out
+
+
+def gate(P: Params, rlk, op: str, a, b=None, c=None, counter: Counter | None = None):
+    """The paper's logic-gate expressions over encrypted bits (Section 3.1):
+    AND = ab, NAND = 1 - ab, OR = a + b - ab, NOR = 1 - OR, XOR = a + b - 2ab,
+    XNOR = 1 - XOR, NOT = 1 - a, MUX(a, b, c) = a(b - c) + c, each product one
+    mul_relin, in this evaluation order."""
+    def one_minus(x):
+        return add_plain(P, neg(P, x), 1)
+    if op == "NOT":
+        return one_minus(a)
+    if op == "MUX":
+        return add(P, mul_relin(P, a, sub(P, b, c), rlk, counter), c)
+    p = mul_relin(P, a, b, rlk, counter)
+    if op == "AND":
+        return p
+    if op == "NAND":
+        return one_minus(p)
+    o = sub(P, add(P, a, b), p)
+    if op == "OR":
+        return o
+    if op == "NOR":
+        return one_minus(o)
+    x = sub(P, o, p)
+    if op == "XOR":
+        return x
+    if op == "XNOR":
+        return one_minus(x)
+    raise ValueError(op)
+
+
+def less_than(P: Params, rlk, a, b, counter: Counter | None = None):
+    """[a < b] for bit vectors a, b (least significant first) by the ripple
+    circuit of the gates: p = a_i b_i, d = b_i - p (NOT a_i AND b_i),
+    e = 1 - ((a_i + b_i) - p - p) (XNOR); lt = d_0, then lt = MUX(e, lt, d)."""
+    lt = None
+    for i in range(len(a)):
+        p = mul_relin(P, a[i], b[i], rlk, counter)
+        d = sub(P, b[i], p)
+        if i == 0:
+            lt = d
+            continue
+        e = add_plain(P, neg(P, sub(P, sub(P, add(P, a[i], b[i]), p), p)), 1)
+        lt = add(P, mul_relin(P, e, sub(P, lt, d), rlk, counter), d)
+    return lt
+
+
+def argmax(P: Params, rlk, scores, counter: Counter | None = None):
+    """One-hot argmax of encrypted unsigned scores (ties to the lower class):
+    for every pair a < b, l = [s_a < s_b]; class a takes the factor 1 - l and
+    class b the factor l, multiplied in as they come."""
+    ncls = len(scores)
+    out = [None] * ncls
+    for a in range(ncls):
+        for b in range(a + 1, ncls):
+            l = less_than(P, rlk, scores[a], scores[b], counter)
+            na = add_plain(P, neg(P, l), 1)
+            out[a] = na if out[a] is None else mul_relin(P, out[a], na, rlk, counter)
+            out[b] = l if out[b] is None else mul_relin(P, out[b], l, rlk, counter)
+    return out
 
 
 def recompose(P: Params, bits) -> np.ndarray:

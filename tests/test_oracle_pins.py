@@ -483,3 +483,108 @@ def test_streams_are_deterministic():
     b = inputs.key_material(64, [7681], 5)
     for key in a:
         assert (a[key] == b[key]).all()
+
+
+# ------------------------------------- modular linear stage, bit-level side --
+
+def _slots_setup(seed, k=4):
+    n, t = 64, 257
+    P = bfv.Params(n, bfv.ntt_primes(n, 55, k), t, "slots")
+    km, pk, rlk = keys_small(P, seed=seed)
+    return P, km, pk, rlk
+
+
+def _enc_slots(P, pk, vecs, seed):
+    r = inputs.encryption_randomness(P.n, len(vecs), seed)
+    return [bfv.encrypt(P, pk, bfv.encode(P, v), r["u"][j], r["e"][j]) for j, v in enumerate(vecs)]
+
+
+def _dec_slots(P, km, ct):
+    return [int(v) for v in bfv.decode(P, bfv.decrypt(P, km["s"], ct))]
+
+
+def test_weighted_sum_decrypts_to_the_weighted_plain_sum():
+    """Dec(sum_j w_j Enc(m_j)) = sum_j w_j m_j mod t in every slot, weights of
+    both signs, including zero rows."""
+    P, km, pk, rlk = _slots_setup(31)
+    rng = random.Random(5)
+    msgs = [[rng.randrange(3) for _ in range(P.n)] for _ in range(6)]
+    cts = _enc_slots(P, pk, msgs, 31)
+    W = [[rng.randint(-8, 8) for _ in range(6)] for _ in range(4)] + [[0] * 6]
+    out = bfv.weighted_sum(P, cts, W)
+    for m, row in enumerate(W):
+        want = [sum(w * msgs[j][s] for j, w in enumerate(row)) % P.t for s in range(P.n)]
+        assert _dec_slots(P, km, out[m]) == want, f"row {m}"
+    assert (out[-1] == 0).all()
+
+
+def test_weighted_sum_equals_repeated_additions():
+    """Small weights: the words equal those of |w| additions or subtractions
+    of each input (the oracle's add/sub, an independent code path)."""
+    P = tiny_params(n=16, bits=30, k=2)
+    rng = random.Random(2)
+    cts = [rand_ct(P, rng) for _ in range(3)]
+    W = [[2, -1, 0], [-2, 1, 1], [0, 0, 0]]
+    got = bfv.weighted_sum(P, cts, W)
+    for m, row in enumerate(W):
+        acc = np.zeros((2, P.k, P.n), dtype=np.uint64)
+        for j, w in enumerate(row):
+            for _ in range(abs(w)):
+                acc = bfv.add(P, acc, cts[j]) if w > 0 else bfv.sub(P, acc, cts[j])
+        assert (got[m] == acc).all(), f"row {m}"
+
+
+def test_gates_truth_tables():
+    """Every gate of the paper's list on all input combinations (slot-packed):
+    decryptions equal the Boolean functions."""
+    P, km, pk, rlk = _slots_setup(32)
+    combos = [(a, b, c) for a in (0, 1) for b in (0, 1) for c in (0, 1)]
+    va = [combos[s % 8][0] for s in range(P.n)]
+    vb = [combos[s % 8][1] for s in range(P.n)]
+    vc = [combos[s % 8][2] for s in range(P.n)]
+    A, B, C = _enc_slots(P, pk, [va, vb, vc], 32)
+    table = {
+        "AND": lambda a, b, c: a & b, "NAND": lambda a, b, c: 1 - (a & b),
+        "OR": lambda a, b, c: a | b, "NOR": lambda a, b, c: 1 - (a | b),
+        "XOR": lambda a, b, c: a ^ b, "XNOR": lambda a, b, c: 1 - (a ^ b),
+        "NOT": lambda a, b, c: 1 - a, "MUX": lambda a, b, c: b if a else c,
+    }
+    for op, f in table.items():
+        got = _dec_slots(P, km, bfv.gate(P, rlk, op, A, B, C))
+        assert got == [f(va[s], vb[s], vc[s]) for s in range(P.n)], op
+
+
+def test_less_than_all_pairs_of_3_bit_numbers():
+    """[x < y] for all 64 pairs of 3-bit numbers at once (slot-packed bits),
+    with 2 nbits - 1 products."""
+    P, km, pk, rlk = _slots_setup(33)
+    xs = [s // 8 for s in range(P.n)]
+    ys = [s % 8 for s in range(P.n)]
+    bits = [[(v >> i) & 1 for v in xs] for i in range(3)] + [[(v >> i) & 1 for v in ys] for i in range(3)]
+    cts = _enc_slots(P, pk, bits, 33)
+    cnt = bfv.Counter()
+    lt = bfv.less_than(P, rlk, cts[:3], cts[3:], cnt)
+    assert cnt.mul == 5
+    assert _dec_slots(P, km, lt) == [int(x < y) for x, y in zip(xs, ys)]
+    assert bfv.noise_ok(P, km["s"], lt, bfv.encode(P, [int(x < y) for x, y in zip(xs, ys)]))[1]
+
+
+def test_argmax_one_hot_ties_to_lower_class():
+    """Three 3-bit scores per slot (random, with forced ties): the outputs
+    decrypt to the one-hot argmax, ties to the lower class."""
+    P, km, pk, rlk = _slots_setup(34, k=5)
+    rng = random.Random(9)
+    sc = [[rng.randrange(8) for _ in range(P.n)] for _ in range(3)]
+    for s in range(0, P.n, 5):
+        sc[1][s] = sc[0][s]
+    for s in range(0, P.n, 7):
+        sc[2][s] = sc[1][s]
+    vecs = [[(sc[c][s] >> i) & 1 for s in range(P.n)] for c in range(3) for i in range(3)]
+    cts = _enc_slots(P, pk, vecs, 34)
+    scores = [cts[3 * c:3 * c + 3] for c in range(3)]
+    cnt = bfv.Counter()
+    oh = bfv.argmax(P, rlk, scores, cnt)
+    assert cnt.mul == 3 * 5 + 3
+    best = [max(range(3), key=lambda c: (sc[c][s], -c)) for s in range(P.n)]
+    for c in range(3):
+        assert _dec_slots(P, km, oh[c]) == [int(b == c) for b in best], f"class {c}"
