@@ -232,6 +232,8 @@ def main():
         out["mixed_sizes"] = mixed_leg(fhe, inputs, torch)
         out["square_chain_n16384"] = chain_leg(fhe, inputs, torch)
         print("[bench] mixed sizes and squaring chains done", file=sys.stderr, flush=True)
+        out["imputation"] = imputation_leg(fhe, inputs, torch)
+        print("[bench] imputation-shaped stages done", file=sys.stderr, flush=True)
         out["serving"] = serving_leg(fhe, inputs, torch, seconds=args.serve_seconds)
         print("[bench] serving loop done", file=sys.stderr, flush=True)
 
@@ -417,12 +419,75 @@ def chain_leg(fhe, inputs, torch, count=64, depth=4, reps=3):
     return res
 
 
+def imputation_leg(fhe, inputs, torch, reps=3, seed=11, subset=32):
+    """The imputation-shaped workload (the paper's genotype-imputation case
+    study), both stages on synthetic data.  Modular: n = 16384, eight 55-bit
+    primes, t = 65537 (8192 samples per ciphertext in slots), 500 targets x 3
+    classes = 1500 outputs, each an integer-weighted sum (weights uniform in
+    [-8, 8]) of 24 encrypted tag genotypes (uniform words stand in for their
+    encryptions), as one fhe_weighted_sum call; algorithmic HBM bytes = the 24
+    inputs read once plus the 1500 outputs written.  Bit-level: per-class
+    scores quantized to [0, 17) for a seeded subset of samples, encrypted at
+    p = 17 (coefficient encoding), bridged to 5 bits each and reduced to a
+    one-hot argmax over the 3 classes (fhe_argmax); decryptions checked."""
+    cfg = inputs.CONFIGS["bridge_n16384"]
+    n, qs = cfg["n"], cfg["q"]
+    nin, ntarget, ncls = 24, 500, 3
+    ctx = fhe.Context(n, qs, 65537, "slots")
+    g = fhe.from_numpy_u64(inputs.uniform_ciphertexts(n, qs, nin, seed, "g"), "cuda")
+    W = np.random.default_rng(seed).integers(-8, 9, size=(ntarget * ncls, nin)).astype(np.int32)
+    out = ctx.weighted_sum(g, W)
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        ctx.weighted_sum(g, W, out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    t_ms = sorted(ms)[len(ms) // 2]
+    ct_bytes = 2 * len(qs) * n * 8
+    hbm = (nin + ntarget * ncls) * ct_bytes
+    res = {"modular": {"n": n, "k": len(qs), "inputs": nin, "outputs": ntarget * ncls, "ms_per_call": t_ms,
+                       "outputs_per_s": ntarget * ncls / (t_ms / 1e3), "gb_per_s": hbm / (t_ms / 1e3) / 1e9,
+                       "hbm_frac": hbm / (t_ms / 1e3) / HBM_PEAK}}
+    del out
+    # bit-level stage on a subset: bridge the class scores, then argmax
+    ctxb = fhe.Context(n, qs, cfg["t"], "coeff")
+    km = inputs.key_material(n, qs, seed)
+    pk, rlk = ctxb.keygen(km["s"], km["pk_a"], km["pk_e"], km["rlk_a"], km["rlk_e"])
+    scores = inputs.bridge_values(cfg["t"], ncls * subset, seed).reshape(ncls, subset)
+    pts = np.zeros((ncls * subset, n), dtype=np.uint64)
+    pts[:, 0] = scores.reshape(-1)
+    r = inputs.encryption_randomness(n, ncls * subset, seed)
+    x = ctxb.encrypt(pk, pts, r["u"], r["e"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bits = ctxb.bridge_to_bits(rlk, x, cfg["nbits"])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    oh = ctxb.argmax(rlk, bits.reshape(ncls, subset, cfg["nbits"], 2, len(qs), n))
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    dec = ctxb.decrypt(km["s"], oh.reshape(ncls * subset, 2, len(qs), n)).reshape(ncls, subset, n)
+    best = [max(range(ncls), key=lambda c: (int(scores[c, j]), -c)) for j in range(subset)]
+    ok = all(int(dec[c, j, 0]) == int(best[j] == c) for c in range(ncls) for j in range(subset))
+    res["bridge_argmax"] = {"samples": subset, "classes": ncls, "bridge_ms": (t1 - t0) * 1e3,
+                            "argmax_ms": (t2 - t1) * 1e3, "samples_per_s": subset / (t2 - t0),
+                            "argmax_mul_relin": ncls * (ncls - 1) // 2 * (2 * cfg["nbits"] - 1) + ncls,
+                            "decrypts_one_hot": ok}
+    return res
+
+
 def serving_leg(fhe, inputs, torch, seconds=10.0, rate=200.0, seed=7):
     """Continuous batching (paper_2204_12201_amd/serving.py): Poisson arrivals at
-    `rate` requests/s for `seconds`, 5 products at n = 8192 (t = 65537) for every
-    3 p = 17 bridge conversions at n = 16384; keys resident, 32 GiB in-flight
-    budget.  Throughput and p50/p99 latency from arrival to completion, per kind
-    and overall."""
+    `rate` requests/s for `seconds`: 50 % products at n = 8192 (t = 65537), 30 %
+    p = 17 bridge conversions at n = 16384, 20 % imputation queries (one
+    target's 3 class scores: weighted sums of 24 resident ciphertexts at
+    n = 16384, t = 65537); keys and genotype ciphertexts resident, 32 GiB
+    in-flight budget.  Throughput and p50/p99 latency from arrival to
+    completion, per kind and overall."""
     from paper_2204_12201_amd import serving
     c8 = inputs.CONFIGS["bfv_n8192"]
     ctx8 = fhe.Context(c8["n"], c8["q"], c8["t"], "slots")
@@ -440,9 +505,13 @@ def serving_leg(fhe, inputs, torch, seconds=10.0, rate=200.0, seed=7):
     pts[:, 0] = xs
     r = inputs.encryption_randomness(cb["n"], pool, seed)
     xb = ctxb.encrypt(pkb, pts, r["u"], r["e"])
-    # warm both lanes (workspaces, kernels)
+    ctxi = fhe.Context(cb["n"], cb["q"], 65537, "slots")
+    gi = fhe.from_numpy_u64(inputs.uniform_ciphertexts(cb["n"], cb["q"], 24, seed, "g"), "cuda")
+    wq = np.random.default_rng(seed + 1).integers(-8, 9, size=(pool, 3, 24)).astype(np.int32)
+    # warm the lanes (workspaces, kernels)
     ctx8.mul_relin(rlk8, a[:64], b[:64])
     ctxb.bridge_to_bits(rlkb, xb[:8], cb["nbits"])
+    ctxi.weighted_sum(gi, wq[:16].reshape(-1, 24))
     torch.cuda.synchronize()
     rng = np.random.default_rng(seed)
     t, reqs, i = 0.0, [], 0
@@ -450,18 +519,18 @@ def serving_leg(fhe, inputs, torch, seconds=10.0, rate=200.0, seed=7):
         t += rng.exponential(1.0 / rate)
         if t >= seconds:
             break
-        if rng.random() < 5.0 / 8.0:
-            j = i % pool
-            reqs.append(serving.Request(rid=i, kind="mul", arrival=t, x=a[j:j + 1], y=b[j:j + 1]))
+        u, j = rng.random(), i % pool
+        if u < 0.5:
+            reqs.append(serving.Request(rid=i, kind="mul_n8192", arrival=t, x=a[j:j + 1], y=b[j:j + 1]))
+        elif u < 0.8:
+            reqs.append(serving.Request(rid=i, kind="bridge_n16384", arrival=t, x=xb[j:j + 1]))
         else:
-            j = i % pool
-            reqs.append(serving.Request(rid=i, kind="bridge", arrival=t, x=xb[j:j + 1]))
+            reqs.append(serving.Request(rid=i, kind="impute_n16384", arrival=t, w=wq[j]))
         i += 1
     srv = serving.Server([serving.Lane("mul_n8192", ctx8, rlk8, "mul", max_batch=256),
-                          serving.Lane("bridge_n16384", ctxb, rlkb, "bridge", max_batch=32, nbits=cb["nbits"])],
+                          serving.Lane("bridge_n16384", ctxb, rlkb, "bridge", max_batch=32, nbits=cb["nbits"]),
+                          serving.Lane("impute_n16384", ctxi, None, "wsum", max_batch=64, shared=gi, rows=3)],
                          budget_bytes=32 << 30)
-    for q in reqs:
-        q.kind = "mul_n8192" if q.kind == "mul" else "bridge_n16384"
     t0 = time.perf_counter()
     done = srv.run(reqs)
     el = time.perf_counter() - t0

@@ -74,7 +74,23 @@ enum {
     FHE_OP_KEYGEN = 4,
     FHE_OP_ENCRYPT = 5,
     FHE_OP_DECRYPT = 6,
-    FHE_OP_RLK_IMPORT = 7
+    FHE_OP_RLK_IMPORT = 7,
+    FHE_OP_WEIGHTED_SUM = 8, /* count = nout * nin weights */
+    FHE_OP_GATE = 9,         /* count = ciphertexts per operand */
+    FHE_OP_COMPARE = 10,     /* count = pairs of bit vectors */
+    FHE_OP_ARGMAX = 11       /* count = score sets */
+};
+
+/* gates of fhe_gate */
+enum {
+    FHE_GATE_AND = 0,
+    FHE_GATE_NAND = 1,
+    FHE_GATE_OR = 2,
+    FHE_GATE_NOR = 3,
+    FHE_GATE_XOR = 4,
+    FHE_GATE_XNOR = 5,
+    FHE_GATE_NOT = 6,
+    FHE_GATE_MUX = 7
 };
 
 typedef struct fhe_ctx fhe_ctx;
@@ -222,6 +238,59 @@ fhe_status fhe_square_chain(fhe_ctx *ctx, const uint64_t *rlk_dev, uint64_t *x, 
 fhe_status fhe_bridge_to_bits(fhe_ctx *ctx, const uint64_t *rlk_dev, const uint64_t *x,
                               uint32_t nbits, uint64_t *bits, uint64_t *eq, size_t count,
                               void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* ----------------------------------------------- modular linear stage --- *
+ * Integer-weighted sums of ciphertexts, word by word modulo each q_i:
+ *   out[m] = sum_{j < nin} w[m * nin + j] * in[j],   m < nout,
+ * the modular stage of the paper's genotype-imputation case study (Section
+ * 4.4, p-Impute with bridging: per-class scores as weighted sums of encrypted
+ * genotypes, before the bridge).  A weighted sum of encryptions encrypts the
+ * same weighted sum of the plaintexts modulo t (noise scaled by sum |w|).
+ *   in   device uint64 [nin][2][k][n]      out device uint64 [nout][2][k][n]
+ *   w    host int32 [nout][nin]; every row must have sum_j |w| < 2^30
+ *        (FHE_EINVAL otherwise); copied into ws before the call returns
+ * out must not overlap in (FHE_EINVAL).  nout == 0 is a no-op; nin == 0
+ * writes zero ciphertexts.  ws: FHE_OP_WEIGHTED_SUM bytes for nout * nin. */
+fhe_status fhe_weighted_sum(fhe_ctx *ctx, const uint64_t *in, size_t nin, const int32_t *w,
+                            size_t nout, uint64_t *out, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------- bit-level side ----- *
+ * Homomorphic gates on ciphertexts of bits (Section 3.1, the logic-gate
+ * expressions over {0, 1}; any t), batched over count ciphertexts per operand,
+ * evaluated exactly in this order (mul = fhe_mul_relin, 1 = add_plain_const 1):
+ *   AND  p = a b                     NAND  1 - a b = add_plain(neg(p), 1)
+ *   OR   (a + b) - a b               NOR   add_plain(neg(OR), 1)
+ *   XOR  ((a + b) - a b) - a b       XNOR  add_plain(neg(XOR), 1)
+ *   NOT  add_plain(neg(a), 1)        MUX   a (b - c) + c   (a ? b : c)
+ * a, b, c, out: device [count][2][k][n]; b is unused by NOT, c is read by MUX
+ * only (NULL allowed where unused).  out may equal an input.
+ * ws: FHE_OP_GATE bytes for count. */
+fhe_status fhe_gate(fhe_ctx *ctx, const uint64_t *rlk_dev, int gate, const uint64_t *a,
+                    const uint64_t *b, const uint64_t *c, uint64_t *out, size_t count, void *ws,
+                    size_t ws_bytes, hipStream_t stream);
+
+/* Encrypted comparison of unsigned bit vectors (Section 3.1: comparisons are
+ * built from the gates as standard combinational circuits), least significant bit
+ * first as fhe_bridge_to_bits writes them:
+ *   out[j] = [a_j < b_j] for a_j = sum_i 2^i a[j][i], b_j likewise.
+ * Circuit, per bit i: p_i = a_i b_i; d_i = b_i - p_i (= NOT a_i AND b_i);
+ * e_i = 1 - ((a_i + b_i) - p_i - p_i) (XNOR); lt = d_0, then for i >= 1
+ * lt = e_i (lt - d_i) + d_i (MUX(e_i, lt, d_i)).  Multiplicative depth nbits.
+ *   a, b device [count][nbits][2][k][n];  out device [count][2][k][n]
+ * nbits >= 1.  ws: FHE_OP_COMPARE bytes for count. */
+fhe_status fhe_less_than(fhe_ctx *ctx, const uint64_t *rlk_dev, const uint64_t *a, const uint64_t *b,
+                         uint32_t nbits, uint64_t *out, size_t count, void *ws, size_t ws_bytes,
+                         hipStream_t stream);
+
+/* One-hot argmax of ncls encrypted unsigned scores per set, ties to the lower
+ * class: for every pair a < b (a ascending, then b) l = [s_a < s_b]
+ * (fhe_less_than); out_a takes the factor 1 - l, out_b the factor l; a class's
+ * first factor is copied, later ones multiplied in (fhe_mul_relin).
+ *   scores device [ncls][count][nbits][2][k][n];  out device [ncls][count][2][k][n]
+ * 2 <= ncls <= 16.  ws: FHE_OP_ARGMAX bytes for count. */
+fhe_status fhe_argmax(fhe_ctx *ctx, const uint64_t *rlk_dev, const uint64_t *scores, uint32_t ncls,
+                      uint32_t nbits, uint64_t *out, size_t count, void *ws, size_t ws_bytes,
+                      hipStream_t stream);
 
 /* The paper's SecureUint -> SecureMod cast (Section 3.2.1, Horner):
  * out[j] = sum_b 2^b bits[j][b], evaluated as r = bit_{nbits-1}; r = r + r + bit_b.

@@ -209,6 +209,11 @@ struct fhe_ctx {
         hipGraphExec_t ge;
     };
     std::vector<ChainGraph> graphs;
+    // pinned staging of fhe_weighted_sum's weights; the event marks the end of
+    // the last copy out of it
+    int32_t *wpin = nullptr;
+    size_t wpin_cap = 0;
+    hipEvent_t wpin_ev = nullptr;
 };
 
 namespace {
@@ -345,6 +350,11 @@ void release(fhe_ctx *c) {
         hipGraphDestroy(cg.g);
     }
     c->graphs.clear();
+    if (c->wpin_ev) {
+        (void)hipEventSynchronize(c->wpin_ev);
+        (void)hipEventDestroy(c->wpin_ev);
+    }
+    if (c->wpin) hipHostFree(c->wpin);
     if (c->fork_ev) hipEventDestroy(c->fork_ev);
     if (c->join_ev) hipEventDestroy(c->join_ev);
     if (c->aux) hipStreamDestroy(c->aux);
@@ -510,6 +520,10 @@ fhe_status fhe_ctx_create(const fhe_params *p, int hip_device, fhe_ctx **out) {
         P.ninv_p = shoup(P.ninv, q);
         P.ninvm = mont(P.ninv, q);
         P.ninvm_p = shoup(P.ninvm, q);
+        P.r32 = (uint64_t)(((u128)1 << 32) % q);
+        P.r32_p = shoup(P.r32, q);
+        P.off59 = ((1ull << 59) + q - 1) / q * q;
+        P.off62 = ((1ull << 62) + q - 1) / q * q;
         const uint64_t psi = find_psi(q, n), ipsi = hinv(psi, q);
         std::vector<uint64_t> pw(n), ipw(n);
         pw[0] = 1;
@@ -712,6 +726,14 @@ size_t fhe_workspace_bytes(const fhe_ctx *c, int op, size_t count) {
             return (k * n + 2 * count * k * n + count * n) * 8 + n + 256;
         case FHE_OP_RLK_IMPORT:
             return 0;
+        case FHE_OP_WEIGHTED_SUM:  // padded rows: at most 8 slots per weight
+            return 32 * count + 256;
+        case FHE_OP_GATE:
+            return 2 * count * ct_words(c) * 8 + fhe_workspace_bytes(c, FHE_OP_MUL_RELIN, count);
+        case FHE_OP_COMPARE:
+            return 6 * count * ct_words(c) * 8 + fhe_workspace_bytes(c, FHE_OP_MUL_RELIN, count);
+        case FHE_OP_ARGMAX:
+            return 2 * count * ct_words(c) * 8 + fhe_workspace_bytes(c, FHE_OP_COMPARE, count);
     }
     return 0;
 }
@@ -1114,6 +1136,194 @@ fhe_status fhe_bits_to_mod(fhe_ctx *c, const uint64_t *bits, uint32_t nbits, uin
     if (overlaps2(out, count * ct_words(c) * 8, bits, count * nbits * ct_words(c) * 8)) return FHE_EINVAL;
     return run(c, KK_ELEMENTWISE, st,
                [&] { return launch_horner(c->dev, bits, (int)nbits, out, count, st); });
+}
+
+// ------------------------------------------------- modular linear stage ----
+
+fhe_status fhe_weighted_sum(fhe_ctx *c, const uint64_t *in, size_t nin, const int32_t *w, size_t nout,
+                            uint64_t *out, void *ws, size_t ws_bytes, hipStream_t st) {
+    if (!c) return FHE_EINVAL;
+    if (nout == 0) return FHE_OK;
+    if (!out || (nin && (!in || !w || !ws))) return FHE_EINVAL;
+    const size_t ctb = ct_words(c) * 8;
+    if (nin && overlaps2(out, nout * ctb, in, nin * ctb)) return FHE_EINVAL;
+    if (nin == 0) {
+        FHE_HIP(hipMemsetAsync(out, 0, nout * ctb, st));
+        return FHE_OK;
+    }
+    if (ws_bytes < fhe_workspace_bytes(c, FHE_OP_WEIGHTED_SUM, nout * nin)) return FHE_EWORKSPACE;
+    const size_t stride = weighted_sum_row_stride(nin);
+    for (size_t m = 0; m < nout; m++) {
+        uint64_t abs_sum = 0;
+        for (size_t j = 0; j < nin; j++) {
+            const int64_t v = w[m * nin + j];
+            abs_sum += (uint64_t)(v < 0 ? -v : v);
+        }
+        if (abs_sum >= (1ull << 30)) return FHE_EINVAL;
+    }
+    FHE_TRY(check_canonical(c, in, nin * 2 * c->k, c->k, 0, st));
+    // padded rows staged in pinned memory (the previous copy out of it must
+    // have finished), then one asynchronous copy into the workspace
+    const size_t words = nout * stride;
+    if (!c->wpin_ev && hipEventCreateWithFlags(&c->wpin_ev, hipEventDisableTiming) != hipSuccess) {
+        c->wpin_ev = nullptr;
+        return FHE_EDEVICE;
+    }
+    FHE_HIP(hipEventSynchronize(c->wpin_ev));
+    if (words > c->wpin_cap) {
+        if (c->wpin) hipHostFree(c->wpin);
+        c->wpin = nullptr;
+        c->wpin_cap = 0;
+        if (hipHostMalloc((void **)&c->wpin, words * 4, hipHostMallocDefault) != hipSuccess) {
+            c->wpin = nullptr;
+            return FHE_ENOMEM;
+        }
+        c->wpin_cap = words;
+    }
+    std::memset(c->wpin, 0, words * 4);
+    for (size_t m = 0; m < nout; m++) std::memcpy(c->wpin + m * stride, w + m * nin, nin * 4);
+    int32_t *wd = (int32_t *)ws;
+    FHE_HIP(hipMemcpyAsync(wd, c->wpin, words * 4, hipMemcpyHostToDevice, st));
+    FHE_HIP(hipEventRecord(c->wpin_ev, st));
+    return run(c, KK_ELEMENTWISE, st, [&] { return launch_weighted_sum(c->dev, in, nin, wd, nout, out, st); });
+}
+
+// ------------------------------------------------------ bit-level side ----
+// Compositions of the product and the elementwise kernels, in the order the
+// header documents (the oracle evaluates the same sequence).
+
+static fhe_status ew(fhe_ctx *c, const uint64_t *a, const uint64_t *b, uint64_t *out, size_t count, int op,
+                     hipStream_t st) {  // op 0: a + b, 1: a - b, 2: -a
+    return run(c, KK_ELEMENTWISE, st,
+               [&] { return launch_addsub(c->dev, a, b, out, count * 2 * c->k, op, st); });
+}
+
+static fhe_status one_minus(fhe_ctx *c, const uint64_t *a, uint64_t *out, size_t count, hipStream_t st) {
+    FHE_TRY(ew(c, a, nullptr, out, count, 2, st));
+    return run(c, KK_ELEMENTWISE, st, [&] { return launch_plain_const(c->dev, out, out, count, 1, +1, st); });
+}
+
+static fhe_status gate_impl(fhe_ctx *c, const uint64_t *rlk, int gate, const uint64_t *a, const uint64_t *b,
+                            const uint64_t *cc, uint64_t *out, size_t count, void *ws, hipStream_t st) {
+    const size_t ctw = ct_words(c);
+    uint64_t *t0 = (uint64_t *)ws, *t1 = t0 + count * ctw;
+    void *mws = t1 + count * ctw;
+    switch (gate) {
+        case FHE_GATE_NOT:
+            return one_minus(c, a, out, count, st);
+        case FHE_GATE_MUX:
+            FHE_TRY(ew(c, b, cc, t0, count, 1, st));
+            FHE_TRY(mul_relin_impl(c, rlk, a, t0, t1, count, mws, st));
+            return ew(c, t1, cc, out, count, 0, st);
+        case FHE_GATE_AND:
+            return mul_relin_impl(c, rlk, a, b, out, count, mws, st);
+        default:
+            break;
+    }
+    FHE_TRY(mul_relin_impl(c, rlk, a, b, t0, count, mws, st));  // p = a b
+    if (gate == FHE_GATE_NAND) return one_minus(c, t0, out, count, st);
+    FHE_TRY(ew(c, a, b, out, count, 0, st));
+    FHE_TRY(ew(c, out, t0, out, count, 1, st));  // OR
+    if (gate == FHE_GATE_XOR || gate == FHE_GATE_XNOR) FHE_TRY(ew(c, out, t0, out, count, 1, st));
+    if (gate == FHE_GATE_NOR || gate == FHE_GATE_XNOR) return one_minus(c, out, out, count, st);
+    return FHE_OK;
+}
+
+fhe_status fhe_gate(fhe_ctx *c, const uint64_t *rlk, int gate, const uint64_t *a, const uint64_t *b,
+                    const uint64_t *cc, uint64_t *out, size_t count, void *ws, size_t ws_bytes,
+                    hipStream_t st) {
+    if (!c) return FHE_EINVAL;
+    if (gate < FHE_GATE_AND || gate > FHE_GATE_MUX) return FHE_EINVAL;
+    if (count == 0) return FHE_OK;
+    const bool needs_b = gate != FHE_GATE_NOT, needs_c = gate == FHE_GATE_MUX, needs_mul = gate != FHE_GATE_NOT;
+    if (!a || !out || (needs_b && !b) || (needs_c && !cc) || (needs_mul && (!rlk || !ws))) return FHE_EINVAL;
+    const size_t bytes = count * ct_words(c) * 8;
+    if (out != a && overlaps(out, a, bytes)) return FHE_EINVAL;
+    if (needs_b && out != b && overlaps(out, b, bytes)) return FHE_EINVAL;
+    if (needs_c && out != cc && overlaps(out, cc, bytes)) return FHE_EINVAL;
+    if (needs_mul && ws_bytes < fhe_workspace_bytes(c, FHE_OP_GATE, count)) return FHE_EWORKSPACE;
+    FHE_TRY(check_canonical(c, a, count * 2 * c->k, c->k, 0, st));
+    if (needs_b) FHE_TRY(check_canonical(c, b, count * 2 * c->k, c->k, 0, st));
+    if (needs_c) FHE_TRY(check_canonical(c, cc, count * 2 * c->k, c->k, 0, st));
+    return gate_impl(c, rlk, gate, a, b, cc, out, count, ws, st);
+}
+
+// Bit i of every item of a [count][nbits][2][k][n] into a contiguous [count] block.
+static fhe_status gather_bit(fhe_ctx *c, const uint64_t *v, uint32_t nbits, uint32_t i, uint64_t *dst,
+                             size_t count, hipStream_t st) {
+    const size_t ctb = ct_words(c) * 8;
+    FHE_HIP(hipMemcpy2DAsync(dst, ctb, v + (size_t)i * ct_words(c), nbits * ctb, ctb, count,
+                             hipMemcpyDeviceToDevice, st));
+    return FHE_OK;
+}
+
+static fhe_status less_than_impl(fhe_ctx *c, const uint64_t *rlk, const uint64_t *a, const uint64_t *b,
+                                 uint32_t nbits, uint64_t *out, size_t count, void *ws, hipStream_t st) {
+    const size_t cw = count * ct_words(c);
+    uint64_t *A = (uint64_t *)ws, *B = A + cw, *Pr = B + cw, *D = Pr + cw, *E = D + cw, *T = E + cw;
+    void *mws = T + cw;
+    for (uint32_t i = 0; i < nbits; i++) {
+        FHE_TRY(gather_bit(c, a, nbits, i, A, count, st));
+        FHE_TRY(gather_bit(c, b, nbits, i, B, count, st));
+        FHE_TRY(mul_relin_impl(c, rlk, A, B, Pr, count, mws, st));  // p = a_i b_i
+        if (i == 0) {
+            FHE_TRY(ew(c, B, Pr, out, count, 1, st));  // lt = d_0
+            continue;
+        }
+        FHE_TRY(ew(c, B, Pr, D, count, 1, st));   // d = b_i - p
+        FHE_TRY(ew(c, A, B, E, count, 0, st));    // e = 1 - ((a + b) - p - p)
+        FHE_TRY(ew(c, E, Pr, E, count, 1, st));
+        FHE_TRY(ew(c, E, Pr, E, count, 1, st));
+        FHE_TRY(one_minus(c, E, E, count, st));
+        FHE_TRY(ew(c, out, D, T, count, 1, st));  // lt = e (lt - d) + d
+        FHE_TRY(mul_relin_impl(c, rlk, E, T, T, count, mws, st));
+        FHE_TRY(ew(c, T, D, out, count, 0, st));
+    }
+    return FHE_OK;
+}
+
+fhe_status fhe_less_than(fhe_ctx *c, const uint64_t *rlk, const uint64_t *a, const uint64_t *b, uint32_t nbits,
+                         uint64_t *out, size_t count, void *ws, size_t ws_bytes, hipStream_t st) {
+    if (!c) return FHE_EINVAL;
+    if (nbits == 0) return FHE_EINVAL;
+    if (count == 0) return FHE_OK;
+    if (!rlk || !a || !b || !out || !ws) return FHE_EINVAL;
+    const size_t ctb = ct_words(c) * 8;
+    if (overlaps2(out, count * ctb, a, count * nbits * ctb) || overlaps2(out, count * ctb, b, count * nbits * ctb))
+        return FHE_EINVAL;
+    if (ws_bytes < fhe_workspace_bytes(c, FHE_OP_COMPARE, count)) return FHE_EWORKSPACE;
+    FHE_TRY(check_canonical(c, a, count * nbits * 2 * c->k, c->k, 0, st));
+    FHE_TRY(check_canonical(c, b, count * nbits * 2 * c->k, c->k, 0, st));
+    return less_than_impl(c, rlk, a, b, nbits, out, count, ws, st);
+}
+
+fhe_status fhe_argmax(fhe_ctx *c, const uint64_t *rlk, const uint64_t *scores, uint32_t ncls, uint32_t nbits,
+                      uint64_t *out, size_t count, void *ws, size_t ws_bytes, hipStream_t st) {
+    if (!c) return FHE_EINVAL;
+    if (nbits == 0 || ncls < 2 || ncls > 16) return FHE_EINVAL;
+    if (count == 0) return FHE_OK;
+    if (!rlk || !scores || !out || !ws) return FHE_EINVAL;
+    const size_t ctw = ct_words(c), cw = count * ctw, sw = count * nbits * ctw;
+    if (overlaps2(out, ncls * cw * 8, scores, ncls * sw * 8)) return FHE_EINVAL;
+    if (ws_bytes < fhe_workspace_bytes(c, FHE_OP_ARGMAX, count)) return FHE_EWORKSPACE;
+    FHE_TRY(check_canonical(c, scores, ncls * count * nbits * 2 * c->k, c->k, 0, st));
+    uint64_t *Lt = (uint64_t *)ws, *Na = Lt + cw;
+    void *cws = Na + cw;
+    void *mws = (uint8_t *)cws + 6 * cw * 8;  // the comparison's product workspace
+    bool first[16];
+    for (uint32_t a = 0; a < ncls; a++) first[a] = true;
+    for (uint32_t a = 0; a < ncls; a++)
+        for (uint32_t b = a + 1; b < ncls; b++) {
+            FHE_TRY(less_than_impl(c, rlk, scores + a * sw, scores + b * sw, nbits, Lt, count, cws, st));
+            FHE_TRY(one_minus(c, Lt, Na, count, st));
+            uint64_t *oa = out + a * cw, *ob = out + b * cw;
+            if (first[a]) FHE_HIP(hipMemcpyAsync(oa, Na, cw * 8, hipMemcpyDeviceToDevice, st));
+            else FHE_TRY(mul_relin_impl(c, rlk, oa, Na, oa, count, mws, st));
+            if (first[b]) FHE_HIP(hipMemcpyAsync(ob, Lt, cw * 8, hipMemcpyDeviceToDevice, st));
+            else FHE_TRY(mul_relin_impl(c, rlk, ob, Lt, ob, count, mws, st));
+            first[a] = first[b] = false;
+        }
+    return FHE_OK;
 }
 
 fhe_status fhe_ntt(fhe_ctx *c, int inverse, uint64_t *polys, size_t count, hipStream_t st) {

@@ -108,3 +108,10 @@ hipError_t launch_horner(const DevCtx &c, const uint64_t *bits, int nbits, uint6
 // flag[0] |= 1 if some word of rows [nrows][n] (limb = row % kmod + off) is >= its prime
 hipError_t launch_validate(const DevCtx &c, const uint64_t *a, size_t nrows, int kmod, int off,
                            unsigned int *flag, hipStream_t s);
+
+// ---- integer-weighted sums (kernels_lin.hip) ----
+// Row stride (in weights) of the device weight matrix: rows padded with zeros.
+size_t weighted_sum_row_stride(size_t nin);
+// out[m] = sum_j w[m][j] in[j] for the padded device matrix w [nout][stride].
+hipError_t launch_weighted_sum(const DevCtx &c, const uint64_t *in, size_t nin, const int32_t *w, size_t nout,
+                               uint64_t *out, hipStream_t s);

@@ -1,0 +1,115 @@
+// Integer-weighted sums of ciphertexts (the modular stage of the paper's
+// genotype-imputation case study, Section 4.4):
+//   out[m] (+)= sum_{j < nj} w[m][j] in[j]   word by word, modulo the word's prime.
+//
+// Exact without 128-bit arithmetic: a word x < q < 2^61 splits as
+// x = x_hi 2^32 + x_lo with x_hi < 2^29.  With every weight row's sum of
+// |w| below 2^30, the signed sums
+//   S_hi = sum w x_hi               (|S_hi| < 2^59)
+//   S_lo = sum w (x_lo - 2^31) + 2^31 sum w  = sum w x_lo   (|S_lo| < 2^62)
+// fit 64-bit integers (one v_mad_i64_i32 each per term, the weight a
+// wave-uniform scalar); shifted by multiples of q (off59, off62) they become
+// non-negative and below 2^64, and S = S_hi 2^32 + S_lo mod q is two Shoup
+// products (by 2^32 mod q and by 1), each in [0, 4q), summed and reduced.
+//
+// The kernel is bound by writing the outputs (one word per output per input
+// word position); the inputs of a position are read once per block of WS_M
+// outputs and stay in the L2 / last-level cache between blocks.
+#include "kernels.hpp"
+#include "modarith.hpp"
+
+namespace {
+
+constexpr int WS_J = 32;  // inputs held in registers per launch
+constexpr int WS_G = 8;   // weight rows are padded with zeros to a multiple of WS_G
+constexpr int WS_M = 64;  // outputs per workgroup row
+
+__device__ __forceinline__ uint64_t canon8w(uint64_t x, uint64_t q) {  // [0, 8q) -> [0, q)
+    return csub(csub(csub(x, q << 2), q << 1), q);
+}
+
+// S = S_hi 2^32 + S_lo mod q from the two signed sums (S_lo still without
+// its 2^31 sum(w) correction), written or added to *o.
+__device__ __forceinline__ void finish(int64_t sl, int64_t sh, int32_t ws, const PrimeConst &P, uint64_t *o,
+                                       int accumulate) {
+    const uint64_t q = P.q;
+    sl += (int64_t)ws * ((int64_t)1 << 31);
+    const uint64_t a = (uint64_t)(sh + (int64_t)P.off59);
+    const uint64_t b = (uint64_t)(sl + (int64_t)P.off62);
+    uint64_t r = canon8w(mul_shoup_lazy4(a, P.r32, P.r32_p, q) + mul_shoup_lazy4(b, 1, P.one_p, q), q);
+    if (accumulate) r = add_mod(r, *o, q);
+    *o = r;
+}
+
+// grid (ceil(W / 256), ceil(nout / WS_M)); W = 2 k n words per ciphertext.
+// in: nj <= WS_J ciphertexts (stride W); w: rows of stride wstride (device,
+// zero beyond the last input of the row); out: nout ciphertexts;
+// accumulate: add into out instead of writing it.
+__global__ __launch_bounds__(256) void k_weighted_sum(DevCtx c, const uint64_t *__restrict__ in, int nj,
+                                                      const int32_t *__restrict__ w, int wstride,
+                                                      size_t nout, uint64_t *__restrict__ out, int accumulate) {
+    const size_t W = (size_t)2 * c.k * c.n;
+    const size_t p = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= W) return;
+    const int limb = (int)((p >> c.L) % (size_t)c.k);
+    const PrimeConst &P = c.pc[limb];
+    const uint64_t q = P.q;
+    int32_t xl[WS_J], xh[WS_J];
+#pragma unroll
+    for (int j = 0; j < WS_J; j++) {
+        const uint64_t x = j < nj ? in[(size_t)j * W + p] : 0;
+        xl[j] = (int32_t)((uint32_t)x ^ 0x80000000u);  // x_lo - 2^31
+        xh[j] = (int32_t)(x >> 32);
+        // opaque: keeps the products signed 32 x 32 bit (v_mad_i64_i32)
+        // instead of being rewritten around the unsigned low word
+        asm("" : "+v"(xl[j]), "+v"(xh[j]));
+    }
+    const size_t m0 = (size_t)blockIdx.y * WS_M;
+    const size_t m1 = m0 + WS_M < nout ? m0 + WS_M : nout;
+    // two outputs per iteration: four independent multiply-add chains
+    for (size_t m = m0; m < m1; m += 2) {
+        const bool two = m + 1 < m1;
+        const int32_t *wr0 = w + m * (size_t)wstride;
+        const int32_t *wr1 = two ? wr0 + wstride : wr0;
+        int64_t sl0 = 0, sh0 = 0, sl1 = 0, sh1 = 0;
+        int32_t ws0 = 0, ws1 = 0;
+#pragma unroll
+        for (int g = 0; g < WS_J / WS_G; g++) {
+            if (g * WS_G < nj) {
+#pragma unroll
+                for (int u = 0; u < WS_G; u++) {
+                    const int j = g * WS_G + u;
+                    const int32_t w0 = wr0[j], w1 = wr1[j];
+                    sl0 += (int64_t)w0 * xl[j];
+                    sh0 += (int64_t)w0 * xh[j];
+                    sl1 += (int64_t)w1 * xl[j];
+                    sh1 += (int64_t)w1 * xh[j];
+                    ws0 += w0;
+                    ws1 += w1;
+                }
+            }
+        }
+        uint64_t *o = out + m * W + p;
+        finish(sl0, sh0, ws0, P, o, accumulate);
+        if (two) finish(sl1, sh1, ws1, P, o + W, accumulate);
+    }
+}
+
+}  // namespace
+
+size_t weighted_sum_row_stride(size_t nin) { return (nin + WS_G - 1) / WS_G * WS_G; }
+
+hipError_t launch_weighted_sum(const DevCtx &c, const uint64_t *in, size_t nin, const int32_t *w, size_t nout,
+                               uint64_t *out, hipStream_t s) {
+    const size_t W = (size_t)2 * c.k * c.n;
+    const size_t wstride = weighted_sum_row_stride(nin);
+    const dim3 grid((unsigned)((W + 255) / 256), (unsigned)((nout + WS_M - 1) / WS_M));
+    for (size_t j0 = 0; j0 < nin; j0 += WS_J) {
+        const int nj = (int)(nin - j0 < (size_t)WS_J ? nin - j0 : (size_t)WS_J);
+        hipLaunchKernelGGL(k_weighted_sum, grid, dim3(256), 0, s, c, in + j0 * W, nj, w + j0, (int)wstride,
+                           nout, out, j0 > 0 ? 1 : 0);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}

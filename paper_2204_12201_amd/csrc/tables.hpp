@@ -18,6 +18,8 @@ struct PrimeConst {
     uint64_t one_p;      // floor(2^64 / q): Shoup companion of 1
     uint64_t ninv, ninv_p;     // n^-1 mod q (Shoup pair)
     uint64_t ninvm, ninvm_p;   // n^-1 2^64 mod q (Shoup pair): inverse after Montgomery products
+    uint64_t r32, r32_p;       // 2^32 mod q (Shoup pair)
+    uint64_t off59, off62;     // smallest multiples of q at least 2^59 and 2^62
     uint64_t pad;
 };
 

@@ -18,6 +18,8 @@ LIBPATH = os.path.join(HERE, "libfhe.so")
 
 ENC_SLOTS, ENC_COEFF = 0, 1
 OP_MUL_RELIN, OP_SQUARE_RELIN, OP_BRIDGE, OP_KEYGEN, OP_ENCRYPT, OP_DECRYPT, OP_RLK_IMPORT = range(1, 8)
+OP_WEIGHTED_SUM, OP_GATE, OP_COMPARE, OP_ARGMAX = range(8, 12)
+GATES = {"AND": 0, "NAND": 1, "OR": 2, "NOR": 3, "XOR": 4, "XNOR": 5, "NOT": 6, "MUX": 7}
 
 STATUS = {0: "ok", -1: "invalid argument", -2: "parameter set rejected", -3: "device allocation failed",
           -4: "HIP error", -5: "shape mismatch", -6: "non-canonical input word",
@@ -71,6 +73,10 @@ _SIGS = [
     ("fhe_square_chain", _I, [_P, _P, _P, _U32, _Z, _P, _Z, _I, _P]),
     ("fhe_bridge_to_bits", _I, [_P, _P, _P, _U32, _P, _P, _Z, _P, _Z, _P]),
     ("fhe_bits_to_mod", _I, [_P, _P, _U32, _P, _Z, _P]),
+    ("fhe_weighted_sum", _I, [_P, _P, _Z, _P, _Z, _P, _P, _Z, _P]),
+    ("fhe_gate", _I, [_P, _P, _I, _P, _P, _P, _P, _Z, _P, _Z, _P]),
+    ("fhe_less_than", _I, [_P, _P, _P, _P, _U32, _P, _Z, _P, _Z, _P]),
+    ("fhe_argmax", _I, [_P, _P, _P, _U32, _U32, _P, _Z, _P, _Z, _P]),
     ("fhe_ntt", _I, [_P, _I, _P, _Z, _P]),
     ("fhe_set_timing", _I, [_P, _I]),
     ("fhe_kernel_kinds", _I, []),
@@ -314,6 +320,51 @@ class Context:
         out = self.empty_ct(count) if out is None else out
         _check(lib().fhe_bits_to_mod(self._h, _dptr(bits), nbits, _dptr(out), count, _stream()),
                "fhe_bits_to_mod")
+        return out
+
+    def weighted_sum(self, x, w, out=None):
+        """out[m] = sum_j w[m][j] x[j]: x device [nin][2][k][n], w host int32
+        [nout][nin] (row sums of |w| below 2^30)."""
+        import numpy as np
+        w = np.ascontiguousarray(w, dtype=np.int32)
+        nout, nin = w.shape
+        out = self.empty_ct(nout) if out is None else out
+        ws, _ = self.workspace(OP_WEIGHTED_SUM, nout * nin)
+        _check(lib().fhe_weighted_sum(self._h, _dptr(x), nin, w.ctypes.data, nout, _dptr(out), _dptr(ws),
+                                      ws.numel(), _stream()), "fhe_weighted_sum")
+        return out
+
+    def gate(self, rlk, op: str, a, b=None, c=None, out=None):
+        """The paper's gate `op` (AND, NAND, OR, NOR, XOR, XNOR, NOT, MUX) on
+        batches of bit ciphertexts (device [count][2][k][n])."""
+        out = self._out(out, a)
+        count = a.shape[0]
+        ws, _ = self.workspace(OP_GATE, count)
+        _check(lib().fhe_gate(self._h, _dptr(rlk), GATES[op], _dptr(a), _dptr(b) if b is not None else None,
+                              _dptr(c) if c is not None else None, _dptr(out), count, _dptr(ws), ws.numel(),
+                              _stream()), "fhe_gate")
+        return out
+
+    def less_than(self, rlk, a, b, out=None):
+        """[a < b] per item: a, b device [count][nbits][2][k][n], least
+        significant bit first."""
+        count, nbits = a.shape[0], a.shape[1]
+        out = self.empty_ct(count) if out is None else out
+        ws, _ = self.workspace(OP_COMPARE, count)
+        _check(lib().fhe_less_than(self._h, _dptr(rlk), _dptr(a), _dptr(b), nbits, _dptr(out), count,
+                                   _dptr(ws), ws.numel(), _stream()), "fhe_less_than")
+        return out
+
+    def argmax(self, rlk, scores, out=None):
+        """One-hot argmax: scores device [ncls][count][nbits][2][k][n] ->
+        [ncls][count][2][k][n]."""
+        import torch
+        ncls, count, nbits = scores.shape[0], scores.shape[1], scores.shape[2]
+        if out is None:
+            out = torch.empty((ncls, count, 2, self.k, self.n), dtype=torch.int64, device=self.device)
+        ws, _ = self.workspace(OP_ARGMAX, count)
+        _check(lib().fhe_argmax(self._h, _dptr(rlk), _dptr(scores), ncls, nbits, _dptr(out), count, _dptr(ws),
+                                ws.numel(), _stream()), "fhe_argmax")
         return out
 
     def ntt(self, polys, inverse: bool = False):

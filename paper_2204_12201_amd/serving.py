@@ -1,7 +1,8 @@
 """Continuous-batching request loop over the library (host side).
 
 Requests of several kinds (a ciphertext product at one ring size, a p = 17
-bridge conversion at another, ...) arrive over time.  The loop keeps each
+bridge conversion at another, an imputation query: the integer-weighted sums
+of resident encrypted genotypes for one target's classes, ...) arrive over time.  The loop keeps each
 kind's relinearization key resident, queues arrived requests per kind, and
 whenever a kind's stream is idle admits the queued requests of that kind (up to
 its batch cap) as one batch, as long as the device bytes of everything in
@@ -23,6 +24,8 @@ import collections
 import time
 from dataclasses import dataclass, field
 
+import numpy as np
+
 from . import fhe
 
 
@@ -31,8 +34,9 @@ class Request:
     rid: int
     kind: str
     arrival: float                 # seconds on the loop's clock
-    x: object                      # device [1][2][k][n] (first operand)
+    x: object = None               # device [1][2][k][n] (first operand; unused by weighted sums)
     y: object = None               # device [1][2][k][n] second operand (products)
+    w: object = None               # host int32 [rows][nin] weights (weighted sums)
     result: object = None          # device tensor once done
     done: float = None             # completion time on the loop's clock
     batch: int = 0                 # size of the batch it ran in
@@ -45,14 +49,17 @@ class Request:
 @dataclass
 class Lane:
     """One request kind: its context, resident key, stream and batch cap.
-    op: "mul" (out = x * y, relinearized) or "bridge" (the p-bit conversion
-    of x, nbits bit ciphertexts)."""
+    op: "mul" (out = x * y, relinearized), "bridge" (the p-bit conversion
+    of x, nbits bit ciphertexts) or "wsum" (rows of integer weights applied to
+    the lane's resident ciphertexts `shared`, one output per row)."""
     kind: str
     ctx: object
     rlk: object
     op: str
     max_batch: int
     nbits: int = 0
+    shared: object = None          # device [nin][2][k][n] resident inputs (wsum)
+    rows: int = 0                  # weight rows per request (wsum)
     stream: object = None
     queue: collections.deque = field(default_factory=collections.deque)
     inflight: tuple = None         # (requests, event, bytes, buffers)
@@ -63,6 +70,10 @@ class Lane:
         if self.op == "mul":
             ws = fhe.lib().fhe_workspace_bytes(c._h, fhe.OP_MUL_RELIN, count)
             return ws + 3 * count * ct
+        if self.op == "wsum":
+            nin = self.shared.shape[0]
+            ws = fhe.lib().fhe_workspace_bytes(c._h, fhe.OP_WEIGHTED_SUM, count * self.rows * nin)
+            return ws + count * self.rows * ct
         ws = fhe.lib().fhe_workspace_bytes(c._h, fhe.OP_BRIDGE, count)
         return ws + count * ct * (1 + self.nbits)
 
@@ -99,18 +110,23 @@ class Server:
         nbytes = ln.bytes_for(count)
         torch = self.torch
         with torch.cuda.stream(ln.stream):
-            xs = torch.cat([r.x for r in reqs]) if count > 1 else reqs[0].x
-            if ln.op == "mul":
+            if ln.op == "wsum":
+                out = ln.ctx.weighted_sum(ln.shared, np.concatenate([r.w for r in reqs]))
+                bufs = (out,)
+            elif ln.op == "mul":
+                xs = torch.cat([r.x for r in reqs]) if count > 1 else reqs[0].x
                 ys = torch.cat([r.y for r in reqs]) if count > 1 else reqs[0].y
                 out = ln.ctx.mul_relin(ln.rlk, xs, ys)
                 bufs = (xs, ys, out)
             else:
+                xs = torch.cat([r.x for r in reqs]) if count > 1 else reqs[0].x
                 out = ln.ctx.bridge_to_bits(ln.rlk, xs, ln.nbits)
                 bufs = (xs, out)
             ev = torch.cuda.Event()
             ev.record(ln.stream)
+        per = ln.rows if ln.op == "wsum" else 1
         for j, r in enumerate(reqs):
-            r.result = out[j:j + 1]
+            r.result = out[j * per:(j + 1) * per]
             r.batch = count
         ln.inflight = (reqs, ev, nbytes, bufs)
         self.in_flight_bytes += nbytes

@@ -220,9 +220,10 @@ def test_square_chain_graph_replays(dev):
 
 
 def test_serving_results_identical_alone_and_in_mix(dev):
-    """The continuous-batching loop: products at n = 8192 (t = 65537) and p = 17
-    bridge conversions at n = 16384 arriving interleaved; every request's result
-    equals the same request computed alone, batches formed, and the two kinds
+    """The continuous-batching loop: products at n = 8192 (t = 65537), p = 17
+    bridge conversions at n = 16384 and imputation queries (weighted sums of
+    24 resident ciphertexts at n = 16384) arriving interleaved; every request's
+    result equals the same request computed alone, batches formed, and kinds
     were in flight together."""
     import torch
     from paper_2204_12201_amd import serving
@@ -242,25 +243,36 @@ def test_serving_results_identical_alone_and_in_mix(dev):
     pts[:, 0] = xs
     r = inputs.encryption_randomness(cb["n"], nb, 52)
     xb = ctxb.encrypt(pkb, pts, r["u"], r["e"])
+    ci = inputs.CONFIGS["bridge_n16384"]
+    ctxi = fhe.Context(ci["n"], ci["q"], 65537, "slots")
+    gi = up(inputs.uniform_ciphertexts(ci["n"], ci["q"], 24, 53, "g"))
+    wrng = np.random.default_rng(53)
+    ni = 6
     torch.cuda.synchronize()
     reqs = []
+    for i in range(ni):
+        reqs.append(serving.Request(rid=200 + i, kind="impute", arrival=0.00015 * i + 0.00002,
+                                    w=wrng.integers(-8, 9, size=(3, 24)).astype(np.int32)))
     for i in range(nm):
         reqs.append(serving.Request(rid=i, kind="mul", arrival=0.0001 * i, x=a[i:i + 1], y=b[i:i + 1]))
     for i in range(nb):  # arrivals faster than service: later requests queue and batch
         reqs.append(serving.Request(rid=100 + i, kind="bridge", arrival=0.0002 * i + 0.00005, x=xb[i:i + 1]))
     reqs.sort(key=lambda q: q.arrival)
     srv = serving.Server([serving.Lane("mul", ctx8, rlk8, "mul", max_batch=64),
-                          serving.Lane("bridge", ctxb, rlkb, "bridge", max_batch=8, nbits=5)],
+                          serving.Lane("bridge", ctxb, rlkb, "bridge", max_batch=8, nbits=5),
+                          serving.Lane("impute", ctxi, None, "wsum", max_batch=16, shared=gi, rows=3)],
                          budget_bytes=32 << 30)
-    say("serving loop: 24 products n=8192 + 6 bridge conversions n=16384")
+    say("serving loop: 24 products n=8192 + 6 bridge conversions + 6 imputation queries n=16384")
     done = srv.run(reqs)
     torch.cuda.synchronize()
-    assert len(done) == nm + nb
+    assert len(done) == nm + nb + ni
     assert max(q.batch for q in done) > 1
     assert srv.max_concurrent >= 2
     for q in done:
         if q.kind == "mul":
             alone = ctx8.mul_relin(rlk8, q.x, q.y)
+        elif q.kind == "impute":
+            alone = ctxi.weighted_sum(gi, q.w)
         else:
             alone = ctxb.bridge_to_bits(rlkb, q.x, 5)
         assert (down(q.result) == down(alone)).all(), q.rid
@@ -494,3 +506,130 @@ def test_validate_flags_noncanonical(dev):
     with pytest.raises(fhe.FheError) as ei:
         ctx.add(up(a), up(a))
     assert ei.value.status == -6
+
+
+# ------------------------------------- modular linear stage, bit-level side --
+
+@pytest.mark.parametrize("n,bits,k,nin,nout", [(256, 36, 3, 24, 5), (64, 55, 4, 40, 70), (16, 61, 2, 1, 3)])
+def test_weighted_sum_all_words(dev, n, bits, k, nin, nout):
+    """Every word of every weighted sum against the oracle: weights uniform in
+    [-8, 8] plus edge rows (all +8, all -8, zero, one weight near the row
+    limit); 40 inputs take two passes, 70 outputs two workgroup rows."""
+    qs = bfv.ntt_primes(n, bits, k)
+    say(f"weighted_sum n={n} k={k} nin={nin} nout={nout}")
+    P = bfv.Params(n, qs, 65537 if n >= 64 else 17, "coeff")
+    ctx = fhe.Context(n, qs, P.t, "coeff")
+    x = inputs.uniform_ciphertexts(n, qs, nin, 41, "x")
+    rng = np.random.default_rng(nin * 1000 + nout)
+    W = rng.integers(-8, 9, size=(nout, nin)).astype(np.int32)
+    W[0, :] = 8
+    W[1 % nout, :] = -8
+    if nout > 2:
+        W[2, :] = 0
+        W[2, nin - 1] = -(1 << 30) + 1
+    got = down(ctx.weighted_sum(up(x), W))
+    want = bfv.weighted_sum(P, x, W.tolist())
+    for m in range(nout):
+        assert (got[m] == want[m]).all(), f"output {m}"
+
+
+def test_weighted_sum_limits_and_empty(dev):
+    n = 64
+    qs = bfv.ntt_primes(n, 55, 2)
+    ctx = fhe.Context(n, qs, 65537, "coeff")
+    x = up(inputs.uniform_ciphertexts(n, qs, 2, 42, "x"))
+    with pytest.raises(fhe.FheError) as ei:
+        ctx.weighted_sum(x, np.array([[1 << 29, 1 << 29]], dtype=np.int32))  # row sum 2^30
+    assert ei.value.status == -1
+    out = ctx.weighted_sum(x[:0], np.zeros((3, 0), dtype=np.int32))
+    assert (down(out) == 0).all()
+
+
+def test_weighted_sum_imputation_shape_sampled(dev):
+    """The imputation-shaped stage at full size (n = 16384, eight 55-bit
+    primes, 24 inputs, 1500 outputs) on sampled words."""
+    cfg = inputs.CONFIGS["bridge_n16384"]
+    n, qs = cfg["n"], cfg["q"]
+    ctx = fhe.Context(n, qs, 65537, "slots")
+    nin, nout = 24, 1500
+    say(f"weighted_sum imputation shape {nout}x{nin}")
+    x = inputs.uniform_ciphertexts(n, qs, nin, 43, "g")
+    W = np.random.default_rng(43).integers(-8, 9, size=(nout, nin)).astype(np.int32)
+    import torch
+    got_d = ctx.weighted_sum(up(x), W)
+    rng = np.random.default_rng(44)
+    idx = [rng.integers(nout, size=400), rng.integers(2, size=400), rng.integers(len(qs), size=400),
+           rng.integers(n, size=400)]
+    got = fhe.to_numpy_u64(got_d[tuple(torch.as_tensor(v, device=got_d.device) for v in idx)].contiguous())
+    for s_, (m, pl, i, cf) in enumerate(zip(*[v.tolist() for v in idx])):
+        want = sum(int(W[m, j]) * int(x[j, pl, i, cf]) for j in range(nin)) % qs[i]
+        assert int(got[s_]) == want, (m, pl, i, cf)
+
+
+@pytest.mark.parametrize("n,bits,k", [(64, 55, 3), (256, 40, 2)])
+def test_gates_all_words(dev, n, bits, k):
+    """All eight gates against the oracle on uniform ciphertexts (the words
+    are defined for any input), including an output aliasing its input."""
+    qs = bfv.ntt_primes(n, bits, k)
+    say(f"gates n={n} k={k}")
+    P, km, pk, rlk, ctx, rlk_d = setup(n, qs, 17, "coeff", 45)
+    count = 3
+    a = inputs.uniform_ciphertexts(n, qs, count, 45, "a")
+    b = inputs.uniform_ciphertexts(n, qs, count, 45, "b")
+    c = inputs.uniform_ciphertexts(n, qs, count, 45, "c")
+    for op in fhe.GATES:
+        got = down(ctx.gate(rlk_d, op, up(a), up(b), up(c)))
+        for j in range(count):
+            assert (got[j] == bfv.gate(P, rlk, op, a[j], b[j], c[j])).all(), (op, j)
+    da = up(a)
+    ctx.gate(rlk_d, "XOR", da, up(b), out=da)
+    assert (down(da)[1] == bfv.gate(P, rlk, "XOR", a[1], b[1])).all()
+
+
+def test_less_than_and_argmax_all_words(dev):
+    """Comparison and three-class argmax against the oracle on uniform
+    ciphertexts, 3-bit vectors, two items."""
+    n, qs = 64, bfv.ntt_primes(64, 55, 3)
+    P, km, pk, rlk, ctx, rlk_d = setup(n, qs, 17, "coeff", 46)
+    count, nbits, ncls = 2, 3, 3
+    s = inputs.uniform_ciphertexts(n, qs, ncls * count * nbits, 46, "s").reshape(ncls, count, nbits, 2, len(qs), n)
+    say("less_than / argmax n=64")
+    lt = down(ctx.less_than(rlk_d, up(s[0]), up(s[1])))
+    for j in range(count):
+        assert (lt[j] == bfv.less_than(P, rlk, list(s[0, j]), list(s[1, j]))).all(), j
+    oh = down(ctx.argmax(rlk_d, up(s)))
+    for j in range(count):
+        want = bfv.argmax(P, rlk, [list(s[cl, j]) for cl in range(ncls)])
+        for cl in range(ncls):
+            assert (oh[cl, j] == want[cl]).all(), (cl, j)
+
+
+def test_bridge_then_argmax_decrypts_one_hot(dev):
+    """End to end at p = 17: encrypted class scores in [0, 17) -> bridge to 5
+    bits -> one-hot argmax (ties to the lower class); decryptions equal the
+    plain argmax and the words equal the oracle's."""
+    n, qs = 256, bfv.ntt_primes(256, 55, 6)
+    P, km, pk, rlk, ctx, rlk_d = setup(n, qs, 17, "coeff", 47)
+    scores = [[16, 3], [16, 9], [2, 9]]  # [class][item]: a tie at the top and a tie below
+    ncls, count = len(scores), len(scores[0])
+    r = inputs.encryption_randomness(n, ncls * count, 47)
+    cts = []
+    for cl in range(ncls):
+        for j in range(count):
+            pt = np.zeros(n, dtype=np.uint64)
+            pt[0] = scores[cl][j]
+            cts.append(bfv.encrypt(P, pk, pt, r["u"][cl * count + j], r["e"][cl * count + j]))
+    cts = np.stack(cts)
+    say("bridge + argmax n=256")
+    bits = ctx.bridge_to_bits(rlk_d, up(cts), 5)  # [ncls*count][5][2][k][n]
+    oh = down(ctx.argmax(rlk_d, bits.reshape(ncls, count, 5, 2, len(qs), n)))
+    bits_o = np.stack([bfv.bridge_to_bits(P, ct, rlk, 5)[0] for ct in cts])
+    assert (down(bits) == bits_o).all()
+    bits_o = bits_o.reshape(ncls, count, 5, 2, len(qs), n)
+    for j in range(count):
+        best = max(range(ncls), key=lambda cl: (scores[cl][j], -cl))
+        want = bfv.argmax(P, rlk, [list(bits_o[cl, j]) for cl in range(ncls)])
+        for cl in range(ncls):
+            assert (oh[cl, j] == want[cl]).all(), (cl, j)
+            d = bfv.decrypt(P, km["s"], oh[cl, j])
+            assert int(d[0]) == int(cl == best) and (d[1:] == 0).all(), (cl, j)
