@@ -27,6 +27,10 @@ paper's introduction):
 * Weighted sums (the case study's modular stage, Section 4.4): out[m] =
   sum_j w_mj ct_j mod q.  Gates (Section 3.1's expressions over {0, 1}), and
   from them a ripple comparison and a one-hot argmax.
+* Signed casts: SecureInt -> SecureMod (Section 3.2.2) as the two's complement
+  value, linear; SecureMod -> SecureInt (Section 3.2.4, its equation) as the
+  bridge's bits, a constant addition of 2^s - t by a ripple-carry adder of the
+  gates, and a MUX on the most significant bit.
 
 Where the paper is silent this oracle takes: Delta = floor(q/t); one key
 switching digit per RNS prime, [C2]_{q_i} in [0, q_i), with the CRT idempotent
@@ -547,6 +551,57 @@ def argmax(P: Params, rlk, scores, counter: Counter | None = None):
             out[a] = na if out[a] is None else mul_relin(P, out[a], na, rlk, counter)
             out[b] = l if out[b] is None else mul_relin(P, out[b], l, rlk, counter)
     return out
+
+
+def int_to_mod(P: Params, bits) -> np.ndarray:
+    """SecureInt -> SecureMod (Section 3.2.2): the two's complement value
+    sum_{i < s-1} 2^i x_i - 2^(s-1) x_{s-1}, which modulo t is the paper's
+    t - 2^s + sum_i 2^i x_i for a negative x and sum_i 2^i x_i otherwise;
+    evaluated linearly as Horner with a negated leading bit:
+    r = -x_{s-1}; r = r + r + x_i for i = s-2 .. 0."""
+    S = len(bits)
+    r = neg(P, bits[S - 1])
+    for i in range(S - 2, -1, -1):
+        r = add(P, add(P, r, r), bits[i])
+    return r
+
+
+def signed_bits(P: Params, X, rlk, counter: Counter | None = None):
+    """The sign adjustment of SecureMod -> SecureInt (Section 3.2.4, its
+    equation): from the unsigned bits X (least significant first, 2^s >= t),
+    A = X + (2^s - t) in s-bit arithmetic by a ripple-carry adder of the gates
+    (constant bit 0: A_i = X_i XOR carry, carry = X_i AND carry; constant bit
+    1: A_i = XNOR, carry = OR; a carry known to be zero is not multiplied),
+    then Y_i = MUX(X_{s-1}, A_i, X_i) = X_{s-1} (A_i - X_i) + X_i."""
+    S = len(X)
+    cst = (1 << S) - P.t
+    A, carry = [], None
+    for i in range(S):
+        ci = (cst >> i) & 1
+        if carry is None:
+            if ci:
+                A.append(add_plain(P, neg(P, X[i]), 1))
+                carry = np.array(X[i], copy=True)
+            else:
+                A.append(np.array(X[i], copy=True))
+            continue
+        p = mul_relin(P, X[i], carry, rlk, counter)
+        o = sub(P, add(P, X[i], carry), p)
+        x = sub(P, o, p)
+        if ci:
+            A.append(add_plain(P, neg(P, x), 1))
+            carry = o
+        else:
+            A.append(x)
+            carry = p
+    msb = X[S - 1]
+    return [add(P, mul_relin(P, msb, sub(P, A[i], X[i]), rlk, counter), X[i]) for i in range(S)]
+
+
+def mod_to_int(P: Params, ct_x, rlk, nbits: int, counter: Counter | None = None):
+    """SecureMod -> SecureInt: the bridge's unsigned bits, then signed_bits."""
+    X, _ = bridge_to_bits(P, ct_x, rlk, nbits, counter)
+    return np.stack(signed_bits(P, list(X), rlk, counter))
 
 
 def recompose(P: Params, bits) -> np.ndarray:

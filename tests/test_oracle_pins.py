@@ -588,3 +588,55 @@ def test_argmax_one_hot_ties_to_lower_class():
     best = [max(range(3), key=lambda c: (sc[c][s], -c)) for s in range(P.n)]
     for c in range(3):
         assert _dec_slots(P, km, oh[c]) == [int(b == c) for b in best], f"class {c}"
+
+
+# --------------------------------------------------------- signed casts ----
+
+def test_int_to_mod_all_5_bit_patterns():
+    """SecureInt -> SecureMod: every 5-bit two's complement pattern decrypts to
+    its signed value mod t (t = 257 slots), and at t = 17 to the paper's case
+    formula t - 2^s + sum 2^i x_i for negative values."""
+    P, km, pk, rlk = _slots_setup(35)
+    pats = [s % 32 for s in range(P.n)]
+    cts = _enc_slots(P, pk, [[(v >> i) & 1 for v in pats] for i in range(5)], 35)
+    got = _dec_slots(P, km, bfv.int_to_mod(P, cts))
+    signed = [v - 32 if v >= 16 else v for v in pats]
+    assert got == [v % P.t for v in signed]
+    assert [(17 - 32 + v) % 17 if v >= 16 else v for v in pats] == [v % 17 for v in signed]
+
+
+def test_signed_bits_two_complement():
+    """The sign adjustment at t = 257 (s = 9, 2^s - t = 255): every slot's
+    unsigned value x in [0, 257) comes out as the 9-bit two's complement of
+    x (x < 256) or x - 257 (x = 256), with the adder's and MUX's product
+    count."""
+    P, km, pk, rlk = _slots_setup(36, k=6)
+    rng = random.Random(11)
+    xs = [256, 255, 0, 1, 128, 127] + [rng.randrange(257) for _ in range(P.n - 6)]
+    X = _enc_slots(P, pk, [[(v >> i) & 1 for v in xs] for i in range(9)], 36)
+    cnt = bfv.Counter()
+    Y = bfv.signed_bits(P, X, rlk, cnt)
+    assert cnt.mul == 8 + 9  # adder: bits 1..8 (carry known zero before bit 0's set bit); MUX: 9
+    want = [(x - 257 if x >= 256 else x) % 512 for x in xs]
+    for i in range(9):
+        assert _dec_slots(P, km, Y[i]) == [(w >> i) & 1 for w in want], f"bit {i}"
+
+
+def test_mod_to_int_round_trip_p17():
+    """p = 17 end to end: x in {16, 5, 0} -> bridge -> signed bits (16 is -1)
+    -> int_to_mod decrypts back to x."""
+    n = 32
+    P = bfv.Params(n, bfv.ntt_primes(n, 55, 5), 17, "coeff")
+    km, pk, rlk = keys_small(P, seed=37)
+    xs = [16, 5, 0]
+    r = inputs.encryption_randomness(n, len(xs), 37)
+    for j, x in enumerate(xs):
+        pt = np.zeros(n, dtype=np.uint64)
+        pt[0] = x
+        ct = bfv.encrypt(P, pk, pt, r["u"][j], r["e"][j])
+        Y = bfv.mod_to_int(P, ct, rlk, 5)
+        v = x - 17 if x >= 16 else x
+        for i in range(5):
+            d = bfv.decrypt(P, km["s"], Y[i])
+            assert int(d[0]) == ((v % 32) >> i) & 1 and (d[1:] == 0).all(), (x, i)
+        assert int(bfv.decrypt(P, km["s"], bfv.int_to_mod(P, list(Y)))[0]) == x
