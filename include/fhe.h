@@ -78,7 +78,8 @@ enum {
     FHE_OP_WEIGHTED_SUM = 8, /* count = nout * nin weights */
     FHE_OP_GATE = 9,         /* count = ciphertexts per operand */
     FHE_OP_COMPARE = 10,     /* count = pairs of bit vectors */
-    FHE_OP_ARGMAX = 11       /* count = score sets */
+    FHE_OP_ARGMAX = 11,      /* count = score sets */
+    FHE_OP_MOD_TO_INT = 12   /* count = inputs */
 };
 
 /* gates of fhe_gate */
@@ -291,6 +292,30 @@ fhe_status fhe_less_than(fhe_ctx *ctx, const uint64_t *rlk_dev, const uint64_t *
 fhe_status fhe_argmax(fhe_ctx *ctx, const uint64_t *rlk_dev, const uint64_t *scores, uint32_t ncls,
                       uint32_t nbits, uint64_t *out, size_t count, void *ws, size_t ws_bytes,
                       hipStream_t stream);
+
+/* The paper's signed casts.
+ * SecureInt -> SecureMod (Section 3.2.2): out[j] encrypts the two's complement
+ * value sum_{b < nbits-1} 2^b bits[j][b] - 2^(nbits-1) bits[j][nbits-1] modulo
+ * t, i.e. the paper's t - 2^s + sum 2^b x_b for a negative input; evaluated
+ * linearly (Horner with the leading bit negated: no multiplication, where the
+ * paper's selection spends two).  bits device [count][nbits][2][k][n]; out
+ * device [count][2][k][n]; needs 2^nbits >= t for the value to fit. */
+fhe_status fhe_int_to_mod(fhe_ctx *ctx, const uint64_t *bits, uint32_t nbits, uint64_t *out, size_t count,
+                          hipStream_t stream);
+
+/* SecureMod -> SecureInt (Section 3.2.4, its equation): X = the unsigned bits
+ * of x (fhe_bridge_to_bits), then the sign adjustment, evaluated as
+ *   A = X + (2^s - t) in s-bit arithmetic, a ripple-carry adder of the gates
+ *       over the constant's bits (bit 0: A_i = X_i XOR carry, carry = X_i AND
+ *       carry; bit 1: A_i = XNOR, carry = OR; no product while the carry is
+ *       known to be zero),
+ *   Y_i = MUX(X_{s-1}, A_i, X_i) = X_{s-1} (A_i - X_i) + X_i,
+ * so x >= 2^(s-1) (the values the paper reads as negative) becomes x - t in
+ * two's complement.  x device [count][2][k][n]; bits device
+ * [count][nbits][2][k][n] (least significant first).  Preconditions of
+ * fhe_bridge_to_bits.  ws: FHE_OP_MOD_TO_INT bytes for count. */
+fhe_status fhe_mod_to_int(fhe_ctx *ctx, const uint64_t *rlk_dev, const uint64_t *x, uint32_t nbits,
+                          uint64_t *bits, size_t count, void *ws, size_t ws_bytes, hipStream_t stream);
 
 /* The paper's SecureUint -> SecureMod cast (Section 3.2.1, Horner):
  * out[j] = sum_b 2^b bits[j][b], evaluated as r = bit_{nbits-1}; r = r + r + bit_b.

@@ -734,6 +734,11 @@ size_t fhe_workspace_bytes(const fhe_ctx *c, int op, size_t count) {
             return 6 * count * ct_words(c) * 8 + fhe_workspace_bytes(c, FHE_OP_MUL_RELIN, count);
         case FHE_OP_ARGMAX:
             return 2 * count * ct_words(c) * 8 + fhe_workspace_bytes(c, FHE_OP_COMPARE, count);
+        case FHE_OP_MOD_TO_INT: {
+            const size_t a = fhe_workspace_bytes(c, FHE_OP_BRIDGE, count);
+            const size_t b = 7 * count * ct_words(c) * 8 + fhe_workspace_bytes(c, FHE_OP_MUL_RELIN, count);
+            return a > b ? a : b;
+        }
     }
     return 0;
 }
@@ -1135,8 +1140,11 @@ fhe_status fhe_bits_to_mod(fhe_ctx *c, const uint64_t *bits, uint32_t nbits, uin
     if (!bits || !out) return FHE_EINVAL;
     if (overlaps2(out, count * ct_words(c) * 8, bits, count * nbits * ct_words(c) * 8)) return FHE_EINVAL;
     return run(c, KK_ELEMENTWISE, st,
-               [&] { return launch_horner(c->dev, bits, (int)nbits, out, count, st); });
+               [&] { return launch_horner(c->dev, bits, (int)nbits, out, count, 0, st); });
 }
+
+
+
 
 // ------------------------------------------------- modular linear stage ----
 
@@ -1324,6 +1332,81 @@ fhe_status fhe_argmax(fhe_ctx *c, const uint64_t *rlk, const uint64_t *scores, u
             first[a] = first[b] = false;
         }
     return FHE_OK;
+}
+
+// ---------------------------------------------------------- signed casts ----
+
+fhe_status fhe_int_to_mod(fhe_ctx *c, const uint64_t *bits, uint32_t nbits, uint64_t *out, size_t count,
+                          hipStream_t st) {
+    if (!c) return FHE_EINVAL;
+    if (nbits == 0) return FHE_EINVAL;
+    if (count == 0) return FHE_OK;
+    if (!bits || !out) return FHE_EINVAL;
+    if (overlaps2(out, count * ct_words(c) * 8, bits, count * nbits * ct_words(c) * 8)) return FHE_EINVAL;
+    FHE_TRY(check_canonical(c, bits, count * nbits * 2 * c->k, c->k, 0, st));
+    return run(c, KK_ELEMENTWISE, st,
+               [&] { return launch_horner(c->dev, bits, (int)nbits, out, count, 1, st); });
+}
+
+// In place on bits [count][nbits] (least significant first): the unsigned
+// value X becomes the signed bits Y of the paper's SecureMod -> SecureInt
+// equation (constant 2^nbits - t added by a ripple-carry adder of the gates,
+// then a MUX on the leading bit).  Bit i is read (gathered) before it is
+// overwritten, and the leading bit is gathered first.
+static fhe_status signed_bits_impl(fhe_ctx *c, const uint64_t *rlk, uint64_t *bits, uint32_t nbits,
+                                   size_t count, void *ws, hipStream_t st) {
+    const size_t ctw = ct_words(c), cw = count * ctw, ctb = ctw * 8;
+    uint64_t *Msb = (uint64_t *)ws, *Xi = Msb + cw, *Ca = Xi + cw, *Pp = Ca + cw, *O = Pp + cw, *Ai = O + cw,
+             *T = Ai + cw;
+    void *mws = T + cw;
+    const uint64_t cst = (1ull << nbits) - c->t;
+    FHE_TRY(gather_bit(c, bits, nbits, nbits - 1, Msb, count, st));
+    bool have_carry = false;
+    for (uint32_t i = 0; i < nbits; i++) {
+        FHE_TRY(gather_bit(c, bits, nbits, i, Xi, count, st));
+        const bool ci = (cst >> i) & 1;
+        if (!have_carry) {
+            if (ci) {
+                FHE_TRY(one_minus(c, Xi, Ai, count, st));
+                FHE_HIP(hipMemcpyAsync(Ca, Xi, cw * 8, hipMemcpyDeviceToDevice, st));
+                have_carry = true;
+            } else {
+                FHE_HIP(hipMemcpyAsync(Ai, Xi, cw * 8, hipMemcpyDeviceToDevice, st));
+            }
+        } else {
+            FHE_TRY(mul_relin_impl(c, rlk, Xi, Ca, Pp, count, mws, st));  // p = X_i carry
+            FHE_TRY(ew(c, Xi, Ca, O, count, 0, st));                       // OR
+            FHE_TRY(ew(c, O, Pp, O, count, 1, st));
+            FHE_TRY(ew(c, O, Pp, Ai, count, 1, st));                       // XOR
+            if (ci) {
+                FHE_TRY(one_minus(c, Ai, Ai, count, st));  // XNOR, carry = OR
+                uint64_t *t = Ca;
+                Ca = O;
+                O = t;
+            } else {  // carry = AND
+                uint64_t *t = Ca;
+                Ca = Pp;
+                Pp = t;
+            }
+        }
+        // Y_i = MSB (A_i - X_i) + X_i
+        FHE_TRY(ew(c, Ai, Xi, T, count, 1, st));
+        FHE_TRY(mul_relin_impl(c, rlk, Msb, T, T, count, mws, st));
+        FHE_TRY(ew(c, T, Xi, T, count, 0, st));
+        FHE_HIP(hipMemcpy2DAsync(bits + (size_t)i * ctw, nbits * ctb, T, ctb, ctb, count, hipMemcpyDeviceToDevice,
+                                 st));
+    }
+    return FHE_OK;
+}
+
+fhe_status fhe_mod_to_int(fhe_ctx *c, const uint64_t *rlk, const uint64_t *x, uint32_t nbits, uint64_t *bits,
+                          size_t count, void *ws, size_t ws_bytes, hipStream_t st) {
+    if (!c) return FHE_EINVAL;
+    if (count == 0) return FHE_OK;
+    if (!ws) return FHE_EINVAL;
+    if (ws_bytes < fhe_workspace_bytes(c, FHE_OP_MOD_TO_INT, count)) return FHE_EWORKSPACE;
+    FHE_TRY(fhe_bridge_to_bits(c, rlk, x, nbits, bits, nullptr, count, ws, ws_bytes, st));
+    return signed_bits_impl(c, rlk, bits, nbits, count, ws, st);
 }
 
 fhe_status fhe_ntt(fhe_ctx *c, int inverse, uint64_t *polys, size_t count, hipStream_t st) {

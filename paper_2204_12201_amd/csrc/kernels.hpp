@@ -103,8 +103,9 @@ hipError_t launch_encrypt_finish(const DevCtx &c, const uint64_t *prod, const in
                                  const uint64_t *pt, uint64_t *ct, size_t count, hipStream_t s);
 hipError_t launch_bridge_combine(const DevCtx &c, const uint64_t *y, uint64_t *bits, uint64_t *eq,
                                  size_t count, int tcount, int nbits, int c0, hipStream_t s);
+// out = sum_b 2^b bits[b] by Horner; signed_top: the leading bit weighs -2^(nbits-1)
 hipError_t launch_horner(const DevCtx &c, const uint64_t *bits, int nbits, uint64_t *out,
-                         size_t count, hipStream_t s);
+                         size_t count, int signed_top, hipStream_t s);
 // flag[0] |= 1 if some word of rows [nrows][n] (limb = row % kmod + off) is >= its prime
 hipError_t launch_validate(const DevCtx &c, const uint64_t *a, size_t nrows, int kmod, int off,
                            unsigned int *flag, hipStream_t s);

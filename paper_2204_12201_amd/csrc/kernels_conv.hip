@@ -566,8 +566,9 @@ __global__ __launch_bounds__(256) void k_bridge_combine(DevCtx c, const uint64_t
 }
 
 // out = sum_b 2^b bits_b by Horner: r = bits_{nb-1}; r = r + r + bits_b.
+// signed_top: the leading bit enters negated (two's complement weight).
 __global__ void k_horner(DevCtx c, const uint64_t *__restrict__ bits, int nbits,
-                         uint64_t *__restrict__ out, size_t count) {
+                         uint64_t *__restrict__ out, size_t count, int signed_top) {
     const size_t n = c.n, k = c.k, ctw = 2 * k * n;
     const size_t total = count * ctw;
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total;
@@ -575,6 +576,7 @@ __global__ void k_horner(DevCtx c, const uint64_t *__restrict__ bits, int nbits,
         const size_t w = i % ctw, j = i / ctw;
         const uint64_t q = c.pc[(w / n) % k].q;
         uint64_t r = bits[(j * nbits + nbits - 1) * ctw + w];
+        if (signed_top) r = sub_mod(0, r, q);
         for (int b = nbits - 2; b >= 0; b--) {
             r = add_mod(r, r, q);
             r = add_mod(r, bits[(j * nbits + b) * ctw + w], q);
@@ -750,10 +752,10 @@ hipError_t launch_bridge_combine(const DevCtx &c, const uint64_t *y, uint64_t *b
 }
 
 hipError_t launch_horner(const DevCtx &c, const uint64_t *bits, int nbits, uint64_t *out,
-                         size_t count, hipStream_t s) {
+                         size_t count, int signed_top, hipStream_t s) {
     const size_t words = count * 2 * c.k * (size_t)c.n;
     if (words == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_horner, dim3(grid_for(words)), dim3(256), 0, s, c, bits, nbits, out, count);
+    hipLaunchKernelGGL(k_horner, dim3(grid_for(words)), dim3(256), 0, s, c, bits, nbits, out, count, signed_top);
     return hipGetLastError();
 }
 

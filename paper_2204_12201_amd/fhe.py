@@ -18,7 +18,7 @@ LIBPATH = os.path.join(HERE, "libfhe.so")
 
 ENC_SLOTS, ENC_COEFF = 0, 1
 OP_MUL_RELIN, OP_SQUARE_RELIN, OP_BRIDGE, OP_KEYGEN, OP_ENCRYPT, OP_DECRYPT, OP_RLK_IMPORT = range(1, 8)
-OP_WEIGHTED_SUM, OP_GATE, OP_COMPARE, OP_ARGMAX = range(8, 12)
+OP_WEIGHTED_SUM, OP_GATE, OP_COMPARE, OP_ARGMAX, OP_MOD_TO_INT = range(8, 13)
 GATES = {"AND": 0, "NAND": 1, "OR": 2, "NOR": 3, "XOR": 4, "XNOR": 5, "NOT": 6, "MUX": 7}
 
 STATUS = {0: "ok", -1: "invalid argument", -2: "parameter set rejected", -3: "device allocation failed",
@@ -77,6 +77,8 @@ _SIGS = [
     ("fhe_gate", _I, [_P, _P, _I, _P, _P, _P, _P, _Z, _P, _Z, _P]),
     ("fhe_less_than", _I, [_P, _P, _P, _P, _U32, _P, _Z, _P, _Z, _P]),
     ("fhe_argmax", _I, [_P, _P, _P, _U32, _U32, _P, _Z, _P, _Z, _P]),
+    ("fhe_int_to_mod", _I, [_P, _P, _U32, _P, _Z, _P]),
+    ("fhe_mod_to_int", _I, [_P, _P, _P, _U32, _P, _Z, _P, _Z, _P]),
     ("fhe_ntt", _I, [_P, _I, _P, _Z, _P]),
     ("fhe_set_timing", _I, [_P, _I]),
     ("fhe_kernel_kinds", _I, []),
@@ -365,6 +367,26 @@ class Context:
         ws, _ = self.workspace(OP_ARGMAX, count)
         _check(lib().fhe_argmax(self._h, _dptr(rlk), _dptr(scores), ncls, nbits, _dptr(out), count, _dptr(ws),
                                 ws.numel(), _stream()), "fhe_argmax")
+        return out
+
+    def int_to_mod(self, bits, out=None):
+        """SecureInt -> SecureMod: bits device [count][nbits][2][k][n]
+        (two's complement, least significant first) -> [count][2][k][n]."""
+        count, nbits = bits.shape[0], bits.shape[1]
+        out = self.empty_ct(count) if out is None else out
+        _check(lib().fhe_int_to_mod(self._h, _dptr(bits), nbits, _dptr(out), count, _stream()), "fhe_int_to_mod")
+        return out
+
+    def mod_to_int(self, rlk, x, nbits: int, out=None):
+        """SecureMod -> SecureInt: x device [count][2][k][n] -> two's
+        complement bits [count][nbits][2][k][n]."""
+        import torch
+        count = x.shape[0]
+        if out is None:
+            out = torch.empty((count, nbits, 2, self.k, self.n), dtype=torch.int64, device=self.device)
+        ws, _ = self.workspace(OP_MOD_TO_INT, count)
+        _check(lib().fhe_mod_to_int(self._h, _dptr(rlk), _dptr(x), nbits, _dptr(out), count, _dptr(ws),
+                                    ws.numel(), _stream()), "fhe_mod_to_int")
         return out
 
     def ntt(self, polys, inverse: bool = False):

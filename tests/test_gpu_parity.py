@@ -633,3 +633,36 @@ def test_bridge_then_argmax_decrypts_one_hot(dev):
             assert (oh[cl, j] == want[cl]).all(), (cl, j)
             d = bfv.decrypt(P, km["s"], oh[cl, j])
             assert int(d[0]) == int(cl == best) and (d[1:] == 0).all(), (cl, j)
+
+
+def test_signed_casts_words_and_round_trip(dev):
+    """SecureInt -> SecureMod on uniform bit ciphertexts (words), and
+    SecureMod -> SecureInt at p = 17 through the bridge (words, decryptions,
+    and the round trip back to x)."""
+    n, qs = 64, bfv.ntt_primes(64, 55, 5)
+    P, km, pk, rlk, ctx, rlk_d = setup(n, qs, 17, "coeff", 48)
+    u = inputs.uniform_ciphertexts(n, qs, 2 * 5, 48, "u").reshape(2, 5, 2, len(qs), n)
+    say("signed casts n=64")
+    got = down(ctx.int_to_mod(up(u)))
+    for j in range(2):
+        assert (got[j] == bfv.int_to_mod(P, list(u[j]))).all(), j
+    xs = [16, 5]
+    r = inputs.encryption_randomness(n, len(xs), 48)
+    cts = []
+    for j, x in enumerate(xs):
+        pt = np.zeros(n, dtype=np.uint64)
+        pt[0] = x
+        cts.append(bfv.encrypt(P, pk, pt, r["u"][j], r["e"][j]))
+    cts = np.stack(cts)
+    Y = ctx.mod_to_int(rlk_d, up(cts), 5)
+    Yh = down(Y)
+    for j, x in enumerate(xs):
+        want = bfv.mod_to_int(P, cts[j], rlk, 5)
+        assert (Yh[j] == want).all(), j
+        v = x - 17 if x >= 16 else x
+        for i in range(5):
+            d = bfv.decrypt(P, km["s"], Yh[j, i])
+            assert int(d[0]) == ((v % 32) >> i) & 1 and (d[1:] == 0).all(), (x, i)
+    back = down(ctx.int_to_mod(Y))
+    for j, x in enumerate(xs):
+        assert int(bfv.decrypt(P, km["s"], back[j])[0]) == x
