@@ -477,6 +477,20 @@ def imputation_leg(fhe, inputs, torch, reps=3, seed=11, subset=32):
                             "argmax_ms": (t2 - t1) * 1e3, "samples_per_s": subset / (t2 - t0),
                             "argmax_mul_relin": ncls * (ncls - 1) // 2 * (2 * cfg["nbits"] - 1) + ncls,
                             "decrypts_one_hot": ok}
+    # signed casts of the same encrypted scores: SecureMod -> SecureInt (bridge,
+    # constant adder, MUX) and back (linear)
+    xs = x[:subset]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ybits = ctxb.mod_to_int(rlk, xs, cfg["nbits"])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    back = ctxb.int_to_mod(ybits)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    dec = ctxb.decrypt(km["s"], back)
+    res["signed_casts"] = {"inputs": subset, "mod_to_int_ms": (t1 - t0) * 1e3, "int_to_mod_ms": (t2 - t1) * 1e3,
+                           "round_trip_ok": bool((dec[:, 0] == scores.reshape(-1)[:subset]).all())}
     return res
 
 
