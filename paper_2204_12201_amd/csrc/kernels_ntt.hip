@@ -390,7 +390,7 @@ __global__ __launch_bounds__(Geo<L>::T) void k_square_tensor(DevCtx c, const uin
 // Key switching fused: grid (k limbs j, items).  For every digit i the row
 // [C2]_{q_i} is reduced mod q_j, transformed and multiply-accumulated with the
 // key rows into two register accumulators (lazy, below 2q); both accumulators
-// are then inverse transformed and added into C0, C1.  The transformed digits
+// are then inverse transformed side by side and added into C0, C1.  The transformed digits
 // never leave the chip.  rlk layout [digit i][comp l][limb j][n], transform
 // domain, each entry premultiplied by n^-1 2^64 so that the Montgomery products
 // give digit * key / n and the inverse transforms need no scaling.
@@ -476,14 +476,13 @@ __global__ __launch_bounds__(Geo<L>::T) void k_relin_fused(DevCtx c, const uint6
     }
     uint64_t *o0 = out + (item * 2 * k + j) * (size_t)n;
     uint64_t *o1 = out + ((item * 2 + 1) * k + j) * (size_t)n;
-    ntt_inv_regs<L, 4, LAZY>(acc0, lds, tid, c.itw + (size_t)j * n, q);
+    ntt_inv_regs2<L, 4, LAZY>(acc0, acc1, lds, tid, c.itw + (size_t)j * n, q);
     const uint32_t t2 = fresh(tid);
 #pragma unroll
     for (int s = 0; s < 16; s++) {
         const uint32_t idx = natural_index<L>(t2, s);
         o0[idx] = add_mod(canon8(acc0[s], q), o0[idx], q);
     }
-    ntt_inv_regs<L, 4, LAZY>(acc1, lds, tid, c.itw + (size_t)j * n, q);
     const uint32_t t3 = fresh(tid);
 #pragma unroll
     for (int s = 0; s < 16; s++) {
