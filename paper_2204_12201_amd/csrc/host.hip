@@ -669,6 +669,12 @@ fhe_status fhe_ctx_create(const fhe_params *p, int hip_device, fhe_ctx **out) {
     d.mrc_q = (const MrcConst *)c->d_mrc_q;
     d.mrc_p = (const MrcConst *)c->d_mrc_p;
     d.fallback = (unsigned long long *)c->d_counters;
+    uint64_t qmin = c->primes[0], qmax = c->primes[0];
+    for (uint32_t i = 1; i < k; i++) {
+        qmin = c->primes[i] < qmin ? c->primes[i] : qmin;
+        qmax = c->primes[i] > qmax ? c->primes[i] : qmax;
+    }
+    d.digit_raw = (u128)qmax < (u128)qmin * 4;
     d.lazy_q = d.lazy_all = 1;
     d.lazy_limbs = 0;
     for (uint32_t i = 0; i < c->K; i++) {

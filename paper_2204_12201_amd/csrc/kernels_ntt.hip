@@ -399,8 +399,10 @@ __global__ __launch_bounds__(Geo<L>::T) void k_square_tensor(DevCtx c, const uin
 // q_j is below 2^64 / (4 (L + 1)), so the digit transforms skip the
 // conditional subtractions (digits below 4 (L + 1) q_j, still a valid
 // Montgomery operand against key entries below q_j) and the inverse transforms
-// half of theirs (accumulators below 8q_j).
-template <int L, bool LAZY>
+// half of theirs (accumulators below 8q_j).  RAW (with LAZY): every Q prime
+// is below 4 min_j q_j, so a digit word (below q_i) is already a valid lazy
+// transform input modulo q_j and enters without the Shoup reduction by 1.
+template <int L, bool LAZY, bool RAW>
 __global__ __launch_bounds__(Geo<L>::T) void k_relin_fused(DevCtx c, const uint64_t *__restrict__ C2,
                                                           const uint64_t *__restrict__ rlk,
                                                           uint64_t *__restrict__ out) {
@@ -427,12 +429,17 @@ __global__ __launch_bounds__(Geo<L>::T) void k_relin_fused(DevCtx c, const uint6
         if (PREFETCH && i > 0) {
             prefetch_wait();
 #pragma unroll
-            for (int s = 0; s < 16; s++)  // digit mod q_j, < 4q
-                x[s] = mul_shoup_lazy4(prefetched(lds, t0, s), 1, one_p, q);
+            for (int s = 0; s < 16; s++) {  // digit mod q_j, < 4q
+                const uint64_t v = prefetched(lds, t0, s);
+                x[s] = RAW ? v : mul_shoup_lazy4(v, 1, one_p, q);
+            }
         } else {
             const uint64_t *src = c2 + (size_t)i * n;
 #pragma unroll
-            for (int s = 0; s < 16; s++) x[s] = mul_shoup_lazy4(src[natural_index<L>(t0, s)], 1, one_p, q);
+            for (int s = 0; s < 16; s++) {
+                const uint64_t v = src[natural_index<L>(t0, s)];
+                x[s] = RAW ? v : mul_shoup_lazy4(v, 1, one_p, q);
+            }
         }
         auto hook = [&]() {
             if constexpr (PREFETCH)
@@ -566,12 +573,13 @@ struct NttL {
     }
     static hipError_t relin_fused(const DevCtx &c, const uint64_t *C2, const uint64_t *rlk, uint64_t *out,
                                   size_t items, hipStream_t s) {
-        if (c.lazy_q)
-            hipLaunchKernelGGL((k_relin_fused<L, true>), dim3(c.k, (unsigned)items), dim3(Geo<L>::T), 0, s, c,
-                               C2, rlk, out);
+        const dim3 grid(c.k, (unsigned)items);
+        if (c.lazy_q && c.digit_raw)
+            hipLaunchKernelGGL((k_relin_fused<L, true, true>), grid, dim3(Geo<L>::T), 0, s, c, C2, rlk, out);
+        else if (c.lazy_q)
+            hipLaunchKernelGGL((k_relin_fused<L, true, false>), grid, dim3(Geo<L>::T), 0, s, c, C2, rlk, out);
         else
-            hipLaunchKernelGGL((k_relin_fused<L, false>), dim3(c.k, (unsigned)items), dim3(Geo<L>::T), 0, s,
-                               c, C2, rlk, out);
+            hipLaunchKernelGGL((k_relin_fused<L, false, false>), grid, dim3(Geo<L>::T), 0, s, c, C2, rlk, out);
         return hipGetLastError();
     }
 };

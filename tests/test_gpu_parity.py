@@ -158,6 +158,25 @@ def test_mul_relin_fused_batch_all_words(dev, n, bits, k):
             assert (sq[j] == bfv.mul_relin(P, a[j], a[j], rlk)).all(), f"square {j}"
 
 
+def test_mul_relin_primes_of_mixed_sizes(dev):
+    """Q primes of 55 and 40 bits (more than a factor 4 apart): the key
+    switching reduces every digit modulo the target prime before its
+    transform; all words of products and squares against the oracle."""
+    n = 1024
+    qs = bfv.ntt_primes(n, 55, 2) + bfv.ntt_primes(n, 40, 1)
+    P, km, pk, rlk, ctx, rlk_d = setup(n, qs, 65537, "slots", 17)
+    count = 40
+    say(f"mul_relin mixed prime sizes n={n} x{count}")
+    a = inputs.uniform_ciphertexts(n, qs, count, 17, "a")
+    b = inputs.uniform_ciphertexts(n, qs, count, 17, "b")
+    out = down(ctx.mul_relin(rlk_d, up(a), up(b)))
+    da = up(a)
+    sq = down(ctx.mul_relin(rlk_d, da, da))
+    for j in range(0, count, 3):
+        assert (out[j] == bfv.mul_relin(P, a[j], b[j], rlk)).all(), f"product {j}"
+        assert (sq[j] == bfv.mul_relin(P, a[j], a[j], rlk)).all(), f"square {j}"
+
+
 def test_mul_relin_multi_mixed_sizes(dev):
     """One fhe_mul_relin_multi call over parts of three contexts (n = 4096,
     8192, 16384 with their configured primes, t = 65537; one n=4096 part large
