@@ -685,6 +685,9 @@ fhe_status fhe_ctx_create(const fhe_params *p, int hip_device, fhe_ctx **out) {
             if (i < k) d.lazy_q = 0;
         }
     }
+    // lazy key switching also sums up to 16 products below 2q unreduced
+    for (uint32_t i = 0; i < k; i++)
+        if (c->primes[i] >= (1ull << 59)) d.lazy_q = 0;
     // default chunk: about 8 GiB of product workspace
     size_t per = item_words_mul(c, false) * 8;
     c->default_limit = ((size_t)8 << 30) / per;

@@ -19,7 +19,7 @@ struct DevCtx {
     const MrcConst *mrc_q;  // basis Q -> targets P (and t in the last slot)
     const MrcConst *mrc_p;  // basis P -> targets Q
     unsigned long long *fallback;  // count of coefficients that took the exact path
-    int lazy_q;             // every Q prime below 2^64 / (4 (L + 1)): lazy digit transforms
+    int lazy_q;             // every Q prime below 2^64 / (4 (L + 1)) and 2^59: lazy key switching
     int lazy_all;           // every prime of Q and P below 2^64 / (4 (L + 1)): lazy transforms
     uint64_t lazy_limbs;    // bit l: prime l (Q then P) below 2^64 / (4 (L + 1))
     int digit_raw;          // every Q prime below 4 min(Q): digits enter the lazy transforms as they are

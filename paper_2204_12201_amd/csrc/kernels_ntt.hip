@@ -389,14 +389,15 @@ __global__ __launch_bounds__(Geo<L>::T) void k_square_tensor(DevCtx c, const uin
 
 // Key switching fused: grid (k limbs j, items).  For every digit i the row
 // [C2]_{q_i} is reduced mod q_j, transformed and multiply-accumulated with the
-// key rows into two register accumulators (lazy, below 2q); both accumulators
-// are then inverse transformed side by side and added into C0, C1.  The transformed digits
+// key rows into two register accumulators (below 2q, or with LAZY summed
+// unreduced and brought below 4q once at the end); both accumulators are then
+// inverse transformed side by side and added into C0, C1.  The transformed digits
 // never leave the chip.  rlk layout [digit i][comp l][limb j][n], transform
 // domain, each entry premultiplied by n^-1 2^64 so that the Montgomery products
 // give digit * key / n and the inverse transforms need no scaling.
 // While digit i finishes its transform and inner product, each wave copies its
 // share of digit i + 1 into its own LDS block (prefetch_row_lds).  LAZY: every
-// q_j is below 2^64 / (4 (L + 1)), so the digit transforms skip the
+// q_j is below 2^64 / (4 (L + 1)) and 2^59, so the digit transforms skip the
 // conditional subtractions (digits below 4 (L + 1) q_j, still a valid
 // Montgomery operand against key entries below q_j) and the inverse transforms
 // half of theirs (accumulators below 8q_j).  RAW (with LAZY): every Q prime
@@ -471,9 +472,14 @@ __global__ __launch_bounds__(Geo<L>::T) void k_relin_fused(DevCtx c, const uint6
             asm volatile("" ::: "memory");
 #pragma unroll
             for (int u = 0; u < 2; u++) {
-                // digit < 4 (L + 1) q and key entries < q: products below q 2^64
-                acc0[s0 + u] = csub(acc0[s0 + u] + mont_mul_lazy(x[s0 + u], ka[u], q, qi), q2);
-                acc1[s0 + u] = csub(acc1[s0 + u] + mont_mul_lazy(x[s0 + u], kb[u], q, qi), q2);
+                // digit < 4 (L + 1) q and key entries < q: products below q 2^64,
+                // each Montgomery result below 2q.  LAZY (q < 2^59): up to 16
+                // of them are summed unreduced (below 32q); otherwise the sum is
+                // kept below 2q.
+                const uint64_t m0 = mont_mul_lazy(x[s0 + u], ka[u], q, qi);
+                const uint64_t m1 = mont_mul_lazy(x[s0 + u], kb[u], q, qi);
+                acc0[s0 + u] = LAZY ? acc0[s0 + u] + m0 : csub(acc0[s0 + u] + m0, q2);
+                acc1[s0 + u] = LAZY ? acc1[s0 + u] + m1 : csub(acc1[s0 + u] + m1, q2);
             }
             ka[0] = ka[2];
             ka[1] = ka[3];
@@ -483,6 +489,13 @@ __global__ __launch_bounds__(Geo<L>::T) void k_relin_fused(DevCtx c, const uint6
     }
     uint64_t *o0 = out + (item * 2 * k + j) * (size_t)n;
     uint64_t *o1 = out + ((item * 2 + 1) * k + j) * (size_t)n;
+    if constexpr (LAZY) {
+#pragma unroll
+        for (int s = 0; s < 16; s++) {  // below 32q (k <= 16) -> below 4q
+            acc0[s] = csub(csub(csub(acc0[s], q << 4), q << 3), q << 2);
+            acc1[s] = csub(csub(csub(acc1[s], q << 4), q << 3), q << 2);
+        }
+    }
     ntt_inv_regs2<L, 4, LAZY>(acc0, acc1, lds, tid, c.itw + (size_t)j * n, q);
     const uint32_t t2 = fresh(tid);
 #pragma unroll
