@@ -109,6 +109,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="length of the Poisson arrival window of the serving leg")
+    ap.add_argument("--no-calib", action="store_true",
+                    help="skip the VALU / copy calibration probe (M0) run beside the roofline")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB device-to-device copy first (HBM counter scale)")
     args = ap.parse_args()
@@ -226,6 +228,8 @@ def main():
         print("[bench] plain vs batched done", file=sys.stderr, flush=True)
 
     if not args.no_plain:
+        out["autotune"] = autotune_leg(fhe, inputs, torch)
+        print("[bench] autotune done", file=sys.stderr, flush=True)
         out["ntt_rows"] = ntt_rows_leg(fhe, inputs, torch)
         out["c0_n4096"] = c0_leg(fhe, inputs, torch)
         print("[bench] transform rows and n=4096 products done", file=sys.stderr, flush=True)
@@ -236,6 +240,14 @@ def main():
         print("[bench] imputation-shaped stages done", file=sys.stderr, flush=True)
         out["serving"] = serving_leg(fhe, inputs, torch, seconds=args.serve_seconds)
         print("[bench] serving loop done", file=sys.stderr, flush=True)
+
+    if not args.no_calib:
+        cal = calibration()
+        if cal:
+            out["calibration"] = cal
+            if "bfly_peak_calibrated" in cal and roofline.get("achieved"):
+                roofline["frac_of_calibrated_issue"] = roofline["achieved"] * 1e12 / cal["bfly_peak_calibrated"]
+        print("[bench] calibration done", file=sys.stderr, flush=True)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inputs)
@@ -304,6 +316,41 @@ def plain_vs_batched(ctx_factory, fhe, inputs, torch, B=256, single_calls=200,
             "plain_mul_relin_per_s": plain, "batched_over_plain": batched / plain,
             "single_call_p50_ms": percentile(lat_ms, 50), "single_call_p99_ms": percentile(lat_ms, 99),
             "batched_kernel_ms": kern, "sweep": rows}
+
+
+def autotune_leg(fhe, inputs, torch, sizes=(1, 4, 16, 256), reps=5):
+    """fhe_autotune_mul_relin on the n = 16384, t = 65537 products: per batch
+    size, the rate with the default launch shape, the shape the autotuner
+    keeps (chunk cap, fused or unfused transforms) and the rate with it (each
+    size on a fresh context)."""
+    cfg = inputs.CONFIGS["bridge_n16384"]
+    n, qs = cfg["n"], cfg["q"]
+    bmax = max(sizes)
+    a = fhe.from_numpy_u64(inputs.uniform_ciphertexts(n, qs, bmax, 5, "a"), "cuda")
+    b = fhe.from_numpy_u64(inputs.uniform_ciphertexts(n, qs, bmax, 5, "b"), "cuda")
+    res = []
+    for bs in sizes:
+        ctx = fhe.Context(n, qs, 65537, "slots")
+        km = inputs.key_material(n, qs, 5)
+        _, rlk = ctx.keygen(km["s"], km["pk_a"], km["pk_e"], km["rlk_a"], km["rlk_e"])
+        out = ctx.empty_ct(bs)
+
+        def rate():
+            ctx.mul_relin(rlk, a[:bs], b[:bs], out=out)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                ctx.mul_relin(rlk, a[:bs], b[:bs], out=out)
+            torch.cuda.synchronize()
+            return bs * reps / (time.perf_counter() - t0)
+
+        before = rate()
+        chunk, fused = ctx.autotune_mul_relin(rlk, a[:bs], b[:bs])
+        after = rate()
+        res.append({"B": bs, "default_mul_relin_per_s": before, "chunk": chunk, "fused": fused,
+                    "tuned_mul_relin_per_s": after})
+        del ctx
+    return res
 
 
 def ntt_rows_leg(fhe, inputs, torch, reps=4):
@@ -551,6 +598,41 @@ def serving_leg(fhe, inputs, torch, seconds=10.0, rate=200.0, seed=7):
     out = serving.summary(done, el)
     out.update({"offered_rate_req_per_s": rate, "seconds": seconds, "wall_s": el,
                 "peak_in_flight_gib": srv.peak_bytes / 2**30, "max_concurrent_lanes": srv.max_concurrent})
+    return out
+
+
+def calibration():
+    """M0: the calibration probe (paper_2204_12201_amd/calib/valu_calib, a
+    child process) measures the issue rates of v_add_u32 and of the 32-bit
+    integer multiplies, and the device copy rate.  From them, the butterfly
+    peak of the same 36-slot model at the measured rates (9 multiplies at the
+    slowest multiply rate, 18 other slots at the add rate)."""
+    import re
+    import subprocess
+    exe = os.path.join(ROOT, "paper_2204_12201_amd", "calib", "valu_calib")
+    if not os.path.exists(exe):
+        return None
+    try:
+        r = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    except (subprocess.TimeoutExpired, OSError):
+        return None
+    if r.returncode != 0:
+        return None
+    vals = {}
+    for line in r.stdout.splitlines():
+        m = re.match(r"(v_\w+)\s+([0-9.]+)\s+T lane-instr/s", line.strip())
+        if m:
+            vals[m.group(1)] = float(m.group(2))
+        m = re.match(r"copy kernel\s+([0-9.]+)\s+GB/s", line.strip())
+        if m:
+            vals["copy"] = float(m.group(1))
+    out = {"valu_add_tlane_per_s": vals.get("v_add_u32"), "mul_lo_tlane_per_s": vals.get("v_mul_lo_u32"),
+           "mul_hi_tlane_per_s": vals.get("v_mul_hi_u32"), "mad_u64_tlane_per_s": vals.get("v_mad_u64_u32"),
+           "copy_gb_per_s": vals.get("copy")}
+    muls = [v for v in (out["mul_lo_tlane_per_s"], out["mul_hi_tlane_per_s"], out["mad_u64_tlane_per_s"]) if v]
+    if muls and out["valu_add_tlane_per_s"]:
+        t = 9 / (min(muls) * 1e12) + 18 / (out["valu_add_tlane_per_s"] * 1e12)
+        out["bfly_peak_calibrated"] = 1.0 / t
     return out
 
 

@@ -127,6 +127,12 @@ size_t fhe_workspace_bytes(const fhe_ctx *ctx, int op, size_t count);
  * the default (about 8 GiB of workspace). */
 fhe_status fhe_set_batch_limit(fhe_ctx *ctx, size_t max_items);
 
+/* Launch-shape switch of the product pipeline: chunks of at least min_rows
+ * (item, limb) workgroups take the fused transform kernel, smaller ones the
+ * unfused kernels (square != 0: the squaring path, whose default is 0 =
+ * always fused; products default to 128).  Same words either way. */
+fhe_status fhe_set_fused_threshold(fhe_ctx *ctx, int square, size_t min_rows);
+
 /* ---------------------------------------------------------------- keys --- *
  * Key generation from explicit randomness (host arrays):
  *   s      int8[n]          secret key, entries in {-1, 0, 1}
@@ -192,6 +198,20 @@ fhe_status fhe_sub_plain_const(fhe_ctx *ctx, const uint64_t *a, uint64_t c, uint
 fhe_status fhe_mul_relin(fhe_ctx *ctx, const uint64_t *rlk_dev, const uint64_t *a,
                          const uint64_t *b, uint64_t *out, size_t count, void *ws,
                          size_t ws_bytes, hipStream_t stream);
+
+/* Autotuner of the product pipeline's launch shape for this context: times
+ * fhe_mul_relin(a, b, out) for count items (a == b: the squaring path) with
+ * chunk caps count, count/2, count/4 (never above the current cap) and with
+ * the fused transform kernel or the unfused ones, three timed runs each after
+ * a warm-up on `stream` (synchronous), and keeps the fastest: the chunk cap
+ * (as fhe_set_batch_limit) and the fused/unfused threshold of that product
+ * kind, set so that chunks of the chosen size take the chosen path.  Results
+ * of every call are the same words whatever the choice; only speed changes.
+ * *chunk and *fused (may be NULL) receive the choice.  out is overwritten.
+ * ws: FHE_OP_MUL_RELIN (FHE_OP_SQUARE_RELIN when a == b) bytes for count. */
+fhe_status fhe_autotune_mul_relin(fhe_ctx *ctx, const uint64_t *rlk_dev, const uint64_t *a,
+                                  const uint64_t *b, uint64_t *out, size_t count, void *ws,
+                                  size_t ws_bytes, hipStream_t stream, size_t *chunk, int *fused);
 
 /* Several product batches, possibly of different contexts (ring sizes,
  * primes), in one call: part i computes what fhe_mul_relin(parts[i].ctx, ...)

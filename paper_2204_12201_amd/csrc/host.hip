@@ -191,6 +191,10 @@ struct fhe_ctx {
     void *d_mrc_q = nullptr, *d_mrc_p = nullptr, *d_counters = nullptr;
     DevCtx dev{};
     size_t batch_limit = 0, default_limit = 0;
+    // fused product kernel (k_mul_tensor / k_square_tensor) from this many
+    // (item, limb) workgroups per launch on; fewer take the unfused kernels
+    // (index 0: products of two ciphertexts, 1: squarings)
+    size_t fused_min_rows[2] = {128, 0};
     bool validate = false;
     bool timing = false;
     std::vector<EvPair> pending[KK_COUNT];
@@ -298,10 +302,11 @@ fhe_status check_canonical(fhe_ctx *c, const uint64_t *a, size_t nrows, int kmod
 }
 
 // The fused product kernel runs one workgroup per (item, limb) doing seven
-// transforms in a row; with fewer such workgroups than this the unfused
-// kernels (one workgroup per transform, seven times as many) finish sooner
-// (measured at n = 16384: one item faster unfused, sixteen faster fused).
-constexpr size_t kMulTensorMinRows = 128;
+// transforms in a row; with few such workgroups the unfused kernels (one
+// workgroup per transform, seven times as many) finish sooner (measured at
+// n = 16384: one item faster unfused, sixteen faster fused): the default
+// threshold is 128 workgroups for products, and fhe_autotune_mul_relin moves
+// it (and the chunk size) per context from timings.
 
 // The product pipeline on `count` items with workspace for min(count, limit).
 
@@ -321,13 +326,14 @@ fhe_status mul_relin_impl(fhe_ctx *c, const uint64_t *rlk, const uint64_t *a, co
         uint64_t *C2 = Dt + items * 3 * K * n;
         const DevCtx &d = c->dev;
         FHE_TRY(run(c, KK_LIFT, s, [&] { return launch_lift(d, ai, bi, E, npoly, items, s); }));
-        if (square) {
-            FHE_TRY(run(c, KK_SQUARE_TENSOR, s, [&] { return launch_square_tensor(d, ai, E, Dt, items, s); }));
-        } else if (items * K >= kMulTensorMinRows) {
-            FHE_TRY(run(c, KK_MUL_TENSOR, s, [&] { return launch_mul_tensor(d, ai, bi, E, Dt, items, s); }));
+        if (items * K >= c->fused_min_rows[square ? 1 : 0]) {
+            if (square)
+                FHE_TRY(run(c, KK_SQUARE_TENSOR, s, [&] { return launch_square_tensor(d, ai, E, Dt, items, s); }));
+            else
+                FHE_TRY(run(c, KK_MUL_TENSOR, s, [&] { return launch_mul_tensor(d, ai, bi, E, Dt, items, s); }));
         } else {  // few items: one workgroup per transform keeps more of the chip busy
             FHE_TRY(run(c, KK_FWD_EXT, s, [&] { return launch_fwd_ext(d, ai, bi, E, npoly, items, s); }));
-            FHE_TRY(run(c, KK_TENSOR_INTT, s, [&] { return launch_tensor_intt(d, E, Dt, false, items, s); }));
+            FHE_TRY(run(c, KK_TENSOR_INTT, s, [&] { return launch_tensor_intt(d, E, Dt, square, items, s); }));
         }
         FHE_TRY(run(c, KK_SCALE, s, [&] { return launch_scale(d, Dt, oi, C2, items, s); }));
         FHE_TRY(run(c, KK_RELIN_FUSED, s, [&] { return launch_relin_fused(d, C2, rlk, oi, items, s); }));
@@ -752,6 +758,12 @@ size_t fhe_workspace_bytes(const fhe_ctx *c, int op, size_t count) {
     return 0;
 }
 
+fhe_status fhe_set_fused_threshold(fhe_ctx *c, int square, size_t min_rows) {
+    if (!c) return FHE_EINVAL;
+    c->fused_min_rows[square ? 1 : 0] = min_rows;
+    return FHE_OK;
+}
+
 fhe_status fhe_set_batch_limit(fhe_ctx *c, size_t max_items) {
     if (!c) return FHE_EINVAL;
     c->batch_limit = max_items ? (max_items > 65535 ? 65535 : max_items) : c->default_limit;
@@ -984,6 +996,77 @@ fhe_status fhe_mul_relin(fhe_ctx *c, const uint64_t *rlk, const uint64_t *a, con
     FHE_TRY(check_canonical(c, a, count * 2 * c->k, c->k, 0, st));
     if (!square) FHE_TRY(check_canonical(c, b, count * 2 * c->k, c->k, 0, st));
     return mul_relin_impl(c, rlk, a, b, out, count, ws, st);
+}
+
+fhe_status fhe_autotune_mul_relin(fhe_ctx *c, const uint64_t *rlk, const uint64_t *a, const uint64_t *b,
+                                  uint64_t *out, size_t count, void *ws, size_t ws_bytes, hipStream_t st,
+                                  size_t *chunk_out, int *fused_out) {
+    if (!c) return FHE_EINVAL;
+    if (count == 0) return FHE_EINVAL;
+    if (!rlk || !a || !b || !out || !ws) return FHE_EINVAL;
+    const bool square = (a == b);
+    const size_t bytes = count * ct_words(c) * 8;
+    if (overlaps(out, a, bytes) || overlaps(out, b, bytes)) return FHE_EINVAL;
+    const size_t saved_limit = c->batch_limit, saved_thr = c->fused_min_rows[square ? 1 : 0];
+    // candidates: chunk caps (whole batch, halves, quarters) x fused or not
+    size_t caps[3];
+    int ncaps = 0;
+    for (size_t div = 1; div <= 4 && ncaps < 3; div *= 2) {
+        size_t cap = (count + div - 1) / div;
+        if (cap > saved_limit) cap = saved_limit;
+        if (ncaps == 0 || caps[ncaps - 1] != cap) caps[ncaps++] = cap;
+    }
+    if (ws_bytes < fhe_workspace_bytes(c, square ? FHE_OP_SQUARE_RELIN : FHE_OP_MUL_RELIN, count)) return FHE_EWORKSPACE;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    FHE_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return FHE_EDEVICE;
+    }
+    const bool timing = c->timing;
+    c->timing = false;
+    float best = -1.0f;
+    size_t best_cap = saved_limit;
+    int best_fused = 1;
+    fhe_status st_all = FHE_OK;
+    for (int ci = 0; ci < ncaps && st_all == FHE_OK; ci++)
+        for (int fused = 0; fused < 2 && st_all == FHE_OK; fused++) {
+            c->batch_limit = caps[ci];
+            c->fused_min_rows[square ? 1 : 0] = fused ? 0 : (size_t)-1;
+            st_all = mul_relin_impl(c, rlk, a, b, out, count, ws, st);  // warm
+            if (st_all != FHE_OK) break;
+            float total = 0.0f;
+            for (int rep = 0; rep < 3 && st_all == FHE_OK; rep++) {
+                if (hipEventRecord(e0, st) != hipSuccess) st_all = FHE_EDEVICE;
+                if (st_all == FHE_OK) st_all = mul_relin_impl(c, rlk, a, b, out, count, ws, st);
+                if (st_all == FHE_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+                    st_all = FHE_EDEVICE;
+                float ms = 0.0f;
+                if (st_all == FHE_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st_all = FHE_EDEVICE;
+                total += ms;
+            }
+            if (st_all == FHE_OK && (best < 0.0f || total < best)) {
+                best = total;
+                best_cap = caps[ci];
+                best_fused = fused;
+            }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->timing = timing;
+    if (st_all != FHE_OK) {
+        c->batch_limit = saved_limit;
+        c->fused_min_rows[square ? 1 : 0] = saved_thr;
+        return st_all;
+    }
+    // keep the winner: the chunk cap, and a threshold that sends this batch's
+    // chunks to the faster product path
+    c->batch_limit = best_cap;
+    const size_t rows = best_cap * c->K;
+    c->fused_min_rows[square ? 1 : 0] = best_fused ? (saved_thr < rows ? saved_thr : rows) : rows + 1;
+    if (chunk_out) *chunk_out = best_cap;
+    if (fused_out) *fused_out = best_fused;
+    return FHE_OK;
 }
 
 static fhe_status ensure_aux(fhe_ctx *c) {

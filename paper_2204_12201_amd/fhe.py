@@ -57,6 +57,9 @@ _SIGS = [
     ("fhe_aux_primes", _U32, [_P]),
     ("fhe_workspace_bytes", _Z, [_P, _I, _Z]),
     ("fhe_set_batch_limit", _I, [_P, _Z]),
+    ("fhe_set_fused_threshold", _I, [_P, _I, _Z]),
+    ("fhe_autotune_mul_relin", _I, [_P, _P, _P, _P, _P, _Z, _P, _Z, _P, ctypes.POINTER(_Z),
+                                    ctypes.POINTER(ctypes.c_int)]),
     ("fhe_keygen", _I, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _Z, _P]),
     ("fhe_rlk_import", _I, [_P, _P, _P, _P, _Z, _P]),
     ("fhe_encode", _I, [_P, _P, _P]),
@@ -288,6 +291,22 @@ class Context:
         _check(lib().fhe_mul_relin(self._h, _dptr(rlk), _dptr(a), _dptr(b), _dptr(out), count, _dptr(ws),
                                    ws.numel(), _stream()), "fhe_mul_relin")
         return out
+
+    def autotune_mul_relin(self, rlk, a, b):
+        """Time the product pipeline on these inputs at the candidate launch
+        shapes and keep the fastest in the context; returns (chunk, fused)."""
+        count = a.shape[0]
+        op = OP_SQUARE_RELIN if a.data_ptr() == b.data_ptr() else OP_MUL_RELIN
+        ws, _ = self.workspace(op, count)
+        out = self.empty_ct(count)
+        chunk, fused = _Z(0), ctypes.c_int(0)
+        _check(lib().fhe_autotune_mul_relin(self._h, _dptr(rlk), _dptr(a), _dptr(b), _dptr(out), count, _dptr(ws),
+                                            ws.numel(), _stream(), ctypes.byref(chunk), ctypes.byref(fused)),
+               "fhe_autotune_mul_relin")
+        return chunk.value, bool(fused.value)
+
+    def set_fused_threshold(self, square: bool, min_rows: int):
+        _check(lib().fhe_set_fused_threshold(self._h, 1 if square else 0, min_rows), "fhe_set_fused_threshold")
 
     def square_chain(self, rlk, x, depth: int, graph: bool = False):
         """x <- x^(2^depth) in place (device [count][2][k][n]); graph: record

@@ -685,3 +685,30 @@ def test_signed_casts_words_and_round_trip(dev):
     back = down(ctx.int_to_mod(Y))
     for j, x in enumerate(xs):
         assert int(bfv.decrypt(P, km["s"], back[j])[0]) == x
+
+
+def test_unfused_squaring_path_and_autotune(dev):
+    """The squaring through the unfused kernels (forced threshold) and the
+    product pipeline after the autotuner picked its launch shape: every word
+    against the oracle either way."""
+    n, qs = 1024, bfv.ntt_primes(1024, 36, 3)
+    P, km, pk, rlk, ctx, rlk_d = setup(n, qs, 65537, "slots", 18)
+    count = 24
+    a = inputs.uniform_ciphertexts(n, qs, count, 18, "a")
+    b = inputs.uniform_ciphertexts(n, qs, count, 18, "b")
+    say("unfused squaring / autotune n=1024")
+    ctx.set_fused_threshold(True, 1 << 40)
+    da = up(a)
+    sq = down(ctx.mul_relin(rlk_d, da, da))
+    ctx.set_fused_threshold(True, 0)
+    for j in range(0, count, 5):
+        assert (sq[j] == bfv.mul_relin(P, a[j], a[j], rlk)).all(), f"square {j}"
+    db = up(b)
+    chunk, fused = ctx.autotune_mul_relin(rlk_d, da, db)
+    assert chunk in (count, count // 2, count // 4)
+    out = down(ctx.mul_relin(rlk_d, da, db))
+    for j in range(0, count, 5):
+        assert (out[j] == bfv.mul_relin(P, a[j], b[j], rlk)).all(), f"product {j}"
+    chunk_s, fused_s = ctx.autotune_mul_relin(rlk_d, da, da)
+    sq2 = down(ctx.mul_relin(rlk_d, da, da))
+    assert (sq2 == sq).all()
