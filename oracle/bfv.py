@@ -27,6 +27,9 @@ paper's introduction):
 * Weighted sums (the case study's modular stage, Section 4.4): out[m] =
   sum_j w_mj ct_j mod q.  Gates (Section 3.1's expressions over {0, 1}), and
   from them a ripple comparison and a one-hot argmax.
+* Bridge from the powers of x (an evaluation of the same bits with fewer
+  products): x^1..x^(t-1) by a least-depth product tree, then each bit as a
+  weighted sum of the powers with the binomial expansion's weights.
 * Signed casts: SecureInt -> SecureMod (Section 3.2.2) as the two's complement
   value, linear; SecureMod -> SecureInt (Section 3.2.4, its equation) as the
   bridge's bits, a constant addition of 2^s - t by a ripple-carry adder of the
@@ -551,6 +554,47 @@ def argmax(P: Params, rlk, scores, counter: Counter | None = None):
             out[a] = na if out[a] is None else mul_relin(P, out[a], na, rlk, counter)
             out[b] = l if out[b] is None else mul_relin(P, out[b], l, rlk, counter)
     return out
+
+
+def power_basis(P: Params, ct_x, rlk, e: int, counter: Counter | None = None) -> dict:
+    """x^k for k = 1..e, each by one product of lower powers at the least
+    depth: x^k = x^h x^(k-h) with h the largest power of two below k (a
+    square when k is a power of two); depth ceil(log2 k)."""
+    pw = {1: np.array(ct_x, copy=True)}
+    for k in range(2, e + 1):
+        h = 1 << ((k - 1).bit_length() - 1)
+        pw[k] = mul_relin(P, pw[h], pw[k - h], rlk, counter)
+    return pw
+
+
+def bridge_weights(t: int, nbits: int) -> list:
+    """The bridge's bits as polynomials in x (mod t): bit_j = sum over c in
+    [1, t) with bit j of c set of 1 - (x - c)^(t-1), and (x - c)^(t-1) =
+    sum_k C(t-1, k) x^k (-c)^(t-1-k).  Returns W[j][k] (k = 0..t-1, x^0 = 1),
+    centred representatives in (-t/2, t/2]."""
+    W = []
+    for j in range(nbits):
+        row = [0] * t
+        for c in range(1, t):
+            if (c >> j) & 1:
+                row[0] += 1
+                for k in range(t):
+                    row[k] -= math.comb(t - 1, k) * (-c) ** (t - 1 - k)
+        row = [w % t for w in row]
+        W.append([w - t if w > t // 2 else w for w in row])
+    return W
+
+
+def bridge_to_bits_powers(P: Params, ct_x, rlk, nbits: int, counter: Counter | None = None) -> np.ndarray:
+    """The bridge's bits from the powers of x instead of per-test squaring
+    chains: the t equality tests share x^1..x^(t-1) (t - 2 products), and
+    each bit is one integer-weighted sum of [1, x, ..., x^(t-1)] with the
+    weights of bridge_weights (1 = the noiseless encryption (Delta, 0))."""
+    pw = power_basis(P, ct_x, rlk, P.t - 1, counter)
+    one = np.zeros((2, P.k, P.n), dtype=np.uint64)
+    for i, qi in enumerate(P.qs):
+        one[0, i, 0] = np.uint64(P.delta % qi)
+    return weighted_sum(P, [one] + [pw[k] for k in range(1, P.t)], bridge_weights(P.t, nbits))
 
 
 def int_to_mod(P: Params, bits) -> np.ndarray:

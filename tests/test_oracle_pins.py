@@ -640,3 +640,51 @@ def test_mod_to_int_round_trip_p17():
             d = bfv.decrypt(P, km["s"], Y[i])
             assert int(d[0]) == ((v % 32) >> i) & 1 and (d[1:] == 0).all(), (x, i)
         assert int(bfv.decrypt(P, km["s"], bfv.int_to_mod(P, list(Y)))[0]) == x
+
+
+# ------------------------------------------------ bridge from the powers ----
+
+def test_bridge_weights_reproduce_the_bits():
+    """Closed form: sum_k W[j][k] x^k = bit j of x (mod t) for every x in
+    [0, t) and t in {17, 257}; centred weights."""
+    for t, nb in ((17, 5), (257, 9)):
+        W = bfv.bridge_weights(t, nb)
+        for x in range(t):
+            for j in range(nb):
+                assert sum(w * pow(x, k, t) for k, w in enumerate(W[j])) % t == (x >> j) & 1, (t, x, j)
+        assert all(abs(w) <= t // 2 for row in W for w in row)
+
+
+def test_bridge_powers_decrypts_to_bits_with_15_products():
+    """p = 17 at n = 32: the power-basis bridge's bits decrypt to the plain
+    bits of x with t - 2 = 15 products (depth 4), against 68 for the per-test
+    chains."""
+    n = 32
+    P = bfv.Params(n, bfv.ntt_primes(n, 55, 4), 17, "coeff")
+    km, pk, rlk = keys_small(P, seed=38)
+    xs = [0, 16, 5, 11]
+    r = inputs.encryption_randomness(n, len(xs), 38)
+    for j, x in enumerate(xs):
+        pt = np.zeros(n, dtype=np.uint64)
+        pt[0] = x
+        ct = bfv.encrypt(P, pk, pt, r["u"][j], r["e"][j])
+        cnt = bfv.Counter()
+        bits = bfv.bridge_to_bits_powers(P, ct, rlk, 5, cnt)
+        assert cnt.mul == 15
+        for b in range(5):
+            d = bfv.decrypt(P, km["s"], bits[b])
+            assert int(d[0]) == (x >> b) & 1 and (d[1:] == 0).all(), (x, b)
+
+
+def test_power_basis_depth_and_values():
+    """x^k decrypts to x^k mod t for k = 1..16 (slots, t = 257), each power
+    one product."""
+    P, km, pk, rlk = _slots_setup(39, k=6)
+    rng = random.Random(4)
+    xs = [rng.randrange(P.t) for _ in range(P.n)]
+    ct = _enc_slots(P, pk, [xs], 39)[0]
+    cnt = bfv.Counter()
+    pw = bfv.power_basis(P, ct, rlk, 16, cnt)
+    assert cnt.mul == 15
+    for k in (2, 3, 7, 8, 13, 16):
+        assert _dec_slots(P, km, pw[k]) == [pow(x, k, P.t) for x in xs], k
