@@ -222,6 +222,23 @@ def main():
         "roofline": roofline,
     }
 
+    # the same bits from the powers of x (another circuit: t - 2 products per
+    # input), on the same inputs and key; reported beside the headline
+    ctx.bridge_to_bits_powers(rlk, x_ct, nbits)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        pbits = ctx.bridge_to_bits_powers(rlk, x_ct, nbits)
+    torch.cuda.synchronize()
+    p_el = time.perf_counter() - t0
+    pdec = ctx.decrypt(km["s"], pbits.reshape(-1, 2, len(qs), n)).reshape(count, nbits, n)[:, :, 0]
+    want = (xs[:, None].astype(np.int64) >> np.arange(nbits)) & 1
+    out_powers = {"conversions_per_s": count * args.steps / p_el, "ms_per_step": p_el * 1e3 / args.steps,
+                  "mul_relin_per_conversion": t - 2, "decrypts_to_bits": bool((pdec.astype(np.int64) == want).all())}
+    out["bridge_power_basis"] = out_powers
+    print("[bench] power-basis bridge done", file=sys.stderr, flush=True)
+    del pbits
+
     if not args.no_plain:
         out["plain_vs_batched"] = plain_vs_batched(ctx_factory=lambda: fhe.Context(
             n, qs, 65537, "slots"), fhe=fhe, inputs=inputs, torch=torch)

@@ -79,7 +79,8 @@ enum {
     FHE_OP_GATE = 9,         /* count = ciphertexts per operand */
     FHE_OP_COMPARE = 10,     /* count = pairs of bit vectors */
     FHE_OP_ARGMAX = 11,      /* count = score sets */
-    FHE_OP_MOD_TO_INT = 12   /* count = inputs */
+    FHE_OP_MOD_TO_INT = 12,  /* count = inputs */
+    FHE_OP_BRIDGE_POWERS = 13 /* count = inputs */
 };
 
 /* gates of fhe_gate */
@@ -336,6 +337,22 @@ fhe_status fhe_int_to_mod(fhe_ctx *ctx, const uint64_t *bits, uint32_t nbits, ui
  * fhe_bridge_to_bits.  ws: FHE_OP_MOD_TO_INT bytes for count. */
 fhe_status fhe_mod_to_int(fhe_ctx *ctx, const uint64_t *rlk_dev, const uint64_t *x, uint32_t nbits,
                           uint64_t *bits, size_t count, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* The same bits as fhe_bridge_to_bits, evaluated from the powers of x instead
+ * of one squaring chain per test: the t tests (x - c)^(t-1) share
+ * x^1..x^(t-1), computed once per input by a least-depth product tree
+ * (x^(h+r) = x^h x^r, h the largest power of two below h + r; t - 2
+ * products, depth ceil(log2(t-1))), and each bit is one integer-weighted sum
+ * of [1, x, ..., x^(t-1)] with the weights of the binomial expansion of
+ * sum over c in [1, t) with bit b of c set of 1 - (x - c)^(t-1) (centred mod
+ * t; 1 = the noiseless encryption (Delta, 0)).  Decrypts to the same bits
+ * with 15 instead of 68 products at t = 17; the words differ from
+ * fhe_bridge_to_bits (another circuit).  Requires coefficient encoding, t
+ * prime, 3 <= t <= 257, 2^nbits >= t.  x device [count][2][k][n]; bits device
+ * [count][nbits][2][k][n].  ws: FHE_OP_BRIDGE_POWERS bytes for count. */
+fhe_status fhe_bridge_to_bits_powers(fhe_ctx *ctx, const uint64_t *rlk_dev, const uint64_t *x, uint32_t nbits,
+                                     uint64_t *bits, size_t count, void *ws, size_t ws_bytes,
+                                     hipStream_t stream);
 
 /* The paper's SecureUint -> SecureMod cast (Section 3.2.1, Horner):
  * out[j] = sum_b 2^b bits[j][b], evaluated as r = bit_{nbits-1}; r = r + r + bit_b.

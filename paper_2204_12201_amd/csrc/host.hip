@@ -279,6 +279,15 @@ size_t bridge_group(const fhe_ctx *c) {
     return g ? g : 1;
 }
 
+// Inputs per group of the power-basis bridge: its largest product level has
+// hmax products per input (hmax the largest power of two below t - 1).
+size_t powers_group(const fhe_ctx *c) {
+    size_t hmax = 1;
+    while (hmax * 2 < c->t - 1) hmax *= 2;
+    size_t g = c->batch_limit / hmax;
+    return g ? g : 1;
+}
+
 bool overlaps(const void *a, const void *b, size_t bytes) {
     const char *x = (const char *)a, *y = (const char *)b;
     return x < y + bytes && y < x + bytes;
@@ -749,6 +758,17 @@ size_t fhe_workspace_bytes(const fhe_ctx *c, int op, size_t count) {
             return 6 * count * ct_words(c) * 8 + fhe_workspace_bytes(c, FHE_OP_MUL_RELIN, count);
         case FHE_OP_ARGMAX:
             return 2 * count * ct_words(c) * 8 + fhe_workspace_bytes(c, FHE_OP_COMPARE, count);
+        case FHE_OP_BRIDGE_POWERS: {
+            if (c->t < 3 || c->t > 257) return 0;
+            const size_t e = c->t - 1;
+            size_t hmax = 1;
+            while (hmax * 2 < e) hmax *= 2;
+            size_t g = powers_group(c);
+            if (count < g) g = count;
+            const size_t wbytes = ((20 * weighted_sum_row_stride(c->t) * 4 + 255) / 256) * 256;
+            return (e + hmax) * g * ct_words(c) * 8 + wbytes +
+                   fhe_workspace_bytes(c, FHE_OP_MUL_RELIN, hmax * g);
+        }
         case FHE_OP_MOD_TO_INT: {
             const size_t a = fhe_workspace_bytes(c, FHE_OP_BRIDGE, count);
             const size_t b = 7 * count * ct_words(c) * 8 + fhe_workspace_bytes(c, FHE_OP_MUL_RELIN, count);
@@ -1240,6 +1260,35 @@ fhe_status fhe_bits_to_mod(fhe_ctx *c, const uint64_t *bits, uint32_t nbits, uin
 
 // ------------------------------------------------- modular linear stage ----
 
+// Weight rows [nout][nin] padded to the kernel's row stride, staged in pinned
+// memory (the previous copy out of it must have finished), then copied
+// asynchronously to dst on st.
+static fhe_status stage_weights(fhe_ctx *c, const int32_t *w, size_t nout, size_t nin, int32_t *dst,
+                                hipStream_t st) {
+    const size_t stride = weighted_sum_row_stride(nin);
+    const size_t words = nout * stride;
+    if (!c->wpin_ev && hipEventCreateWithFlags(&c->wpin_ev, hipEventDisableTiming) != hipSuccess) {
+        c->wpin_ev = nullptr;
+        return FHE_EDEVICE;
+    }
+    FHE_HIP(hipEventSynchronize(c->wpin_ev));
+    if (words > c->wpin_cap) {
+        if (c->wpin) (void)hipHostFree(c->wpin);
+        c->wpin = nullptr;
+        c->wpin_cap = 0;
+        if (hipHostMalloc((void **)&c->wpin, words * 4, hipHostMallocDefault) != hipSuccess) {
+            c->wpin = nullptr;
+            return FHE_ENOMEM;
+        }
+        c->wpin_cap = words;
+    }
+    std::memset(c->wpin, 0, words * 4);
+    for (size_t m = 0; m < nout; m++) std::memcpy(c->wpin + m * stride, w + m * nin, nin * 4);
+    FHE_HIP(hipMemcpyAsync(dst, c->wpin, words * 4, hipMemcpyHostToDevice, st));
+    FHE_HIP(hipEventRecord(c->wpin_ev, st));
+    return FHE_OK;
+}
+
 fhe_status fhe_weighted_sum(fhe_ctx *c, const uint64_t *in, size_t nin, const int32_t *w, size_t nout,
                             uint64_t *out, void *ws, size_t ws_bytes, hipStream_t st) {
     if (!c) return FHE_EINVAL;
@@ -1261,30 +1310,10 @@ fhe_status fhe_weighted_sum(fhe_ctx *c, const uint64_t *in, size_t nin, const in
         }
         if (abs_sum >= (1ull << 30)) return FHE_EINVAL;
     }
+    (void)stride;
     FHE_TRY(check_canonical(c, in, nin * 2 * c->k, c->k, 0, st));
-    // padded rows staged in pinned memory (the previous copy out of it must
-    // have finished), then one asynchronous copy into the workspace
-    const size_t words = nout * stride;
-    if (!c->wpin_ev && hipEventCreateWithFlags(&c->wpin_ev, hipEventDisableTiming) != hipSuccess) {
-        c->wpin_ev = nullptr;
-        return FHE_EDEVICE;
-    }
-    FHE_HIP(hipEventSynchronize(c->wpin_ev));
-    if (words > c->wpin_cap) {
-        if (c->wpin) hipHostFree(c->wpin);
-        c->wpin = nullptr;
-        c->wpin_cap = 0;
-        if (hipHostMalloc((void **)&c->wpin, words * 4, hipHostMallocDefault) != hipSuccess) {
-            c->wpin = nullptr;
-            return FHE_ENOMEM;
-        }
-        c->wpin_cap = words;
-    }
-    std::memset(c->wpin, 0, words * 4);
-    for (size_t m = 0; m < nout; m++) std::memcpy(c->wpin + m * stride, w + m * nin, nin * 4);
     int32_t *wd = (int32_t *)ws;
-    FHE_HIP(hipMemcpyAsync(wd, c->wpin, words * 4, hipMemcpyHostToDevice, st));
-    FHE_HIP(hipEventRecord(c->wpin_ev, st));
+    FHE_TRY(stage_weights(c, w, nout, nin, wd, st));
     return run(c, KK_ELEMENTWISE, st, [&] { return launch_weighted_sum(c->dev, in, nin, wd, nout, out, st); });
 }
 
@@ -1423,6 +1452,79 @@ fhe_status fhe_argmax(fhe_ctx *c, const uint64_t *rlk, const uint64_t *scores, u
             else FHE_TRY(mul_relin_impl(c, rlk, ob, Lt, ob, count, mws, st));
             first[a] = first[b] = false;
         }
+    return FHE_OK;
+}
+
+// ------------------------------------------------ bridge from the powers ----
+// The bits of the bridge as weighted sums of x^0..x^(t-1): bit_j = sum over
+// c in [1, t) with bit j of c set of 1 - (x - c)^(t-1), expanded binomially
+// (centred weights modulo t); x^0 is the noiseless encryption of 1.
+
+static void bridge_weights(uint64_t t, uint32_t nbits, std::vector<int32_t> &W) {
+    W.assign((size_t)nbits * t, 0);
+    std::vector<uint64_t> binom(t, 1);  // C(t-1, k) mod t
+    for (uint64_t k = 1; k < t; k++) binom[k] = (uint64_t)((u128)binom[k - 1] * ((t - k) % t) % t * hinv(k % t, t) % t);
+    for (uint32_t j = 0; j < nbits; j++) {
+        std::vector<uint64_t> row(t, 0);
+        for (uint64_t cc = 1; cc < t; cc++) {
+            if (!((cc >> j) & 1)) continue;
+            row[0] = (row[0] + 1) % t;
+            const uint64_t mc = t - cc;  // -c mod t
+            for (uint64_t k = 0; k < t; k++) {
+                const uint64_t term = (uint64_t)((u128)binom[k] * hpow(mc, t - 1 - k, t) % t);
+                row[k] = (row[k] + t - term) % t;
+            }
+        }
+        for (uint64_t k = 0; k < t; k++)
+            W[(size_t)j * t + k] = (int32_t)(row[k] > t / 2 ? (int64_t)row[k] - (int64_t)t : (int64_t)row[k]);
+    }
+}
+
+fhe_status fhe_bridge_to_bits_powers(fhe_ctx *c, const uint64_t *rlk, const uint64_t *x, uint32_t nbits,
+                                     uint64_t *bits, size_t count, void *ws, size_t ws_bytes, hipStream_t st) {
+    if (!c) return FHE_EINVAL;
+    if (c->encoding != FHE_ENC_COEFF || !is_prime_u64(c->t) || c->t < 3 || c->t > 257) return FHE_EUNSUPPORTED;
+    if (nbits == 0 || nbits > 20 || (1ull << nbits) < c->t) return FHE_EINVAL;
+    if (count == 0) return FHE_OK;
+    if (!rlk || !x || !bits || !ws) return FHE_EINVAL;
+    if (ws_bytes < fhe_workspace_bytes(c, FHE_OP_BRIDGE_POWERS, count)) return FHE_EWORKSPACE;
+    const size_t ctw = ct_words(c), ctb = ctw * 8;
+    if (overlaps2(bits, count * nbits * ctb, x, count * ctb)) return FHE_EINVAL;
+    FHE_TRY(check_canonical(c, x, count * 2 * c->k, c->k, 0, st));
+    const size_t e = c->t - 1;
+    size_t hmax = 1;
+    while (hmax * 2 < e) hmax *= 2;
+    const size_t G = powers_group(c);
+    const size_t gmax = count < G ? count : G;
+    // workspace: powers [e][gmax], the replicated left operand [hmax][gmax],
+    // the weights, then the product workspace
+    uint64_t *Pw = (uint64_t *)ws;
+    uint64_t *A = Pw + e * gmax * ctw;
+    int32_t *wd = (int32_t *)(A + hmax * gmax * ctw);
+    void *mws = (uint8_t *)wd + ((20 * weighted_sum_row_stride(c->t) * 4 + 255) / 256) * 256;
+    std::vector<int32_t> W;
+    bridge_weights(c->t, nbits, W);
+    FHE_TRY(stage_weights(c, W.data(), nbits, c->t, wd, st));
+    for (size_t g0 = 0; g0 < count; g0 += G) {
+        const size_t gc = count - g0 < G ? count - g0 : G;
+        const size_t bw = gc * ctw;  // one power of every input of the group
+        FHE_HIP(hipMemcpyAsync(Pw, x + g0 * ctw, bw * 8, hipMemcpyDeviceToDevice, st));
+        // level of x^(h+1) .. x^(2h): x^(h+r) = x^h x^r, r = 1..min(h, e - h)
+        for (size_t h = 1; h < e; h *= 2) {
+            const size_t nk = (2 * h <= e ? 2 * h : e) - h;
+            const uint64_t *a = Pw + (h - 1) * bw;
+            if (h > 1) {
+                for (size_t r = 0; r < nk; r++)
+                    FHE_HIP(hipMemcpyAsync(A + r * bw, a, bw * 8, hipMemcpyDeviceToDevice, st));
+                a = A;
+            }
+            FHE_TRY(mul_relin_impl(c, rlk, a, Pw, Pw + h * bw, nk * gc, mws, st));
+        }
+        FHE_TRY(run(c, KK_ELEMENTWISE, st, [&] {
+            return launch_weighted_sum_items(c->dev, Pw, bw, ctw, c->t, 1, wd, nbits, bits + g0 * nbits * ctw, ctw,
+                                             nbits * ctw, gc, st);
+        }));
+    }
     return FHE_OK;
 }
 

@@ -117,3 +117,10 @@ size_t weighted_sum_row_stride(size_t nin);
 // out[m] = sum_j w[m][j] in[j] for the padded device matrix w [nout][stride].
 hipError_t launch_weighted_sum(const DevCtx &c, const uint64_t *in, size_t nin, const int32_t *w, size_t nout,
                                uint64_t *out, hipStream_t s);
+// The same over `items` independent sets with one weight matrix: set z reads
+// input j at in + z in_is + j in_js and writes output m at out + z out_is +
+// m out_ms; one_first: input 0 is the noiseless encryption of 1 (not read)
+// and input j >= 1 sits at index j - 1.
+hipError_t launch_weighted_sum_items(const DevCtx &c, const uint64_t *in, size_t in_js, size_t in_is, size_t nin,
+                                     int one_first, const int32_t *w, size_t nout, uint64_t *out, size_t out_ms,
+                                     size_t out_is, size_t items, hipStream_t s);

@@ -41,23 +41,32 @@ __device__ __forceinline__ void finish(int64_t sl, int64_t sh, int32_t ws, const
     *o = r;
 }
 
-// grid (ceil(W / 256), ceil(nout / WS_M)); W = 2 k n words per ciphertext.
-// in: nj <= WS_J ciphertexts (stride W); w: rows of stride wstride (device,
-// zero beyond the last input of the row); out: nout ciphertexts;
-// accumulate: add into out instead of writing it.
-__global__ __launch_bounds__(256) void k_weighted_sum(DevCtx c, const uint64_t *__restrict__ in, int nj,
+// grid (ceil(W / 256), ceil(nout / WS_M), items); W = 2 k n words per
+// ciphertext.  Item z reads its nj <= WS_J inputs at in + z in_is + j in_js
+// (one_first: input 0 is instead the noiseless encryption of 1, (Delta, 0),
+// and input j >= 1 is at index j - 1), and writes output m at
+// out + z out_is + m out_ms.  w: rows of stride wstride (device, zero beyond
+// the last input of the row); accumulate: add into out instead of writing it.
+__global__ __launch_bounds__(256) void k_weighted_sum(DevCtx c, const uint64_t *__restrict__ in, size_t in_js,
+                                                      size_t in_is, int nj, int one_first,
                                                       const int32_t *__restrict__ w, int wstride,
-                                                      size_t nout, uint64_t *__restrict__ out, int accumulate) {
+                                                      size_t nout, uint64_t *__restrict__ out, size_t out_ms,
+                                                      size_t out_is, int accumulate) {
     const size_t W = (size_t)2 * c.k * c.n;
     const size_t p = (size_t)blockIdx.x * 256 + threadIdx.x;
     if (p >= W) return;
     const int limb = (int)((p >> c.L) % (size_t)c.k);
     const PrimeConst &P = c.pc[limb];
     const uint64_t q = P.q;
+    in += blockIdx.z * in_is;
+    out += blockIdx.z * out_is;
+    // the constant coefficient of the first polynomial carries Delta in the encryption of 1
+    const uint64_t one = p < (size_t)c.k * c.n && (p & (c.n - 1)) == 0 ? c.cc->delta_q[limb] : 0;
     int32_t xl[WS_J], xh[WS_J];
 #pragma unroll
     for (int j = 0; j < WS_J; j++) {
-        const uint64_t x = j < nj ? in[(size_t)j * W + p] : 0;
+        uint64_t x = 0;
+        if (j < nj) x = (one_first && j == 0) ? one : in[(size_t)(j - one_first) * in_js + p];
         xl[j] = (int32_t)((uint32_t)x ^ 0x80000000u);  // x_lo - 2^31
         xh[j] = (int32_t)(x >> 32);
         // opaque: keeps the products signed 32 x 32 bit (v_mad_i64_i32)
@@ -89,9 +98,9 @@ __global__ __launch_bounds__(256) void k_weighted_sum(DevCtx c, const uint64_t *
                 }
             }
         }
-        uint64_t *o = out + m * W + p;
+        uint64_t *o = out + m * out_ms + p;
         finish(sl0, sh0, ws0, P, o, accumulate);
-        if (two) finish(sl1, sh1, ws1, P, o + W, accumulate);
+        if (two) finish(sl1, sh1, ws1, P, o + out_ms, accumulate);
     }
 }
 
@@ -102,12 +111,21 @@ size_t weighted_sum_row_stride(size_t nin) { return (nin + WS_G - 1) / WS_G * WS
 hipError_t launch_weighted_sum(const DevCtx &c, const uint64_t *in, size_t nin, const int32_t *w, size_t nout,
                                uint64_t *out, hipStream_t s) {
     const size_t W = (size_t)2 * c.k * c.n;
+    return launch_weighted_sum_items(c, in, W, 0, nin, 0, w, nout, out, W, 0, 1, s);
+}
+
+hipError_t launch_weighted_sum_items(const DevCtx &c, const uint64_t *in, size_t in_js, size_t in_is, size_t nin,
+                                     int one_first, const int32_t *w, size_t nout, uint64_t *out, size_t out_ms,
+                                     size_t out_is, size_t items, hipStream_t s) {
+    const size_t W = (size_t)2 * c.k * c.n;
     const size_t wstride = weighted_sum_row_stride(nin);
-    const dim3 grid((unsigned)((W + 255) / 256), (unsigned)((nout + WS_M - 1) / WS_M));
+    const dim3 grid((unsigned)((W + 255) / 256), (unsigned)((nout + WS_M - 1) / WS_M), (unsigned)items);
     for (size_t j0 = 0; j0 < nin; j0 += WS_J) {
         const int nj = (int)(nin - j0 < (size_t)WS_J ? nin - j0 : (size_t)WS_J);
-        hipLaunchKernelGGL(k_weighted_sum, grid, dim3(256), 0, s, c, in + j0 * W, nj, w + j0, (int)wstride,
-                           nout, out, j0 > 0 ? 1 : 0);
+        const int first = j0 == 0 ? one_first : 0;
+        const uint64_t *src = in + (j0 - (j0 ? (size_t)one_first : 0)) * in_js;
+        hipLaunchKernelGGL(k_weighted_sum, grid, dim3(256), 0, s, c, src, in_js, in_is, nj, first, w + j0,
+                           (int)wstride, nout, out, out_ms, out_is, j0 > 0 ? 1 : 0);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -18,7 +18,7 @@ LIBPATH = os.path.join(HERE, "libfhe.so")
 
 ENC_SLOTS, ENC_COEFF = 0, 1
 OP_MUL_RELIN, OP_SQUARE_RELIN, OP_BRIDGE, OP_KEYGEN, OP_ENCRYPT, OP_DECRYPT, OP_RLK_IMPORT = range(1, 8)
-OP_WEIGHTED_SUM, OP_GATE, OP_COMPARE, OP_ARGMAX, OP_MOD_TO_INT = range(8, 13)
+OP_WEIGHTED_SUM, OP_GATE, OP_COMPARE, OP_ARGMAX, OP_MOD_TO_INT, OP_BRIDGE_POWERS = range(8, 14)
 GATES = {"AND": 0, "NAND": 1, "OR": 2, "NOR": 3, "XOR": 4, "XNOR": 5, "NOT": 6, "MUX": 7}
 
 STATUS = {0: "ok", -1: "invalid argument", -2: "parameter set rejected", -3: "device allocation failed",
@@ -82,6 +82,7 @@ _SIGS = [
     ("fhe_argmax", _I, [_P, _P, _P, _U32, _U32, _P, _Z, _P, _Z, _P]),
     ("fhe_int_to_mod", _I, [_P, _P, _U32, _P, _Z, _P]),
     ("fhe_mod_to_int", _I, [_P, _P, _P, _U32, _P, _Z, _P, _Z, _P]),
+    ("fhe_bridge_to_bits_powers", _I, [_P, _P, _P, _U32, _P, _Z, _P, _Z, _P]),
     ("fhe_ntt", _I, [_P, _I, _P, _Z, _P]),
     ("fhe_set_timing", _I, [_P, _I]),
     ("fhe_kernel_kinds", _I, []),
@@ -386,6 +387,18 @@ class Context:
         ws, _ = self.workspace(OP_ARGMAX, count)
         _check(lib().fhe_argmax(self._h, _dptr(rlk), _dptr(scores), ncls, nbits, _dptr(out), count, _dptr(ws),
                                 ws.numel(), _stream()), "fhe_argmax")
+        return out
+
+    def bridge_to_bits_powers(self, rlk, x, nbits: int, out=None):
+        """The bridge's bits from the powers of x (t - 2 products per input):
+        x device [count][2][k][n] -> [count][nbits][2][k][n]."""
+        import torch
+        count = x.shape[0]
+        if out is None:
+            out = torch.empty((count, nbits, 2, self.k, self.n), dtype=torch.int64, device=self.device)
+        ws, _ = self.workspace(OP_BRIDGE_POWERS, count)
+        _check(lib().fhe_bridge_to_bits_powers(self._h, _dptr(rlk), _dptr(x), nbits, _dptr(out), count, _dptr(ws),
+                                               ws.numel(), _stream()), "fhe_bridge_to_bits_powers")
         return out
 
     def int_to_mod(self, bits, out=None):

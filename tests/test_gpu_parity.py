@@ -712,3 +712,30 @@ def test_unfused_squaring_path_and_autotune(dev):
     chunk_s, fused_s = ctx.autotune_mul_relin(rlk_d, da, da)
     sq2 = down(ctx.mul_relin(rlk_d, da, da))
     assert (sq2 == sq).all()
+
+
+@pytest.mark.parametrize("n,k,limit", [(64, 4, 0), (256, 5, 16)])
+def test_bridge_powers_all_words(dev, n, k, limit):
+    """The power-basis bridge against the oracle word for word, bits decrypt
+    to the plain bits (x = 16, 0, 9); with a batch cap of 16 the inputs run
+    in groups of two."""
+    qs = bfv.ntt_primes(n, 55, k)
+    P, km, pk, rlk, ctx, rlk_d = setup(n, qs, 17, "coeff", 49)
+    if limit:
+        ctx.set_batch_limit(limit)
+    xs = [16, 0, 9]
+    r = inputs.encryption_randomness(n, len(xs), 49)
+    cts = []
+    for j, x in enumerate(xs):
+        pt = np.zeros(n, dtype=np.uint64)
+        pt[0] = x
+        cts.append(bfv.encrypt(P, pk, pt, r["u"][j], r["e"][j]))
+    cts = np.stack(cts)
+    say(f"bridge powers n={n} k={k} limit={limit}")
+    got = down(ctx.bridge_to_bits_powers(rlk_d, up(cts), 5))
+    for j, x in enumerate(xs):
+        want = bfv.bridge_to_bits_powers(P, cts[j], rlk, 5)
+        assert (got[j] == want).all(), j
+        for b in range(5):
+            d = bfv.decrypt(P, km["s"], got[j, b])
+            assert int(d[0]) == (x >> b) & 1 and (d[1:] == 0).all(), (x, b)
