@@ -106,7 +106,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--inputs", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-plain", action="store_true", help="skip every leg after the headline bridge")
+    ap.add_argument("--legs", default="all",
+                    help="comma-separated legs after the headline (plain, autotune, ntt, c0, mixed, chain, "
+                         "imputation, serving) or all")
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="length of the Poisson arrival window of the serving leg")
     ap.add_argument("--no-calib", action="store_true",
@@ -239,22 +242,32 @@ def main():
     print("[bench] power-basis bridge done", file=sys.stderr, flush=True)
     del pbits
 
-    if not args.no_plain:
+    legs = set(args.legs.split(",")) if args.legs != "all" else {
+        "plain", "autotune", "ntt", "c0", "mixed", "chain", "imputation", "serving"}
+    if args.no_plain:
+        legs = set()
+    if "plain" in legs:
         out["plain_vs_batched"] = plain_vs_batched(ctx_factory=lambda: fhe.Context(
             n, qs, 65537, "slots"), fhe=fhe, inputs=inputs, torch=torch)
         print("[bench] plain vs batched done", file=sys.stderr, flush=True)
 
-    if not args.no_plain:
+    if "autotune" in legs:
         out["autotune"] = autotune_leg(fhe, inputs, torch)
         print("[bench] autotune done", file=sys.stderr, flush=True)
+    if "ntt" in legs:
         out["ntt_rows"] = ntt_rows_leg(fhe, inputs, torch)
+    if "c0" in legs:
         out["c0_n4096"] = c0_leg(fhe, inputs, torch)
         print("[bench] transform rows and n=4096 products done", file=sys.stderr, flush=True)
+    if "mixed" in legs:
         out["mixed_sizes"] = mixed_leg(fhe, inputs, torch)
+    if "chain" in legs:
         out["square_chain_n16384"] = chain_leg(fhe, inputs, torch)
         print("[bench] mixed sizes and squaring chains done", file=sys.stderr, flush=True)
+    if "imputation" in legs:
         out["imputation"] = imputation_leg(fhe, inputs, torch)
         print("[bench] imputation-shaped stages done", file=sys.stderr, flush=True)
+    if "serving" in legs:
         out["serving"] = serving_leg(fhe, inputs, torch, seconds=args.serve_seconds)
         print("[bench] serving loop done", file=sys.stderr, flush=True)
 
