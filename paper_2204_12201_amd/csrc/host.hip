@@ -350,24 +350,21 @@ fhe_status mul_relin_impl(fhe_ctx *c, const uint64_t *rlk, const uint64_t *a, co
     return FHE_OK;
 }
 
-// Products of `count` items whose left operand is input (item mod na) of the
-// extended, transformed Ahat [na][2][K][n] (k_lift + k_fwd_ext), right operand
-// b [count][2][k][n]; chunks of the batch cap, workspace as for products.
-fhe_status mul_relin_pre_impl(fhe_ctx *c, const uint64_t *rlk, const uint64_t *Ahat, size_t na, const uint64_t *b,
-                              uint64_t *out, size_t count, void *ws, hipStream_t s) {
-    const size_t n = c->n, K = c->K, k = c->k, ctw = ct_words(c);
+// Products of `count` items from transformed operands (k_lift + k_fwd_ext
+// layout [.][2][K][n]): item z multiplies input z mod na of Ahat by entry z of
+// Bhat; chunks of the batch cap, workspace as for products.
+fhe_status mul_relin_pre2_impl(fhe_ctx *c, const uint64_t *rlk, const uint64_t *Ahat, size_t na,
+                               const uint64_t *Bhat, uint64_t *out, size_t count, void *ws, hipStream_t s) {
+    const size_t n = c->n, K = c->K, ctw = ct_words(c);
     const size_t chunk = c->batch_limit;
     const DevCtx &d = c->dev;
     for (size_t off = 0; off < count; off += chunk) {
         const size_t items = count - off < chunk ? count - off : chunk;
-        const uint64_t *bi = b + off * ctw;
         uint64_t *oi = out + off * ctw;
-        uint64_t *Eb = (uint64_t *)ws;
-        uint64_t *Dt = Eb + items * 2 * K * n;
+        uint64_t *Dt = (uint64_t *)ws;
         uint64_t *C2 = Dt + items * 3 * K * n;
-        FHE_TRY(run(c, KK_LIFT, s, [&] { return launch_lift(d, bi, bi, Eb, 2, items, s); }));
         FHE_TRY(run(c, KK_MUL_TENSOR, s,
-                    [&] { return launch_mul_tensor_pre(d, Ahat, (int)na, off, bi, Eb, Dt, items, s); }));
+                    [&] { return launch_mul_tensor_pre2(d, Ahat, (int)na, off, Bhat, Dt, items, s); }));
         FHE_TRY(run(c, KK_SCALE, s, [&] { return launch_scale(d, Dt, oi, C2, items, s); }));
         FHE_TRY(run(c, KK_RELIN_FUSED, s, [&] { return launch_relin_fused(d, C2, rlk, oi, items, s); }));
     }
@@ -790,9 +787,8 @@ size_t fhe_workspace_bytes(const fhe_ctx *c, int op, size_t count) {
             size_t g = powers_group(c);
             if (count < g) g = count;
             const size_t wbytes = ((20 * weighted_sum_row_stride(c->t) * 4 + 255) / 256) * 256;
-            const size_t aw = hmax * ct_words(c) > 2 * (size_t)c->K * c->n ? hmax * ct_words(c)
-                                                                               : 2 * (size_t)c->K * c->n;
-            return (e * ct_words(c) + aw) * g * 8 + wbytes + fhe_workspace_bytes(c, FHE_OP_MUL_RELIN, hmax * g);
+            return (e * ct_words(c) + hmax * 2 * (size_t)c->K * c->n) * g * 8 + wbytes +
+                   fhe_workspace_bytes(c, FHE_OP_MUL_RELIN, hmax * g);
         }
         case FHE_OP_MOD_TO_INT: {
             const size_t a = fhe_workspace_bytes(c, FHE_OP_BRIDGE, count);
@@ -1521,34 +1517,38 @@ fhe_status fhe_bridge_to_bits_powers(fhe_ctx *c, const uint64_t *rlk, const uint
     while (hmax * 2 < e) hmax *= 2;
     const size_t G = powers_group(c);
     const size_t gmax = count < G ? count : G;
-    // workspace: powers [e][gmax], the shared left operand's transform
-    // [gmax][2][K][n] (within hmax ct-sized slots per input), the weights,
-    // then the product workspace
+    // workspace: powers [e][gmax] (coefficient form), the transforms of the
+    // extended powers x^1..x^hmax [hmax][gmax][2][K][n] (the operands of every
+    // product), the weights, then the product workspace
+    const size_t tw_words = 2 * (size_t)c->K * c->n;
     uint64_t *Pw = (uint64_t *)ws;
-    uint64_t *A = Pw + e * gmax * ctw;
-    const size_t aw = hmax * ctw > 2 * (size_t)c->K * c->n ? hmax * ctw : 2 * (size_t)c->K * c->n;
-    int32_t *wd = (int32_t *)(A + aw * gmax);
+    uint64_t *T = Pw + e * gmax * ctw;
+    int32_t *wd = (int32_t *)(T + hmax * gmax * tw_words);
     void *mws = (uint8_t *)wd + ((20 * weighted_sum_row_stride(c->t) * 4 + 255) / 256) * 256;
     std::vector<int32_t> W;
     bridge_weights(c->t, nbits, W);
     FHE_TRY(stage_weights(c, W.data(), nbits, c->t, wd, st));
+    const DevCtx &d = c->dev;
     for (size_t g0 = 0; g0 < count; g0 += G) {
         const size_t gc = count - g0 < G ? count - g0 : G;
-        const size_t bw = gc * ctw;  // one power of every input of the group
+        const size_t bw = gc * ctw;      // one power of every input of the group
+        const size_t tb = gc * tw_words; // its transform
         FHE_HIP(hipMemcpyAsync(Pw, x + g0 * ctw, bw * 8, hipMemcpyDeviceToDevice, st));
-        // level of x^(h+1) .. x^(2h): x^(h+r) = x^h x^r, r = 1..min(h, e - h);
-        // x^h is lifted and transformed once per input (into A) and shared by
-        // the level's products
+        FHE_TRY(run(c, KK_LIFT, st, [&] { return launch_lift(d, Pw, Pw, T, 2, gc, st); }));
+        FHE_TRY(run(c, KK_FWD_EXT, st, [&] { return launch_fwd_ext(d, Pw, Pw, T, 2, gc, st); }));
+        // level of x^(h+1) .. x^(2h): x^(h+r) = x^h x^r, r = 1..min(h, e - h),
+        // from the cached transforms; the new powers up to hmax are then
+        // lifted and transformed once for the later levels
         for (size_t h = 1; h < e; h *= 2) {
             const size_t nk = (2 * h <= e ? 2 * h : e) - h;
-            const uint64_t *xh = Pw + (h - 1) * bw;
-            if (h == 1) {
-                FHE_TRY(mul_relin_impl(c, rlk, xh, xh, Pw + bw, gc, mws, st));
-                continue;
+            FHE_TRY(mul_relin_pre2_impl(c, rlk, T + (h - 1) * tb, gc, T, Pw + h * bw, nk * gc, mws, st));
+            const size_t keep = h + nk <= hmax ? nk : (h < hmax ? hmax - h : 0);
+            if (keep) {
+                const uint64_t *np = Pw + h * bw;
+                uint64_t *nt = T + h * tb;
+                FHE_TRY(run(c, KK_LIFT, st, [&] { return launch_lift(d, np, np, nt, 2, keep * gc, st); }));
+                FHE_TRY(run(c, KK_FWD_EXT, st, [&] { return launch_fwd_ext(d, np, np, nt, 2, keep * gc, st); }));
             }
-            FHE_TRY(run(c, KK_LIFT, st, [&] { return launch_lift(c->dev, xh, xh, A, 2, gc, st); }));
-            FHE_TRY(run(c, KK_FWD_EXT, st, [&] { return launch_fwd_ext(c->dev, xh, xh, A, 2, gc, st); }));
-            FHE_TRY(mul_relin_pre_impl(c, rlk, A, gc, Pw, Pw + h * bw, nk * gc, mws, st));
         }
         FHE_TRY(run(c, KK_ELEMENTWISE, st, [&] {
             return launch_weighted_sum_items(c->dev, Pw, bw, ctw, c->t, 1, wd, nbits, bits + g0 * nbits * ctw, ctw,

@@ -62,11 +62,11 @@ hipError_t launch_tensor_intt(const DevCtx &c, const uint64_t *E, uint64_t *Dt, 
 // inverse-transformed tensor components, one workgroup per (limb, item).
 hipError_t launch_mul_tensor(const DevCtx &c, const uint64_t *a, const uint64_t *b, const uint64_t *E,
                              uint64_t *Dt, size_t items, hipStream_t s);
-// Products whose left operand is already transformed: item z multiplies input
-// (item0 + z) mod na of Ahat [input][2][K][n] (transform domain, canonical) by
-// b [items][2][k][n] with its lift Eb [items][2][K][n]; tensor into Dt.
-hipError_t launch_mul_tensor_pre(const DevCtx &c, const uint64_t *Ahat, int na, size_t item0, const uint64_t *b,
-                                 const uint64_t *Eb, uint64_t *Dt, size_t items, hipStream_t s);
+// Products of two transformed operands: item z multiplies input (item0 + z)
+// mod na of Ahat by entry item0 + z of Bhat (both [.][2][K][n], transform
+// domain, canonical); tensor into Dt.
+hipError_t launch_mul_tensor_pre2(const DevCtx &c, const uint64_t *Ahat, int na, size_t item0, const uint64_t *Bhat,
+                                  uint64_t *Dt, size_t items, hipStream_t s);
 hipError_t launch_square_tensor(const DevCtx &c, const uint64_t *a, const uint64_t *E, uint64_t *Dt,
                                 size_t items, hipStream_t s);
 // Key switching: out[item][l] += sum_i [C2]_{q_i} rlk_i[l] for l = 0, 1.

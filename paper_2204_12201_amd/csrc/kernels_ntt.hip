@@ -387,62 +387,42 @@ __global__ __launch_bounds__(Geo<L>::T) void k_square_tensor(DevCtx c, const uin
     for (int s = 0; s < 16; s++) d1[natural_index<L>(t6, s)] = mul_shoup(y[s], P.ninvm, P.ninvm_p, q);
 }
 
-// Product with a left operand already transformed: grid (K limbs, items).
-// Item z multiplies input z mod na of Ahat ([input][2][K][n], transform
-// domain, canonical: the extended operand as k_fwd_ext leaves it) by b_z (Q
-// limbs from b, P limbs from its lift in Eb [item][2][K][n]): transforms b1 and
-// b0 side by side, forms d0 = A0 B0, d1 = A0 B1 + A1 B0, d2 = A1 B1 (d2 parked
-// in its own output row) and inverse-transforms the three components.  Used
-// when one operand multiplies many (the power tree of the bridge), so its
-// transforms are done once.
+// Product of two operands both already transformed: grid (K limbs, items).
+// Item z multiplies input (item0 + z) mod na of Ahat by entry item0 + z of
+// Bhat (both [.][2][K][n], transform domain, canonical): d0 = A0 B0,
+// d1 = A0 B1 + A1 B0, d2 = A1 B1 (d2 parked in its own output row), three
+// inverse transforms.  Used when every operand of a batch of products is
+// reused (the power tree of the bridge caches the transforms of its powers).
 template <int L, bool LZ>
-__global__ __launch_bounds__(Geo<L>::T) void k_mul_tensor_pre(DevCtx c, const uint64_t *__restrict__ Ahat,
-                                                             int na, size_t item0,
-                                                             const uint64_t *__restrict__ b,
-                                                             const uint64_t *__restrict__ Eb,
-                                                             uint64_t *__restrict__ Dt) {
+__global__ __launch_bounds__(Geo<L>::T) void k_mul_tensor_pre2(DevCtx c, const uint64_t *__restrict__ Ahat,
+                                                              int na, size_t item0,
+                                                              const uint64_t *__restrict__ Bhat,
+                                                              uint64_t *__restrict__ Dt) {
     __shared__ uint64_t lds[Geo<L>::lds_words];
     constexpr int n = Geo<L>::N;
     const uint32_t tid = threadIdx.x;
     const int limb = blockIdx.x;
     const size_t item = blockIdx.y;
-    const int k = c.k, K = c.K;
+    const int K = c.K;
     const PrimeConst &P = c.pc[limb];
-    const uint64_t q = P.q, qi = P.qinv_neg, one_p = P.one_p;
-    const Tw *tw = c.tw + (size_t)limb * n;
+    const uint64_t q = P.q, qi = P.qinv_neg;
     const Tw *itw = c.itw + (size_t)limb * n;
-    const uint64_t *src0, *src1;
-    if (limb < k) {
-        src0 = b + ((item * 2 + 0) * k + limb) * (size_t)n;
-        src1 = b + ((item * 2 + 1) * k + limb) * (size_t)n;
-    } else {
-        src0 = Eb + ((item * 2 + 0) * K + limb) * (size_t)n;
-        src1 = Eb + ((item * 2 + 1) * K + limb) * (size_t)n;
-    }
-    const size_t ia = (item0 + item) % (size_t)na;
+    const size_t ia = (item0 + item) % (size_t)na, ib = item0 + item;
     const uint64_t *a0h = Ahat + ((ia * 2 + 0) * K + limb) * (size_t)n;
     const uint64_t *a1h = Ahat + ((ia * 2 + 1) * K + limb) * (size_t)n;
+    const uint64_t *b0h = Bhat + ((ib * 2 + 0) * K + limb) * (size_t)n;
+    const uint64_t *b1h = Bhat + ((ib * 2 + 1) * K + limb) * (size_t)n;
     uint64_t *d0 = Dt + ((item * 3 + 0) * K + limb) * (size_t)n;
     uint64_t *d1 = Dt + ((item * 3 + 1) * K + limb) * (size_t)n;
     uint64_t *d2 = Dt + ((item * 3 + 2) * K + limb) * (size_t)n;
     uint64_t x[16], y[16];
-    const uint32_t t1 = fresh(tid);
-#pragma unroll
-    for (int s = 0; s < 16; s++) x[s] = src1[natural_index<L>(t1, s)];
-#pragma unroll
-    for (int s = 0; s < 16; s++) y[s] = src0[natural_index<L>(t1, s)];
-    asm volatile("" ::: "memory");
-    ntt_fwd_regs2<L, 4, !LZ>(x, y, lds, tid, tw, q);  // B1, B0
-    // d2 = A1 B1 parked; d1 = A0 B1 + A1 B0 in x, d0 = A0 B0 in y (below 4q)
     const uint32_t t2 = fresh(tid);
 #pragma unroll
     for (int s = 0; s < 16; s++) {
         const uint32_t idx = bitrev_layout_index<L>(t2, s);
-        const uint64_t b1 = fwd_operand<LZ>(x[s], q, one_p);
-        const uint64_t b0 = fwd_operand<LZ>(y[s], q, one_p);
-        const uint64_t a0 = a0h[idx], a1 = a1h[idx];
+        const uint64_t a0 = a0h[idx], a1 = a1h[idx], b0 = b0h[idx], b1 = b1h[idx];
         d2[idx] = mont_mul_lazy(a1, b1, q, qi);
-        x[s] = mont_mul_lazy(a0, b1, q, qi) + mont_mul_lazy(a1, b0, q, qi);
+        x[s] = mont_mul_lazy(a0, b1, q, qi) + mont_mul_lazy(a1, b0, q, qi);  // below 4q
         y[s] = mont_mul_lazy(a0, b0, q, qi);
     }
     asm volatile("" ::: "memory");
@@ -652,15 +632,15 @@ struct NttL {
             hipLaunchKernelGGL((k_mul_tensor<L, false>), grid, dim3(Geo<L>::T), 0, s, c, a, b, E, Dt);
         return hipGetLastError();
     }
-    static hipError_t mul_tensor_pre(const DevCtx &c, const uint64_t *Ahat, int na, size_t item0, const uint64_t *b,
-                                     const uint64_t *Eb, uint64_t *Dt, size_t items, hipStream_t s) {
+    static hipError_t mul_tensor_pre2(const DevCtx &c, const uint64_t *Ahat, int na, size_t item0,
+                                      const uint64_t *Bhat, uint64_t *Dt, size_t items, hipStream_t s) {
         const dim3 grid(c.K, (unsigned)items);
         if (c.lazy_all)
-            hipLaunchKernelGGL((k_mul_tensor_pre<L, true>), grid, dim3(Geo<L>::T), 0, s, c, Ahat, na, item0, b, Eb,
+            hipLaunchKernelGGL((k_mul_tensor_pre2<L, true>), grid, dim3(Geo<L>::T), 0, s, c, Ahat, na, item0, Bhat,
                                Dt);
         else
-            hipLaunchKernelGGL((k_mul_tensor_pre<L, false>), grid, dim3(Geo<L>::T), 0, s, c, Ahat, na, item0, b,
-                               Eb, Dt);
+            hipLaunchKernelGGL((k_mul_tensor_pre2<L, false>), grid, dim3(Geo<L>::T), 0, s, c, Ahat, na, item0,
+                               Bhat, Dt);
         return hipGetLastError();
     }
     static hipError_t square_tensor(const DevCtx &c, const uint64_t *a, const uint64_t *E, uint64_t *Dt,
@@ -727,10 +707,10 @@ hipError_t launch_mul_tensor(const DevCtx &c, const uint64_t *a, const uint64_t 
     FHE_DISPATCH_L(c.L, mul_tensor(c, a, b, E, Dt, items, s));
 }
 
-hipError_t launch_mul_tensor_pre(const DevCtx &c, const uint64_t *Ahat, int na, size_t item0, const uint64_t *b,
-                                 const uint64_t *Eb, uint64_t *Dt, size_t items, hipStream_t s) {
+hipError_t launch_mul_tensor_pre2(const DevCtx &c, const uint64_t *Ahat, int na, size_t item0, const uint64_t *Bhat,
+                                  uint64_t *Dt, size_t items, hipStream_t s) {
     if (items == 0) return hipSuccess;
-    FHE_DISPATCH_L(c.L, mul_tensor_pre(c, Ahat, na, item0, b, Eb, Dt, items, s));
+    FHE_DISPATCH_L(c.L, mul_tensor_pre2(c, Ahat, na, item0, Bhat, Dt, items, s));
 }
 
 hipError_t launch_square_tensor(const DevCtx &c, const uint64_t *a, const uint64_t *E, uint64_t *Dt,
