@@ -60,8 +60,8 @@ HBM_PEAK = 8.0e12
 # mix as the timed run), together with the hash of the kernel sources they were
 # taken on.  Reported only while the sources match.
 TRAFFIC = {
-    "relin_fused": {"bytes": 2256254.0 * 1024 * 2.0 + 1003509.9 * 1024 * 1.0, "src": "633d865c6e2c6b83"},
-    "square_tensor": {"bytes": 1375309.0 * 1024 * 2.0 + 3211268.4 * 1024 * 1.0, "src": "633d865c6e2c6b83"},
+    "relin_fused": {"bytes": 2257631.5 * 1024 * 2.0 + 1003514.1 * 1024 * 1.0, "src": "1534e549f582f3b8"},
+    "square_tensor": {"bytes": 1375293.7 * 1024 * 2.0 + 3211267.2 * 1024 * 1.0, "src": "1534e549f582f3b8"},
 }
 KERNEL_SOURCES = ["paper_2204_12201_amd/csrc/kernels_ntt.hip", "paper_2204_12201_amd/csrc/ntt_core.hpp",
                   "paper_2204_12201_amd/csrc/modarith.hpp"]
@@ -108,7 +108,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip every leg after the headline bridge")
     ap.add_argument("--legs", default="all",
-                    help="comma-separated legs after the headline (plain, autotune, ntt, c0, mixed, chain, "
+                    help="comma-separated legs after the headline (powers, plain, autotune, ntt, c0, mixed, chain, "
                          "imputation, serving) or all")
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="length of the Poisson arrival window of the serving leg")
@@ -225,27 +225,16 @@ def main():
         "roofline": roofline,
     }
 
-    # the same bits from the powers of x (another circuit: t - 2 products per
-    # input), on the same inputs and key; reported beside the headline
-    ctx.bridge_to_bits_powers(rlk, x_ct, nbits)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for s in range(args.steps):
-        pbits = ctx.bridge_to_bits_powers(rlk, x_ct, nbits)
-    torch.cuda.synchronize()
-    p_el = time.perf_counter() - t0
-    pdec = ctx.decrypt(km["s"], pbits.reshape(-1, 2, len(qs), n)).reshape(count, nbits, n)[:, :, 0]
-    want = (xs[:, None].astype(np.int64) >> np.arange(nbits)) & 1
-    out_powers = {"conversions_per_s": count * args.steps / p_el, "ms_per_step": p_el * 1e3 / args.steps,
-                  "mul_relin_per_conversion": t - 2, "decrypts_to_bits": bool((pdec.astype(np.int64) == want).all())}
-    out["bridge_power_basis"] = out_powers
-    print("[bench] power-basis bridge done", file=sys.stderr, flush=True)
-    del pbits
-
     legs = set(args.legs.split(",")) if args.legs != "all" else {
-        "plain", "autotune", "ntt", "c0", "mixed", "chain", "imputation", "serving"}
+        "powers", "plain", "autotune", "ntt", "c0", "mixed", "chain", "imputation", "serving"}
     if args.no_plain:
         legs = set()
+
+    # the same bits from the powers of x (another circuit: t - 2 products per
+    # input), on the same inputs and key; reported beside the headline
+    if "powers" in legs:
+        out["bridge_power_basis"] = power_basis_leg(ctx, rlk, x_ct, xs, km, nbits, args.steps, torch)
+        print("[bench] power-basis bridge done", file=sys.stderr, flush=True)
     if "plain" in legs:
         out["plain_vs_batched"] = plain_vs_batched(ctx_factory=lambda: fhe.Context(
             n, qs, 65537, "slots"), fhe=fhe, inputs=inputs, torch=torch)
@@ -383,37 +372,62 @@ def autotune_leg(fhe, inputs, torch, sizes=(1, 4, 16, 256), reps=5):
     return res
 
 
+def power_basis_leg(ctx, rlk, x_ct, xs, km, nbits, steps, torch):
+    """The bits of the headline's inputs from the shared powers of x (t - 2
+    products per input, another circuit than the per-test chains), timed over
+    `steps` calls after one untimed call; the decryptions are checked."""
+    n, k, t = ctx.n, ctx.k, ctx.t
+    count = len(xs)
+    ctx.bridge_to_bits_powers(rlk, x_ct, nbits)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        pbits = ctx.bridge_to_bits_powers(rlk, x_ct, nbits)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    pdec = ctx.decrypt(km["s"], pbits.reshape(-1, 2, k, n)).reshape(count, nbits, n)[:, :, 0]
+    want = (xs[:, None].astype(np.int64) >> np.arange(nbits)) & 1
+    return {"conversions_per_s": count * steps / el, "ms_per_step": el * 1e3 / steps,
+            "mul_relin_per_conversion": t - 2, "decrypts_to_bits": bool((pdec.astype(np.int64) == want).all())}
+
+
 def ntt_rows_leg(fhe, inputs, torch, reps=4):
-    """The transform kernel alone: forward then inverse transform of 128 MiB of
-    rows per launch (uniform residues; 4096 / 2048 / 1024 rows at n = 4096 /
-    8192 / 16384) with the configured primes; rows/s, butterflies/s and
-    algorithmic HBM bytes (each row read and written once, 16 bytes per
-    coefficient) against the ALU and HBM peaks."""
+    """The transform kernel alone: forward then inverse transform of a batch of
+    rows per launch (uniform residues) with the configured primes, at two batch
+    sizes: 128 MiB (4096 / 2048 / 1024 rows at n = 4096 / 8192 / 16384), which
+    the 256 MB last-level cache largely holds between the two launches, and
+    512 MiB, which it does not (every row comes from and goes to HBM; each
+    resident workgroup runs 16 rows).  Rows/s, butterflies/s and algorithmic
+    bytes (each row read and written once, 16 bytes per coefficient) against
+    the ALU and HBM peaks."""
     res = []
-    for key in ("bfv_n4096", "bfv_n8192", "bfv_n16384"):
-        cfg = inputs.CONFIGS[key]
-        n, qs = cfg["n"], cfg["q"]
-        k = len(qs)
-        ctx = fhe.Context(n, qs, cfg["t"], cfg["encoding"])
-        count = -(-(16384 * 1024 // n) // k)
-        polys = fhe.from_numpy_u64(inputs.uniform_ciphertexts(n, qs, count, 6, "ntt")[:, 0], "cuda")
-        ctx.ntt(polys)
-        ctx.ntt(polys, inverse=True)
-        torch.cuda.synchronize()
-        ctx.reset_kernel_stats()
-        ctx.set_timing(True)
-        for _ in range(reps):
+    for mib in (128, 512):
+        for key in ("bfv_n4096", "bfv_n8192", "bfv_n16384"):
+            cfg = inputs.CONFIGS[key]
+            n, qs = cfg["n"], cfg["q"]
+            k = len(qs)
+            ctx = fhe.Context(n, qs, cfg["t"], cfg["encoding"])
+            count = -(-(mib * 131072 // n) // k)
+            polys = fhe.from_numpy_u64(inputs.uniform_ciphertexts(n, qs, count, 6, "ntt")[:, 0], "cuda")
             ctx.ntt(polys)
             ctx.ntt(polys, inverse=True)
-        torch.cuda.synchronize()
-        ctx.set_timing(False)
-        ms, launches = ctx.kernel_stats()["ntt_rows"]
-        rows = count * k * launches
-        rows_s = rows / (ms / 1e3)
-        bfly_s = rows_s * (n // 2) * int(math.log2(n))
-        bytes_s = rows_s * n * 16
-        res.append({"n": n, "rows_per_launch": count * k, "rows_per_s": rows_s, "tbutterfly_per_s": bfly_s / 1e12,
-                    "alu_frac": bfly_s / PEAK_BFLY, "gb_per_s": bytes_s / 1e9, "hbm_frac": bytes_s / HBM_PEAK})
+            torch.cuda.synchronize()
+            ctx.reset_kernel_stats()
+            ctx.set_timing(True)
+            for _ in range(reps):
+                ctx.ntt(polys)
+                ctx.ntt(polys, inverse=True)
+            torch.cuda.synchronize()
+            ctx.set_timing(False)
+            ms, launches = ctx.kernel_stats()["ntt_rows"]
+            rows = count * k * launches
+            rows_s = rows / (ms / 1e3)
+            bfly_s = rows_s * (n // 2) * int(math.log2(n))
+            bytes_s = rows_s * n * 16
+            res.append({"n": n, "batch_mib": mib, "rows_per_launch": count * k, "rows_per_s": rows_s,
+                        "tbutterfly_per_s": bfly_s / 1e12, "alu_frac": bfly_s / PEAK_BFLY,
+                        "gb_per_s": bytes_s / 1e9, "hbm_frac": bytes_s / HBM_PEAK})
+            del polys
     return res
 
 

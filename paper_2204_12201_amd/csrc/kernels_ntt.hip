@@ -80,6 +80,11 @@ __global__ __launch_bounds__(Geo<L>::T) void k_ntt_rows(DevCtx c, uint64_t *__re
         }
         const uint32_t t1 = fresh(tid);
         if constexpr (FWD) {
+            // the prefetch is waited for before this row's stores are issued
+            // (the wait counter covers stores too), so that they drain while
+            // the next row is transformed
+            if constexpr (DMA)
+                if (next < nrows) prefetch_wait();
 #pragma unroll
             for (int s = 0; s < 16; s++) {
                 uint64_t v;
@@ -98,7 +103,6 @@ __global__ __launch_bounds__(Geo<L>::T) void k_ntt_rows(DevCtx c, uint64_t *__re
         }
         if (next < nrows) {
             if constexpr (DMA) {
-                prefetch_wait();
                 const uint32_t t0 = fresh(tid);
 #pragma unroll
                 for (int s = 0; s < 16; s++) x[s] = prefetched(lds, t0, s);
