@@ -739,3 +739,55 @@ def test_bridge_powers_all_words(dev, n, k, limit):
         for b in range(5):
             d = bfv.decrypt(P, km["s"], got[j, b])
             assert int(d[0]) == (x >> b) & 1 and (d[1:] == 0).all(), (x, b)
+
+
+@pytest.mark.parametrize("t,nbits,xs", [(3, 2, [2, 0, 1]), (5, 3, [4, 3]), (7, 3, [6, 5]), (257, 9, [256, 100])])
+def test_bridge_powers_other_moduli(dev, t, nbits, xs):
+    """The power-basis bridge for other prime plaintext moduli, including the
+    degenerate trees (t = 3: one product and no cached power beyond x; t = 5
+    and 7: a last level shorter than the one before) and t = 257 (255
+    products, depth 8, nine bits): GPU words equal the oracle's, bits decrypt
+    to the bits of x."""
+    n, k = 64, 4
+    qs = bfv.ntt_primes(n, 55, k)
+    P, km, pk, rlk, ctx, rlk_d = setup(n, qs, t, "coeff", 50)
+    r = inputs.encryption_randomness(n, len(xs), 50)
+    cts = []
+    for j, x in enumerate(xs):
+        pt = np.zeros(n, dtype=np.uint64)
+        pt[0] = x
+        cts.append(bfv.encrypt(P, pk, pt, r["u"][j], r["e"][j]))
+    cts = np.stack(cts)
+    say(f"bridge powers t={t} nbits={nbits}")
+    got = down(ctx.bridge_to_bits_powers(rlk_d, up(cts), nbits))
+    for j, x in enumerate(xs):
+        want = bfv.bridge_to_bits_powers(P, cts[j], rlk, nbits)
+        assert (got[j] == want).all(), (t, j)
+        for b in range(nbits):
+            d = bfv.decrypt(P, km["s"], got[j, b])
+            assert int(d[0]) == (x >> b) & 1 and (d[1:] == 0).all(), (t, x, b)
+
+
+def test_bridge_powers_full_size_sampled(dev):
+    """The power-basis bridge at the benchmark's shape and launch
+    configuration: n = 16384, eight 55-bit primes, p = 17, 256 inputs in one
+    call.  The last input's five bit ciphertexts against the oracle word for
+    word, and every decrypted bit equal to the plain bit."""
+    cfg = inputs.CONFIGS["bridge_n16384"]
+    n, qs, t = cfg["n"], cfg["q"], cfg["t"]
+    say("bridge powers n=16384 k=8 x256")
+    P, km, pk, rlk, ctx, rlk_d = setup(n, qs, t, "coeff", 0)
+    count = 256
+    xs = inputs.bridge_values(t, count, 0)
+    pts = np.zeros((count, n), dtype=np.uint64)
+    pts[:, 0] = xs
+    r = inputs.encryption_randomness(n, count, 0)
+    ct_d = ctx.encrypt(up(pk), pts, r["u"], r["e"])
+    bits = ctx.bridge_to_bits_powers(rlk_d, ct_d, 5)
+    j = count - 1
+    last = down(bits[j])
+    want = bfv.bridge_to_bits_powers(P, down(ct_d[j]), rlk, 5)
+    assert (last == want).all()
+    dec = ctx.decrypt(km["s"], bits.reshape(-1, 2, len(qs), n)).reshape(count, 5, n)[:, :, 0]
+    plain = (xs[:, None].astype(np.int64) >> np.arange(5)) & 1
+    assert (dec.astype(np.int64) == plain).all()
