@@ -63,6 +63,17 @@ FHE_HD uint64_t mul_shoup_lazy4(uint64_t a, uint64_t w, uint64_t wp, uint64_t q)
     return a * w - h * q;
 }
 
+// The same value with nq = 2^64 - q: a w - h q = a w + h nq modulo 2^64.  A
+// caller that hides nq from the compiler gets a sum of two products, which
+// the device builds from multiply-adds without a borrow chain.
+FHE_HD uint64_t mul_shoup_lazy4n(uint64_t a, uint64_t w, uint64_t wp, uint64_t nq) {
+    const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32);
+    const uint32_t p0 = (uint32_t)wp, p1 = (uint32_t)(wp >> 32);
+    uint64_t h = (uint64_t)a1 * p1 + mulhi32(a1, p0);
+    h += mulhi32(a0, p1);
+    return a * w + h * nq;
+}
+
 FHE_HD uint64_t csub(uint64_t x, uint64_t m) { return x >= m ? x - m : x; }
 
 FHE_HD uint64_t mul_shoup(uint64_t a, uint64_t w, uint64_t wp, uint64_t q) {

@@ -83,22 +83,32 @@ __device__ __forceinline__ uint32_t elem_index(uint32_t tid, uint32_t g, uint32_
     return ((F >> lo) << (lo + r)) | (e << lo) | (F & ((1u << lo) - 1u));
 }
 
+// 2^64 - q for mul_shoup_lazy4n, opaque to the compiler (which would
+// otherwise fold the sum back into a subtraction).  q is uniform.
+__device__ __forceinline__ uint64_t neg_opaque(uint64_t q) {
+    const uint64_t n = 0 - q;
+    uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)n);
+    uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(n >> 32));
+    asm volatile("" : "+s"(lo), "+s"(hi));
+    return ((uint64_t)hi << 32) | lo;
+}
+
 // q4 = 4q.  REDUCE: X, Y in [0, 8q) -> [0, 8q); otherwise bounds grow by 4q.
 template <bool REDUCE>
 __device__ __forceinline__ void ct_bfly(uint64_t &X, uint64_t &Y, uint64_t w, uint64_t wp,
-                                        uint64_t q, uint64_t q4) {
+                                        uint64_t nq, uint64_t q4) {
     uint64_t x = REDUCE ? csub(X, q4) : X;       // [0, 4q)
-    uint64_t t = mul_shoup_lazy4(Y, w, wp, q);   // [0, 4q)
+    uint64_t t = mul_shoup_lazy4n(Y, w, wp, nq); // [0, 4q)
     X = x + t;                                   // [0, 8q)
     Y = x - t + q4;                              // (0, 8q)
 }
 
 // X, Y in [0, 4q) -> [0, 4q).
 __device__ __forceinline__ void gs_bfly(uint64_t &X, uint64_t &Y, uint64_t w, uint64_t wp,
-                                        uint64_t q, uint64_t q4) {
+                                        uint64_t nq, uint64_t q4) {
     uint64_t x = X, y = Y;
     X = csub(x + y, q4);
-    Y = mul_shoup_lazy4(x - y + q4, w, wp, q);
+    Y = mul_shoup_lazy4n(x - y + q4, w, wp, nq);
 }
 
 // Inverse butterfly with a two-class bound (16q < 2^64): X, Y below b, where b
@@ -108,11 +118,11 @@ __device__ __forceinline__ void gs_bfly(uint64_t &X, uint64_t &Y, uint64_t w, ui
 // product lands in [0, 4q).
 template <bool BIG>
 __device__ __forceinline__ void gs_bfly_semi(uint64_t &X, uint64_t &Y, uint64_t w, uint64_t wp,
-                                             uint64_t q, uint64_t b) {
+                                             uint64_t nq, uint64_t b) {
     uint64_t x = X, y = Y;
     const uint64_t s = x + y;
     X = BIG ? csub(s, b) : s;
-    Y = mul_shoup_lazy4(x - y + b, w, wp, q);
+    Y = mul_shoup_lazy4n(x - y + b, w, wp, nq);
 }
 
 // Twiddle i.  UNIFORM: the index is the same in every lane of the wave; the
@@ -135,7 +145,7 @@ __device__ __forceinline__ void fwd_pass(uint64_t (&x)[1 << LE], int tid, const 
                                          uint64_t q) {
     constexpr int r = Geo<L, LE>::R(P), lo = Geo<L, LE>::LO(P), LT = Geo<L, LE>::LT;
     constexpr int R = 1 << r, G = (1 << LE) >> r, l0 = LE * P;
-    const uint64_t q4 = q << 2;
+    const uint64_t q4 = q << 2, nq = neg_opaque(q);
 #pragma unroll
     for (int g = 0; g < G; g++) {
         const uint32_t F = fixed_bits<L, LE, P>((uint32_t)tid, (uint32_t)g);
@@ -150,7 +160,7 @@ __device__ __forceinline__ void fwd_pass(uint64_t (&x)[1 << LE], int tid, const 
 #pragma unroll
                 for (int w = 0; w < half; w++) {
                     const int e0 = (v << (r - u)) | w;
-                    ct_bfly<REDUCE>(x[g * R + e0], x[g * R + e0 + half], W.w, W.wp, q, q4);
+                    ct_bfly<REDUCE>(x[g * R + e0], x[g * R + e0 + half], W.w, W.wp, nq, q4);
                 }
             }
         }
@@ -167,7 +177,7 @@ __device__ __forceinline__ void inv_pass(uint64_t (&x)[1 << LE], int tid, const 
     constexpr int r = Geo<L, LE>::R(P), lo = Geo<L, LE>::LO(P), LT = Geo<L, LE>::LT;
     constexpr int R = 1 << r, G = (1 << LE) >> r, l0 = LE * P;
     constexpr bool FIRST = P == Geo<L, LE>::NPASS - 1;
-    const uint64_t q4 = q << 2, q8 = q << 3;
+    const uint64_t q4 = q << 2, q8 = q << 3, nq = neg_opaque(q);
 #pragma unroll
     for (int g = 0; g < G; g++) {
         const uint32_t F = fixed_bits<L, LE, P>((uint32_t)tid, (uint32_t)g);
@@ -185,10 +195,10 @@ __device__ __forceinline__ void inv_pass(uint64_t (&x)[1 << LE], int tid, const 
                     uint64_t &X = x[g * R + e0], &Y = x[g * R + e0 + half];
                     if constexpr (SEMI) {
                         const bool big = u == r - 1 ? !FIRST : ((w >> (r - 2 - u)) & 1) == 0;
-                        if (big) gs_bfly_semi<true>(X, Y, W.w, W.wp, q, q8);
-                        else gs_bfly_semi<false>(X, Y, W.w, W.wp, q, q4);
+                        if (big) gs_bfly_semi<true>(X, Y, W.w, W.wp, nq, q8);
+                        else gs_bfly_semi<false>(X, Y, W.w, W.wp, nq, q4);
                     } else {
-                        gs_bfly(X, Y, W.w, W.wp, q, q4);
+                        gs_bfly(X, Y, W.w, W.wp, nq, q4);
                     }
                 }
             }
@@ -296,7 +306,7 @@ __device__ __forceinline__ void fwd_pass2(uint64_t (&x)[1 << LE], uint64_t (&y)[
                                           const Tw *__restrict__ tw, uint64_t q) {
     constexpr int r = Geo<L, LE>::R(P), lo = Geo<L, LE>::LO(P), LT = Geo<L, LE>::LT;
     constexpr int R = 1 << r, G = (1 << LE) >> r, l0 = LE * P;
-    const uint64_t q4 = q << 2;
+    const uint64_t q4 = q << 2, nq = neg_opaque(q);
 #pragma unroll
     for (int g = 0; g < G; g++) {
         const uint32_t F = fixed_bits<L, LE, P>((uint32_t)tid, (uint32_t)g);
@@ -311,8 +321,8 @@ __device__ __forceinline__ void fwd_pass2(uint64_t (&x)[1 << LE], uint64_t (&y)[
 #pragma unroll
                 for (int w = 0; w < half; w++) {
                     const int e0 = (v << (r - u)) | w;
-                    ct_bfly<REDUCE>(x[g * R + e0], x[g * R + e0 + half], W.w, W.wp, q, q4);
-                    ct_bfly<REDUCE>(y[g * R + e0], y[g * R + e0 + half], W.w, W.wp, q, q4);
+                    ct_bfly<REDUCE>(x[g * R + e0], x[g * R + e0 + half], W.w, W.wp, nq, q4);
+                    ct_bfly<REDUCE>(y[g * R + e0], y[g * R + e0 + half], W.w, W.wp, nq, q4);
                 }
             }
         }
@@ -325,7 +335,7 @@ __device__ __forceinline__ void inv_pass2(uint64_t (&x)[1 << LE], uint64_t (&y)[
     constexpr int r = Geo<L, LE>::R(P), lo = Geo<L, LE>::LO(P), LT = Geo<L, LE>::LT;
     constexpr int R = 1 << r, G = (1 << LE) >> r, l0 = LE * P;
     constexpr bool FIRST = P == Geo<L, LE>::NPASS - 1;
-    const uint64_t q4 = q << 2, q8 = q << 3;
+    const uint64_t q4 = q << 2, q8 = q << 3, nq = neg_opaque(q);
 #pragma unroll
     for (int g = 0; g < G; g++) {
         const uint32_t F = fixed_bits<L, LE, P>((uint32_t)tid, (uint32_t)g);
@@ -345,15 +355,15 @@ __device__ __forceinline__ void inv_pass2(uint64_t (&x)[1 << LE], uint64_t (&y)[
                     if constexpr (SEMI) {
                         const bool big = u == r - 1 ? !FIRST : ((w >> (r - 2 - u)) & 1) == 0;
                         if (big) {
-                            gs_bfly_semi<true>(X0, Y0, W.w, W.wp, q, q8);
-                            gs_bfly_semi<true>(X1, Y1, W.w, W.wp, q, q8);
+                            gs_bfly_semi<true>(X0, Y0, W.w, W.wp, nq, q8);
+                            gs_bfly_semi<true>(X1, Y1, W.w, W.wp, nq, q8);
                         } else {
-                            gs_bfly_semi<false>(X0, Y0, W.w, W.wp, q, q4);
-                            gs_bfly_semi<false>(X1, Y1, W.w, W.wp, q, q4);
+                            gs_bfly_semi<false>(X0, Y0, W.w, W.wp, nq, q4);
+                            gs_bfly_semi<false>(X1, Y1, W.w, W.wp, nq, q4);
                         }
                     } else {
-                        gs_bfly(X0, Y0, W.w, W.wp, q, q4);
-                        gs_bfly(X1, Y1, W.w, W.wp, q, q4);
+                        gs_bfly(X0, Y0, W.w, W.wp, nq, q4);
+                        gs_bfly(X1, Y1, W.w, W.wp, nq, q4);
                     }
                 }
             }
