@@ -36,9 +36,18 @@ __device__ __forceinline__ void load_bitrev(uint64_t (&x)[16], const uint64_t *_
     for (int s = 0; s < 16; s++) x[s] = src[bitrev_layout_index<L>(tid, s)];
 }
 
+// Shoup products whose remainder a w - h q is formed as a w + h (2^64 - q)
+// (equal modulo 2^64, no borrow chain; see neg_opaque).
+__device__ __forceinline__ uint64_t mul_shoup_s(uint64_t a, uint64_t w, uint64_t wp, uint64_t q) {
+    return csub(a * w + mulhi64(a, wp) * neg_opaque(q), q);
+}
+__device__ __forceinline__ uint64_t mul_shoup_lazy4_s(uint64_t a, uint64_t w, uint64_t wp, uint64_t q) {
+    return mul_shoup_lazy4n(a, w, wp, neg_opaque(q));
+}
+
 // Canonical residue of any 64-bit value: Shoup multiplication by 1.
 __device__ __forceinline__ uint64_t canon_any(uint64_t x, uint64_t q, uint64_t one_p) {
-    return mul_shoup(x, 1, one_p, q);
+    return mul_shoup_s(x, 1, one_p, q);
 }
 
 // mode: NttMode (kernels.hpp).  Rows row0, row0 + gridDim.x, ... of data:
@@ -88,7 +97,7 @@ __global__ __launch_bounds__(Geo<L>::T) void k_ntt_rows(DevCtx c, uint64_t *__re
 #pragma unroll
             for (int s = 0; s < 16; s++) {
                 uint64_t v;
-                if (mode == NTT_FWD_NINVM) v = mul_shoup(x[s], P.ninvm, P.ninvm_p, q);
+                if (mode == NTT_FWD_NINVM) v = mul_shoup_s(x[s], P.ninvm, P.ninvm_p, q);
                 else v = LZ ? canon_any(x[s], q, P.one_p) : canon8(x[s], q);
                 ptr[bitrev_layout_index<L>(t1, s)] = v;
             }
@@ -96,7 +105,7 @@ __global__ __launch_bounds__(Geo<L>::T) void k_ntt_rows(DevCtx c, uint64_t *__re
             const uint64_t w = mode == NTT_INV ? P.ninv : P.ninvm;
             const uint64_t wp = mode == NTT_INV ? P.ninv_p : P.ninvm_p;
 #pragma unroll
-            for (int s = 0; s < 16; s++) ptr[natural_index<L>(t1, s)] = mul_shoup(x[s], w, wp, q);
+            for (int s = 0; s < 16; s++) ptr[natural_index<L>(t1, s)] = mul_shoup_s(x[s], w, wp, q);
             // the inverse ends on the workgroup-wide exchange and the next row
             // starts with a wave-local one in the same buffer
             __syncthreads();
@@ -188,7 +197,7 @@ __global__ __launch_bounds__(Geo<L>::T) void k_tensor_intt(DevCtx c, const uint6
     ntt_inv_regs<L, 4, LZ>(x, lds, tid, c.itw + (size_t)limb * n, q);
     uint64_t *dst = Dt + ((item * 3 + comp) * K + limb) * (size_t)n;
 #pragma unroll
-    for (int s = 0; s < 16; s++) dst[natural_index<L>(tid, s)] = mul_shoup(x[s], P.ninvm, P.ninvm_p, q);
+    for (int s = 0; s < 16; s++) dst[natural_index<L>(tid, s)] = mul_shoup_s(x[s], P.ninvm, P.ninvm_p, q);
 }
 
 // A forward transform output as a Montgomery operand: below 4q (LZ: from
@@ -197,7 +206,7 @@ __global__ __launch_bounds__(Geo<L>::T) void k_tensor_intt(DevCtx c, const uint6
 // q 2^64 for q < 2^60.
 template <bool LZ>
 __device__ __forceinline__ uint64_t fwd_operand(uint64_t v, uint64_t q, uint64_t one_p) {
-    if constexpr (LZ) return mul_shoup_lazy4(v, 1, one_p, q);
+    if constexpr (LZ) return mul_shoup_lazy4_s(v, 1, one_p, q);
     else return csub(csub(v, q << 2), q << 1);
 }
 
@@ -305,7 +314,7 @@ __global__ __launch_bounds__(Geo<L>::T) void k_mul_tensor(DevCtx c, const uint64
     ntt_inv_regs<L, 4, LZ>(x, lds, tid, itw, q);
     const uint32_t t6 = fresh(tid);
 #pragma unroll
-    for (int s = 0; s < 16; s++) d0[natural_index<L>(t6, s)] = mul_shoup(x[s], P.ninvm, P.ninvm_p, q);
+    for (int s = 0; s < 16; s++) d0[natural_index<L>(t6, s)] = mul_shoup_s(x[s], P.ninvm, P.ninvm_p, q);
     // d2's parked product, read while d1 is transformed
     const uint32_t t7 = fresh(tid);
 #pragma unroll
@@ -314,11 +323,11 @@ __global__ __launch_bounds__(Geo<L>::T) void k_mul_tensor(DevCtx c, const uint64
     ntt_inv_regs<L, 4, LZ>(y, lds, tid, itw, q);
     const uint32_t t8 = fresh(tid);
 #pragma unroll
-    for (int s = 0; s < 16; s++) d1[natural_index<L>(t8, s)] = mul_shoup(y[s], P.ninvm, P.ninvm_p, q);
+    for (int s = 0; s < 16; s++) d1[natural_index<L>(t8, s)] = mul_shoup_s(y[s], P.ninvm, P.ninvm_p, q);
     ntt_inv_regs<L, 4, LZ>(x, lds, tid, itw, q);
     const uint32_t t9 = fresh(tid);
 #pragma unroll
-    for (int s = 0; s < 16; s++) d2[natural_index<L>(t9, s)] = mul_shoup(x[s], P.ninvm, P.ninvm_p, q);
+    for (int s = 0; s < 16; s++) d2[natural_index<L>(t9, s)] = mul_shoup_s(x[s], P.ninvm, P.ninvm_p, q);
 }
 
 // Squaring, transform phase fused: grid (K limbs, items).  For limb l of item
@@ -376,19 +385,19 @@ __global__ __launch_bounds__(Geo<L>::T) void k_square_tensor(DevCtx c, const uin
     ntt_inv_regs2<L, 4, LZ>(y, x, lds, tid, itw, q);
     const uint32_t t3 = fresh(tid);
 #pragma unroll
-    for (int s = 0; s < 16; s++) d0[natural_index<L>(t3, s)] = mul_shoup(y[s], P.ninvm, P.ninvm_p, q);
+    for (int s = 0; s < 16; s++) d0[natural_index<L>(t3, s)] = mul_shoup_s(y[s], P.ninvm, P.ninvm_p, q);
     // every thread rereads only the positions it parked
     const uint32_t t4 = fresh(tid);
 #pragma unroll
     for (int s = 0; s < 16; s++) y[s] = d1[bitrev_layout_index<L>(t4, s)];
     const uint32_t t5 = fresh(tid);
 #pragma unroll
-    for (int s = 0; s < 16; s++) d2[natural_index<L>(t5, s)] = mul_shoup(x[s], P.ninvm, P.ninvm_p, q);
+    for (int s = 0; s < 16; s++) d2[natural_index<L>(t5, s)] = mul_shoup_s(x[s], P.ninvm, P.ninvm_p, q);
     asm volatile("" ::: "memory");
     ntt_inv_regs<L, 4, LZ>(y, lds, tid, itw, q);
     const uint32_t t6 = fresh(tid);
 #pragma unroll
-    for (int s = 0; s < 16; s++) d1[natural_index<L>(t6, s)] = mul_shoup(y[s], P.ninvm, P.ninvm_p, q);
+    for (int s = 0; s < 16; s++) d1[natural_index<L>(t6, s)] = mul_shoup_s(y[s], P.ninvm, P.ninvm_p, q);
 }
 
 // Product of two operands both already transformed: grid (K limbs, items).
@@ -433,19 +442,19 @@ __global__ __launch_bounds__(Geo<L>::T) void k_mul_tensor_pre2(DevCtx c, const u
     ntt_inv_regs2<L, 4, LZ>(y, x, lds, tid, itw, q);
     const uint32_t t3 = fresh(tid);
 #pragma unroll
-    for (int s = 0; s < 16; s++) d0[natural_index<L>(t3, s)] = mul_shoup(y[s], P.ninvm, P.ninvm_p, q);
+    for (int s = 0; s < 16; s++) d0[natural_index<L>(t3, s)] = mul_shoup_s(y[s], P.ninvm, P.ninvm_p, q);
     // every thread rereads only the positions it parked
     const uint32_t t4 = fresh(tid);
 #pragma unroll
     for (int s = 0; s < 16; s++) y[s] = d2[bitrev_layout_index<L>(t4, s)];
     const uint32_t t5 = fresh(tid);
 #pragma unroll
-    for (int s = 0; s < 16; s++) d1[natural_index<L>(t5, s)] = mul_shoup(x[s], P.ninvm, P.ninvm_p, q);
+    for (int s = 0; s < 16; s++) d1[natural_index<L>(t5, s)] = mul_shoup_s(x[s], P.ninvm, P.ninvm_p, q);
     asm volatile("" ::: "memory");
     ntt_inv_regs<L, 4, LZ>(y, lds, tid, itw, q);
     const uint32_t t6 = fresh(tid);
 #pragma unroll
-    for (int s = 0; s < 16; s++) d2[natural_index<L>(t6, s)] = mul_shoup(y[s], P.ninvm, P.ninvm_p, q);
+    for (int s = 0; s < 16; s++) d2[natural_index<L>(t6, s)] = mul_shoup_s(y[s], P.ninvm, P.ninvm_p, q);
 }
 
 // Key switching fused: grid (k limbs j, items).  For every digit i the row
@@ -493,14 +502,14 @@ __global__ __launch_bounds__(Geo<L>::T) void k_relin_fused(DevCtx c, const uint6
 #pragma unroll
             for (int s = 0; s < 16; s++) {  // digit mod q_j, < 4q
                 const uint64_t v = prefetched(lds, t0, s);
-                x[s] = RAW ? v : mul_shoup_lazy4(v, 1, one_p, q);
+                x[s] = RAW ? v : mul_shoup_lazy4_s(v, 1, one_p, q);
             }
         } else {
             const uint64_t *src = c2 + (size_t)i * n;
 #pragma unroll
             for (int s = 0; s < 16; s++) {
                 const uint64_t v = src[natural_index<L>(t0, s)];
-                x[s] = RAW ? v : mul_shoup_lazy4(v, 1, one_p, q);
+                x[s] = RAW ? v : mul_shoup_lazy4_s(v, 1, one_p, q);
             }
         }
         auto hook = [&]() {

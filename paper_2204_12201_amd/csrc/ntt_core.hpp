@@ -89,7 +89,7 @@ __device__ __forceinline__ uint64_t neg_opaque(uint64_t q) {
     const uint64_t n = 0 - q;
     uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)n);
     uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(n >> 32));
-    asm volatile("" : "+s"(lo), "+s"(hi));
+    asm("" : "+s"(lo), "+s"(hi));
     return ((uint64_t)hi << 32) | lo;
 }
 
