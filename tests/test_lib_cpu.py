@@ -78,3 +78,24 @@ def test_valid_params_pass_validation(L):
     assert st in (0, -4)
     st = _create(L, 16384, inputs.PRIMES[(16384, 55)], 17, fhe.ENC_COEFF)
     assert st in (0, -4)
+
+
+def test_shoup_sum_form_host(tmp_path):
+    """The transforms form the lazy Shoup remainder a w - h q as
+    a w + h (2^64 - q) (equal modulo 2^64, no borrow chain).  The header's
+    host build checks both forms against each other and against a w mod q
+    (below 4q) for the configured primes and moduli at the extremes of the
+    supported range, on edge operands and 200,000 random pairs each."""
+    import shutil
+    import subprocess
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("no host C++ compiler")
+    exe = str(tmp_path / "host_modarith")
+    src = os.path.join(ROOT, "tests", "host_modarith.cpp")
+    inc = os.path.join(ROOT, "paper_2204_12201_amd", "csrc")
+    subprocess.run([gxx, "-O2", "-std=c++17", "-I", inc, src, "-o", exe], check=True)
+    qs = sorted({q for cfg in inputs.CONFIGS.values() for q in cfg["q"]})
+    qs += [3, (1 << 36) + 1, (1 << 61) - 1]
+    r = subprocess.run([exe, *map(str, qs)], capture_output=True, text=True)
+    assert r.returncode == 0 and r.stdout.startswith("ok"), r.stdout + r.stderr
