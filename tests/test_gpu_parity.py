@@ -791,3 +791,28 @@ def test_bridge_powers_full_size_sampled(dev):
     dec = ctx.decrypt(km["s"], bits.reshape(-1, 2, len(qs), n)).reshape(count, 5, n)[:, :, 0]
     plain = (xs[:, None].astype(np.int64) >> np.arange(5)) & 1
     assert (dec.astype(np.int64) == plain).all()
+
+
+@pytest.mark.parametrize("n,bits,k,count", [(16384, 55, 3, 183), (2048, 55, 5, 1101), (1024, 36, 3, 2731)])
+def test_ntt_row_loop_many_rows(dev, n, bits, k, count):
+    """Launches with more rows than resident workgroups, so every workgroup
+    loops over several rows (prefetching the next one while it transforms
+    the current one) and the last pass is ragged: sampled rows in the pinned
+    order against the oracle's transform, and every row back after the
+    inverse."""
+    qs = bfv.ntt_primes(n, bits, k)
+    say(f"ntt row loop n={n} k={k} rows={count * k}")
+    ctx = fhe.Context(n, qs, 17, "coeff")
+    rng = np.random.default_rng(n + count)
+    polys = np.stack([np.stack([rng.integers(0, q, n, dtype=np.uint64) for q in qs]) for _ in range(count)])
+    d = up(polys)
+    ctx.ntt(d)
+    got = down(d)
+    psis = [bfv.find_psi(q, n) for q in qs]
+    L = n.bit_length() - 1
+    rev = np.array([int(format(j, f"0{L}b")[::-1], 2) for j in range(n)])
+    for c in sorted({0, 1, count // 2, count - 2, count - 1}):
+        want = bfv.clib.ntt_rows(polys[c], qs, psis)
+        assert (got[c][:, rev] == want).all(), f"poly {c}"
+    ctx.ntt(d, inverse=True)
+    assert (down(d) == polys).all()
