@@ -714,11 +714,13 @@ def test_unfused_squaring_path_and_autotune(dev):
     assert (sq2 == sq).all()
 
 
-@pytest.mark.parametrize("n,k,limit", [(64, 4, 0), (256, 5, 16)])
+@pytest.mark.parametrize("n,k,limit", [(64, 4, 0), (256, 5, 16), (64, 4, 4)])
 def test_bridge_powers_all_words(dev, n, k, limit):
     """The power-basis bridge against the oracle word for word, bits decrypt
     to the plain bits (x = 16, 0, 9); with a batch cap of 16 the inputs run
-    in groups of two."""
+    in groups of two; with a cap of 4 (below the eight products of the last
+    tree level) one input at a time, each level in launches of at most four
+    products."""
     qs = bfv.ntt_primes(n, 55, k)
     P, km, pk, rlk, ctx, rlk_d = setup(n, qs, 17, "coeff", 49)
     if limit:
