@@ -818,3 +818,36 @@ def test_ntt_row_loop_many_rows(dev, n, bits, k, count):
         assert (got[c][:, rev] == want).all(), f"poly {c}"
     ctx.ntt(d, inverse=True)
     assert (down(d) == polys).all()
+
+
+def test_bridge_powers_edges(dev):
+    """Argument handling of the power-basis bridge: no inputs is a no-op;
+    slot encoding is unsupported; too few bits, a workspace below the
+    documented size and an output overlapping the inputs are rejected before
+    any launch (the output keeps its contents)."""
+    import torch
+    n = 64
+    qs = bfv.ntt_primes(n, 55, 3)
+    say("bridge powers edges")
+    P, km, pk, rlk, ctx, rlk_d = setup(n, qs, 17, "coeff", 14)
+    x = up(inputs.uniform_ciphertexts(n, qs, 2, 14, "x") % 2)  # canonical words
+    assert ctx.bridge_to_bits_powers(rlk_d, ctx.empty_ct(0), 5).shape == (0, 5, 2, 3, n)
+    with pytest.raises(fhe.FheError) as ei:
+        fhe.Context(n, qs, 257, "slots").bridge_to_bits_powers(rlk_d, x, 9)
+    assert ei.value.status == -7
+    with pytest.raises(fhe.FheError) as ei:
+        ctx.bridge_to_bits_powers(rlk_d, x, 4)  # 2^4 < 17
+    assert ei.value.status == -1
+    L = fhe.lib()
+    out = torch.zeros((2, 5, 2, 3, n), dtype=torch.int64, device="cuda")
+    ws = torch.empty(64, dtype=torch.uint8, device="cuda")
+    st = L.fhe_bridge_to_bits_powers(ctx._h, fhe._dptr(rlk_d), fhe._dptr(x), 5, fhe._dptr(out), 2,
+                                     fhe._dptr(ws), 64, fhe._stream())
+    assert st == -8
+    ws, _ = ctx.workspace(fhe.OP_BRIDGE_POWERS, 1)
+    buf = torch.zeros((6, 2, 3, n), dtype=torch.int64, device="cuda")
+    buf[0].copy_(x[0])
+    st = L.fhe_bridge_to_bits_powers(ctx._h, fhe._dptr(rlk_d), fhe._dptr(buf), 5, fhe._dptr(buf), 1,
+                                     fhe._dptr(ws), ws.numel(), fhe._stream())
+    assert st == -1
+    assert (down(out) == 0).all() and (down(buf[1:]) == 0).all()
