@@ -32,10 +32,15 @@
  * and returns without synchronising, except the calls that return host data
  * (fhe_decrypt) which synchronise the stream.  Argument and shape errors are
  * returned synchronously before anything is enqueued; launch failures return
- * FHE_EDEVICE.  A context is not thread safe: one context per host thread.
+ * FHE_EDEVICE; a fault of a kernel already enqueued surfaces as FHE_EDEVICE
+ * from fhe_sync (or from the next call that synchronises).  A context is not
+ * thread safe: one context per host thread.
  *
- * Aliasing: `out` may be exactly `a` or `b` (in-place); any other overlap
- * between outputs and inputs is undefined.
+ * Aliasing: where a call documents it, `out` may be exactly `a` or `b`
+ * (in place).  Any other overlap between an output and an input, or between
+ * the workspace and an operand of the multiply calls, is rejected with
+ * FHE_EINVAL before anything is enqueued (the checks compare address ranges
+ * on the host).
  *
  * Inputs must be canonical residues.  With the environment variable
  * FHE_VALIDATE=1 the elementwise, multiply and bridge calls check this first
@@ -219,11 +224,14 @@ fhe_status fhe_autotune_mul_relin(fhe_ctx *ctx, const uint64_t *rlk_dev, const u
  * computes.  Each part runs on its context's own stream (created on first use,
  * default priority), which first waits for the work already queued on `stream`;
  * `stream` then waits for all parts, so parts of different contexts overlap on
- * the device.  The call returns once everything is enqueued.  Parts must not
- * share outputs or workspaces (FHE_EINVAL, checked before anything is
- * enqueued); parts of one context run one after the other.  All contexts must
- * be on the current device.  Arguments as for fhe_mul_relin (each ws sized for
- * its part). */
+ * the device.  The call returns once everything is enqueued.  Since parts run
+ * concurrently, an output or workspace range of one part must not overlap the
+ * inputs, output or workspace of any other part (FHE_EINVAL, checked before
+ * anything is enqueued); parts of one context run one after the other.  If an
+ * error stops the call after some parts were enqueued, `stream` still waits
+ * for those parts before the error is returned.  All contexts must be on the
+ * current device.  Arguments as for fhe_mul_relin (each ws sized for its
+ * part). */
 typedef struct {
     fhe_ctx *ctx;
     const uint64_t *rlk_dev, *a, *b;
@@ -237,10 +245,14 @@ fhe_status fhe_mul_relin_multi(const fhe_mul_part *parts, size_t nparts, hipStre
 /* Repeated squaring in place: x[j] <- x[j]^(2^depth), i.e. depth calls of
  * fhe_mul_relin(x, x, x) (same words), for j < count.  graph != 0 records the
  * launch sequence once into a HIP graph kept by the context, keyed by
- * (rlk_dev, x, ws, count, depth), and replays it on later calls with the same
- * key (the graph holds those addresses: the buffers must stay allocated while
- * the context lives).  Per-launch timing or validation makes the call run
- * eagerly.  ws: FHE_OP_SQUARE_RELIN bytes for count. */
+ * (rlk_dev, x, ws, ws_bytes, count, depth) and the launch shape it recorded
+ * (batch limit, fused threshold of squarings), and replays it on later calls
+ * with the same key.  fhe_set_batch_limit, fhe_set_fused_threshold and
+ * fhe_autotune_mul_relin drop every recorded graph; at most 16 are kept
+ * (the oldest is dropped first).  A graph holds the buffers' addresses: they
+ * must stay allocated while the graph is kept.  Per-launch timing or
+ * validation makes the call run eagerly.  ws: FHE_OP_SQUARE_RELIN bytes for
+ * count. */
 fhe_status fhe_square_chain(fhe_ctx *ctx, const uint64_t *rlk_dev, uint64_t *x, uint32_t depth,
                             size_t count, void *ws, size_t ws_bytes, int graph, hipStream_t stream);
 
@@ -382,6 +394,10 @@ fhe_status fhe_reset_kernel_stats(fhe_ctx *ctx);
 /* Number of coefficients that took the exact (multi-word) path in the base
  * conversions since the context was created (diagnostic; synchronises). */
 fhe_status fhe_fallback_count(fhe_ctx *ctx, uint64_t *count);
+
+/* Waits for all work enqueued on `stream` and returns FHE_EDEVICE if any of
+ * it failed on the device (the asynchronous errors of the calls above). */
+fhe_status fhe_sync(fhe_ctx *ctx, hipStream_t stream);
 
 const char *fhe_status_str(fhe_status status);
 

@@ -205,12 +205,17 @@ struct fhe_ctx {
     // and the graphs of fhe_square_chain; created on first use
     hipStream_t aux = nullptr;
     hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+    // A graph holds the addresses, the chunking and the fused/unfused choice
+    // of the launches it recorded: its key is all of them, and the setters of
+    // the launch shape drop every graph.  `done` is recorded after each replay
+    // so a graph is destroyed only once its last replay has finished.
     struct ChainGraph {
         const void *rlk, *x, *ws;
-        size_t count;
+        size_t count, ws_bytes, batch_limit, fused_min_rows;
         uint32_t depth;
         hipGraph_t g;
         hipGraphExec_t ge;
+        hipEvent_t done;
     };
     std::vector<ChainGraph> graphs;
     // pinned staging of fhe_weighted_sum's weights; the event marks the end of
@@ -221,6 +226,9 @@ struct fhe_ctx {
 };
 
 namespace {
+
+// Most squaring-chain graphs a context keeps (each holds its buffers' addresses).
+constexpr size_t kMaxGraphs = 16;
 
 const char *kKernelNames[KK_COUNT] = {"lift_q2p",   "square_tensor", "scale_round", "relin_fused",
                                       "ntt_rows",   "elementwise",   "bridge",      "misc",
@@ -380,12 +388,24 @@ fhe_status alloc_copy(void **dst, const void *src, size_t bytes) {
     return FHE_OK;
 }
 
-void release(fhe_ctx *c) {
-    for (auto &cg : c->graphs) {
-        hipGraphExecDestroy(cg.ge);
-        hipGraphDestroy(cg.g);
+// Destroys graph i of the squaring-chain cache after its last replay ended.
+void drop_graph(fhe_ctx *c, size_t i) {
+    fhe_ctx::ChainGraph &cg = c->graphs[i];
+    if (cg.done) {
+        (void)hipEventSynchronize(cg.done);
+        (void)hipEventDestroy(cg.done);
     }
-    c->graphs.clear();
+    (void)hipGraphExecDestroy(cg.ge);
+    (void)hipGraphDestroy(cg.g);
+    c->graphs.erase(c->graphs.begin() + (long)i);
+}
+
+void drop_graphs(fhe_ctx *c) {
+    while (!c->graphs.empty()) drop_graph(c, c->graphs.size() - 1);
+}
+
+void release(fhe_ctx *c) {
+    drop_graphs(c);
     if (c->wpin_ev) {
         (void)hipEventSynchronize(c->wpin_ev);
         (void)hipEventDestroy(c->wpin_ev);
@@ -802,12 +822,14 @@ size_t fhe_workspace_bytes(const fhe_ctx *c, int op, size_t count) {
 fhe_status fhe_set_fused_threshold(fhe_ctx *c, int square, size_t min_rows) {
     if (!c) return FHE_EINVAL;
     c->fused_min_rows[square ? 1 : 0] = min_rows;
+    drop_graphs(c);
     return FHE_OK;
 }
 
 fhe_status fhe_set_batch_limit(fhe_ctx *c, size_t max_items) {
     if (!c) return FHE_EINVAL;
     c->batch_limit = max_items ? (max_items > 65535 ? 65535 : max_items) : c->default_limit;
+    drop_graphs(c);
     return FHE_OK;
 }
 
@@ -1023,17 +1045,14 @@ fhe_status fhe_sub_plain_const(fhe_ctx *c, const uint64_t *a, uint64_t cval, uin
 
 // -------------------------------------------------------------- hot path ----
 
+static fhe_status mul_args_ok(fhe_ctx *c, const uint64_t *rlk, const uint64_t *a, const uint64_t *b,
+                              uint64_t *out, size_t count, void *ws, size_t ws_bytes);
+
 fhe_status fhe_mul_relin(fhe_ctx *c, const uint64_t *rlk, const uint64_t *a, const uint64_t *b,
                          uint64_t *out, size_t count, void *ws, size_t ws_bytes, hipStream_t st) {
-    if (!c) return FHE_EINVAL;
+    FHE_TRY(mul_args_ok(c, rlk, a, b, out, count, ws, ws_bytes));
     if (count == 0) return FHE_OK;
-    if (!rlk || !a || !b || !out || !ws) return FHE_EINVAL;
-    const size_t bytes = count * ct_words(c) * 8;
-    if (out != a && overlaps(out, a, bytes)) return FHE_EINVAL;
-    if (out != b && overlaps(out, b, bytes)) return FHE_EINVAL;
     const bool square = (a == b);
-    if (ws_bytes < fhe_workspace_bytes(c, square ? FHE_OP_SQUARE_RELIN : FHE_OP_MUL_RELIN, count))
-        return FHE_EWORKSPACE;
     FHE_TRY(check_canonical(c, a, count * 2 * c->k, c->k, 0, st));
     if (!square) FHE_TRY(check_canonical(c, b, count * 2 * c->k, c->k, 0, st));
     return mul_relin_impl(c, rlk, a, b, out, count, ws, st);
@@ -1049,6 +1068,7 @@ fhe_status fhe_autotune_mul_relin(fhe_ctx *c, const uint64_t *rlk, const uint64_
     const size_t bytes = count * ct_words(c) * 8;
     if (overlaps(out, a, bytes) || overlaps(out, b, bytes)) return FHE_EINVAL;
     const size_t saved_limit = c->batch_limit, saved_thr = c->fused_min_rows[square ? 1 : 0];
+    drop_graphs(c);  // recorded graphs hold the launch shape this call changes
     // candidates: chunk caps (whole batch, halves, quarters) x fused or not
     size_t caps[3];
     int ncaps = 0;
@@ -1130,8 +1150,11 @@ static fhe_status mul_args_ok(fhe_ctx *c, const uint64_t *rlk, const uint64_t *a
     const size_t bytes = count * ct_words(c) * 8;
     if (out != a && overlaps(out, a, bytes)) return FHE_EINVAL;
     if (out != b && overlaps(out, b, bytes)) return FHE_EINVAL;
-    if (ws_bytes < fhe_workspace_bytes(c, a == b ? FHE_OP_SQUARE_RELIN : FHE_OP_MUL_RELIN, count))
-        return FHE_EWORKSPACE;
+    const size_t need = fhe_workspace_bytes(c, a == b ? FHE_OP_SQUARE_RELIN : FHE_OP_MUL_RELIN, count);
+    if (ws_bytes < need) return FHE_EWORKSPACE;
+    // the pipeline writes all of its workspace: it must not overlap any operand
+    if (overlaps2(ws, need, a, bytes) || overlaps2(ws, need, b, bytes) || overlaps2(ws, need, out, bytes))
+        return FHE_EINVAL;
     return FHE_OK;
 }
 
@@ -1142,32 +1165,49 @@ fhe_status fhe_mul_relin_multi(const fhe_mul_part *parts, size_t nparts, hipStre
     if (hipGetDevice(&dev) != hipSuccess) return FHE_EDEVICE;
     for (size_t i = 0; i < nparts; i++) {
         const fhe_mul_part &p = parts[i];
+        if (!p.ctx) return FHE_EINVAL;
         FHE_TRY(mul_args_ok(p.ctx, p.rlk_dev, p.a, p.b, p.out, p.count, p.ws, p.ws_bytes));
         if (p.ctx->device != dev) return FHE_EINVAL;
-        for (size_t j = 0; j < i; j++) {
+        if (p.count == 0) continue;
+        const size_t pb = p.count * ct_words(p.ctx) * 8;
+        const size_t pw = fhe_workspace_bytes(p.ctx, p.a == p.b ? FHE_OP_SQUARE_RELIN : FHE_OP_MUL_RELIN, p.count);
+        for (size_t j = 0; j < nparts; j++) {
             const fhe_mul_part &o = parts[j];
-            if (p.count && o.count &&
-                (overlaps2(p.out, p.count * ct_words(p.ctx) * 8, o.out, o.count * ct_words(o.ctx) * 8) ||
-                 (p.ws == o.ws)))
+            if (j == i || o.count == 0) continue;
+            const size_t ob = o.count * ct_words(o.ctx) * 8;
+            const size_t ow = fhe_workspace_bytes(o.ctx, o.a == o.b ? FHE_OP_SQUARE_RELIN : FHE_OP_MUL_RELIN, o.count);
+            // parts may run concurrently: an output or a workspace of one part
+            // must not overlap anything another part reads or writes
+            if (overlaps2(p.out, pb, o.out, ob) || overlaps2(p.out, pb, o.a, ob) || overlaps2(p.out, pb, o.b, ob) ||
+                overlaps2(p.ws, pw, o.ws, ow) || overlaps2(p.ws, pw, o.a, ob) || overlaps2(p.ws, pw, o.b, ob) ||
+                overlaps2(p.ws, pw, o.out, ob))
                 return FHE_EINVAL;
         }
         FHE_TRY(ensure_aux(p.ctx));
     }
     hipEvent_t fork = parts[0].ctx->fork_ev;
     FHE_HIP(hipEventRecord(fork, st));
-    for (size_t i = 0; i < nparts; i++) {
-        const fhe_mul_part &p = parts[i];
+    // on an error after some parts were enqueued, `st` still waits for them,
+    // so the caller's stream never runs ahead of work on its buffers
+    fhe_status res = FHE_OK;
+    size_t enq = 0;
+    for (; enq < nparts && res == FHE_OK; enq++) {
+        const fhe_mul_part &p = parts[enq];
         if (p.count == 0) continue;
         fhe_ctx *c = p.ctx;
-        FHE_HIP(hipStreamWaitEvent(c->aux, fork, 0));
-        FHE_TRY(check_canonical(c, p.a, p.count * 2 * c->k, c->k, 0, c->aux));
-        if (p.a != p.b) FHE_TRY(check_canonical(c, p.b, p.count * 2 * c->k, c->k, 0, c->aux));
-        FHE_TRY(mul_relin_impl(c, p.rlk_dev, p.a, p.b, p.out, p.count, p.ws, c->aux));
-        FHE_HIP(hipEventRecord(c->join_ev, c->aux));
+        if (hipStreamWaitEvent(c->aux, fork, 0) != hipSuccess) {
+            res = FHE_EDEVICE;
+            break;
+        }
+        res = check_canonical(c, p.a, p.count * 2 * c->k, c->k, 0, c->aux);
+        if (res == FHE_OK && p.a != p.b) res = check_canonical(c, p.b, p.count * 2 * c->k, c->k, 0, c->aux);
+        if (res == FHE_OK) res = mul_relin_impl(c, p.rlk_dev, p.a, p.b, p.out, p.count, p.ws, c->aux);
+        if (hipEventRecord(c->join_ev, c->aux) != hipSuccess && res == FHE_OK) res = FHE_EDEVICE;
     }
-    for (size_t i = 0; i < nparts; i++)
-        if (parts[i].count) FHE_HIP(hipStreamWaitEvent(st, parts[i].ctx->join_ev, 0));
-    return FHE_OK;
+    for (size_t i = 0; i < enq && i < nparts; i++)
+        if (parts[i].count && hipStreamWaitEvent(st, parts[i].ctx->join_ev, 0) != hipSuccess && res == FHE_OK)
+            res = FHE_EDEVICE;
+    return res;
 }
 
 fhe_status fhe_square_chain(fhe_ctx *c, const uint64_t *rlk, uint64_t *x, uint32_t depth, size_t count,
@@ -1181,11 +1221,16 @@ fhe_status fhe_square_chain(fhe_ctx *c, const uint64_t *rlk, uint64_t *x, uint32
         for (uint32_t d = 0; d < depth; d++) FHE_TRY(mul_relin_impl(c, rlk, x, x, x, count, ws, st));
         return FHE_OK;
     }
+    const size_t thr = c->fused_min_rows[1];
     for (auto &cg : c->graphs)
-        if (cg.rlk == rlk && cg.x == x && cg.ws == ws && cg.count == count && cg.depth == depth) {
+        if (cg.rlk == rlk && cg.x == x && cg.ws == ws && cg.count == count && cg.depth == depth &&
+            cg.ws_bytes == ws_bytes && cg.batch_limit == c->batch_limit && cg.fused_min_rows == thr) {
             FHE_HIP(hipGraphLaunch(cg.ge, st));
+            FHE_HIP(hipEventRecord(cg.done, st));
             return FHE_OK;
         }
+    // bounded cache: the oldest graph goes first
+    while (c->graphs.size() >= kMaxGraphs) drop_graph(c, 0);
     // record the launches on the context's own stream (capture executes
     // nothing), then run the graph on the caller's stream
     FHE_TRY(ensure_aux(c));
@@ -1203,8 +1248,15 @@ fhe_status fhe_square_chain(fhe_ctx *c, const uint64_t *rlk, uint64_t *x, uint32
         hipGraphDestroy(g);
         return FHE_EDEVICE;
     }
-    c->graphs.push_back({rlk, x, ws, count, depth, g, ge});
+    hipEvent_t done = nullptr;
+    if (hipEventCreateWithFlags(&done, hipEventDisableTiming) != hipSuccess) {
+        hipGraphExecDestroy(ge);
+        hipGraphDestroy(g);
+        return FHE_EDEVICE;
+    }
+    c->graphs.push_back({rlk, x, ws, count, ws_bytes, c->batch_limit, thr, depth, g, ge, done});
     FHE_HIP(hipGraphLaunch(ge, st));
+    FHE_HIP(hipEventRecord(done, st));
     return FHE_OK;
 }
 
@@ -1684,6 +1736,14 @@ fhe_status fhe_reset_kernel_stats(fhe_ctx *c) {
         c->launches[i] = 0;
     }
     return FHE_OK;
+}
+
+fhe_status fhe_sync(fhe_ctx *c, hipStream_t st) {
+    if (!c) return FHE_EINVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return FHE_EDEVICE;
+    const hipError_t e = hipStreamSynchronize(st);
+    const hipError_t l = hipGetLastError();
+    return (e == hipSuccess && l == hipSuccess) ? FHE_OK : FHE_EDEVICE;
 }
 
 fhe_status fhe_fallback_count(fhe_ctx *c, uint64_t *count) {

@@ -90,6 +90,7 @@ _SIGS = [
     ("fhe_kernel_stats", _I, [_P, _I, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_uint64)]),
     ("fhe_reset_kernel_stats", _I, [_P]),
     ("fhe_fallback_count", _I, [_P, ctypes.POINTER(ctypes.c_uint64)]),
+    ("fhe_sync", _I, [_P, _P]),
     ("fhe_status_str", ctypes.c_char_p, [_I]),
 ]
 
@@ -447,6 +448,10 @@ class Context:
         v = ctypes.c_uint64()
         _check(lib().fhe_fallback_count(self._h, ctypes.byref(v)), "fhe_fallback_count")
         return v.value
+
+    def sync(self):
+        """Wait for the current stream; raises FheError on a device fault."""
+        _check(lib().fhe_sync(self._h, _stream()), "fhe_sync")
 
 
 def mul_relin_multi(parts):

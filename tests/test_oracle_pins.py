@@ -352,6 +352,72 @@ def test_decryption_chain_small_slots():
     assert bfv.noise_ok(P, km["s"], c, bfv.encode(P, want))[1]
 
 
+def _negacyclic(a, b, q):
+    """Plain negacyclic product mod q (written here, not the oracle's)."""
+    n = len(a)
+    out = [0] * n
+    for i in range(n):
+        for j in range(n):
+            if i + j < n:
+                out[i + j] += a[i] * b[j]
+            else:
+                out[i + j - n] -= a[i] * b[j]
+    return [x % q for x in out]
+
+
+@pytest.mark.parametrize("t", [17, 257])
+def test_noise_ok_against_exact_rational_decryption(t):
+    """noise_ok(ct, m) returns max |v| of the centred noise v = [c0 + c1 s -
+    Delta m]_q and a flag that must be True exactly when decryption returns m
+    in every coefficient (the flag's criterion |t v - (q mod t) m| < q/2 is
+    the exact condition once q > 2 t^2).  Ciphertexts are built with chosen
+    noise straddling the decryption boundary on both sides, for several m
+    (so the (q mod t) m term matters), and decrypted here by exact rational
+    rounding of t [c0 + c1 s]_q / q; vmax is checked against the planted v."""
+    n = 16
+    P = bfv.Params(n, bfv.ntt_primes(n, 30, 2), t, "coeff")
+    q, D, r = P.q, P.delta, P.q % t
+    assert r != 0 and q > 2 * t * t
+    rng = random.Random(t)
+    s = [rng.choice((-1, 0, 1)) for _ in range(n)]
+    seen = {True: 0, False: 0}
+    for m0 in (0, 1, t // 2, t - 1):
+        # largest v0 >= 0 and smallest v0 < 0 with |t v0 - r m0| < q/2, found by
+        # exact rationals (independent of the criterion's algebra)
+        def dec_ok(v0):
+            return round_half_up(Fraction(t * ((D * m0 + v0) % q), q)) % t == m0
+
+        def round_half_up(x):
+            return math.floor(x + Fraction(1, 2))
+
+        hi = (q // 2 + r * m0) // t
+        while dec_ok(hi + 1):
+            hi += 1
+        while not dec_ok(hi):
+            hi -= 1
+        lo = -((q // 2 - r * m0) // t)
+        while dec_ok(lo - 1):
+            lo -= 1
+        while not dec_ok(lo):
+            lo += 1
+        for v0 in (hi - 1, hi, hi + 1, hi + 2, lo - 2, lo - 1, lo, lo + 1, 0, 5):
+            m = [rng.randrange(t) for _ in range(n)]
+            m[0] = m0
+            v = [rng.randrange(-50, 51) for _ in range(n)]
+            v[0] = v0
+            c1 = [rng.randrange(q) for _ in range(n)]
+            c1s = _negacyclic(c1, s, q)
+            c0 = [(D * mi + vi - x) % q for mi, vi, x in zip(m, v, c1s)]
+            ct = np.stack([bfv.from_ints(P, c0), bfv.from_ints(P, c1)])
+            vmax, ok = bfv.noise_ok(P, np.array(s, dtype=np.int8), ct, np.array(m, dtype=np.uint64))
+            X = [(a + b) % q for a, b in zip(c0, _negacyclic(c1, s, q))]
+            dec = [round_half_up(Fraction(t * x, q)) % t for x in X]
+            assert ok == (dec == m), (m0, v0)
+            assert vmax == max(abs(x) for x in v)
+            seen[ok] += 1
+    assert seen[True] and seen[False]
+
+
 def test_decryption_chain_plain_bfv_workload():
     """n=4096, three 36-bit primes, t=65537: Dec(Enc a * Enc b) = a b slotwise."""
     cfg = inputs.CONFIGS["bfv_n4096"]
