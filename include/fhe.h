@@ -205,6 +205,25 @@ fhe_status fhe_mul_relin(fhe_ctx *ctx, const uint64_t *rlk_dev, const uint64_t *
                          const uint64_t *b, uint64_t *out, size_t count, void *ws,
                          size_t ws_bytes, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the words
+ * of fhe_mul_relin(ctx, rlk_dev, a, b, out, count, ...) without a caller
+ * workspace.  The workspace is a static device array of FHE_STATIC_WS_BYTES
+ * bytes inside the library, one per device, held from the first context on
+ * that device until the process ends; the call allocates nothing (no
+ * hipMalloc, no events: per-launch timing is skipped for it).  A call needs
+ * fhe_workspace_bytes(ctx, FHE_OP_MUL_RELIN or FHE_OP_SQUARE_RELIN when
+ * a == b, count) bytes, i.e. min(count, batch limit) products' worth; more
+ * than FHE_STATIC_WS_BYTES returns FHE_EWORKSPACE before anything is enqueued
+ * (split the call or lower fhe_set_batch_limit).  Every call on a device, from
+ * any context or stream, uses the same array: calls that overlap in time on
+ * one device race and give undefined words; serialise them (one stream, or
+ * events).  Nothing in the array needs to start at zero: each call writes the
+ * part it reads.  Aliasing and the other arguments as for fhe_mul_relin. */
+#define FHE_STATIC_WS_BYTES (64u << 20)
+fhe_status fhe_mul_relin_static(fhe_ctx *ctx, const uint64_t *rlk_dev, const uint64_t *a,
+                                const uint64_t *b, uint64_t *out, size_t count, hipStream_t stream);
+
 /* Autotuner of the product pipeline's launch shape for this context: times
  * fhe_mul_relin(a, b, out) for count items (a == b: the squaring path) with
  * chunk caps count, count/2, count/4 (never above the current cap) and with

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "fhe.h"
@@ -13,7 +14,30 @@
 #include "ntt_core.hpp"
 #include "tables.hpp"
 
+// Workspace of fhe_mul_relin_static: one array per device, held by the
+// loaded code object until the process ends.  In host code `scratch` only
+// names the symbol; its device address (one per device) comes from
+// hipGetSymbolAddress with that device current and is kept in scratch_dev.
+static __device__ __align__(256) uint8_t scratch[FHE_STATIC_WS_BYTES];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+void *scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on `device`, which must be the current device.
+fhe_status scratch_address(int device, void **out) {
+    if (device < 0 || device >= kMaxDevices) return FHE_EDEVICE;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_dev[device]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return FHE_EDEVICE;
+        scratch_dev[device] = ptr;
+    }
+    *out = scratch_dev[device];
+    return FHE_OK;
+}
 
 // ------------------------------------------------------------ host math ----
 
@@ -218,6 +242,9 @@ struct fhe_ctx {
         hipEvent_t done;
     };
     std::vector<ChainGraph> graphs;
+    // device address of the static workspace of fhe_mul_relin_static on this
+    // context's device (shared by every context on the device)
+    void *scratch = nullptr;
     // pinned staging of fhe_weighted_sum's weights; the event marks the end of
     // the last copy out of it
     int32_t *wpin = nullptr;
@@ -693,6 +720,7 @@ fhe_status fhe_ctx_create(const fhe_params *p, int hip_device, fhe_ctx **out) {
 
     fhe_status st = FHE_OK;
     if (hipSetDevice(hip_device) != hipSuccess) st = FHE_EDEVICE;
+    if (st == FHE_OK) st = scratch_address(hip_device, &c->scratch);
     if (st == FHE_OK) st = alloc_copy(&c->d_pc, pc.data(), pc.size() * sizeof(PrimeConst));
     if (st == FHE_OK) st = alloc_copy(&c->d_tw, tw.data(), tw.size() * sizeof(Tw));
     if (st == FHE_OK) st = alloc_copy(&c->d_itw, itw.data(), itw.size() * sizeof(Tw));
@@ -1047,6 +1075,27 @@ fhe_status fhe_sub_plain_const(fhe_ctx *c, const uint64_t *a, uint64_t cval, uin
 
 static fhe_status mul_args_ok(fhe_ctx *c, const uint64_t *rlk, const uint64_t *a, const uint64_t *b,
                               uint64_t *out, size_t count, void *ws, size_t ws_bytes);
+
+fhe_status fhe_mul_relin_static(fhe_ctx *c, const uint64_t *rlk, const uint64_t *a, const uint64_t *b,
+                                uint64_t *out, size_t count, hipStream_t st) {
+    if (!c) return FHE_EINVAL;
+    if (count == 0) return FHE_OK;
+    if (!c->scratch) return FHE_EDEVICE;
+    const bool square = (a == b);
+    const size_t need = fhe_workspace_bytes(c, square ? FHE_OP_SQUARE_RELIN : FHE_OP_MUL_RELIN, count);
+    if (need > (size_t)FHE_STATIC_WS_BYTES) return FHE_EWORKSPACE;
+    // the static array is the library's own memory: only the operands'
+    // mutual aliasing needs checking (mul_args_ok with the array as workspace)
+    FHE_TRY(mul_args_ok(c, rlk, a, b, out, count, c->scratch, FHE_STATIC_WS_BYTES));
+    FHE_TRY(check_canonical(c, a, count * 2 * c->k, c->k, 0, st));
+    if (!square) FHE_TRY(check_canonical(c, b, count * 2 * c->k, c->k, 0, st));
+    // per-launch timing would create events on demand: off for this call
+    const bool timing = c->timing;
+    c->timing = false;
+    const fhe_status res = mul_relin_impl(c, rlk, a, b, out, count, c->scratch, st);
+    c->timing = timing;
+    return res;
+}
 
 fhe_status fhe_mul_relin(fhe_ctx *c, const uint64_t *rlk, const uint64_t *a, const uint64_t *b,
                          uint64_t *out, size_t count, void *ws, size_t ws_bytes, hipStream_t st) {

@@ -73,6 +73,7 @@ _SIGS = [
     ("fhe_sub_plain_const", _I, [_P, _P, _U64, _P, _Z, _P]),
     ("fhe_mul_relin", _I, [_P, _P, _P, _P, _P, _Z, _P, _Z, _P]),
     ("fhe_mul_relin_multi", _I, [ctypes.POINTER(MulPart), _Z, _P]),
+    ("fhe_mul_relin_static", _I, [_P, _P, _P, _P, _P, _Z, _P]),
     ("fhe_square_chain", _I, [_P, _P, _P, _U32, _Z, _P, _Z, _I, _P]),
     ("fhe_bridge_to_bits", _I, [_P, _P, _P, _U32, _P, _P, _Z, _P, _Z, _P]),
     ("fhe_bits_to_mod", _I, [_P, _P, _U32, _P, _Z, _P]),
