@@ -41,16 +41,25 @@ METRIC = "ct mul+relin/s at n=16384 (batched vs plain GPU), bridge conversions/s
 # Peak figures (MI355X, gfx950): 256 CUs x 128 32-bit lanes at 2.4 GHz issue
 # 78.6 T simple VALU lane-ops/s (the fp32 vector peak of 157.3 TFLOP/s counts an
 # FMA as two); 32-bit integer multiplies (v_mul_lo_u32, v_mul_hi_u32,
-# v_mad_u64_u32) issue at half that rate on gfx950.  The lazy 64-bit butterfly
-# used here (Shoup product with a three-multiply quotient estimate) needs at
-# least 9 multiplies (3 for the estimate, 3 each for the low halves of a*w and of
-# quotient*q) and 18 full-rate slots of 64-bit adds, subtracts and the
-# conditional subtraction: 9*2 + 18 = 36 issue slots, so the butterfly roofline
-# is 78.6e12 / 36 = 2.18e12 butterflies/s.
+# v_mad_u64_u32) issue at half that rate on gfx950 (measured by the calibration
+# probe).
+#
+# Roofline of a 64-bit modular butterfly, algorithmic count: about 10
+# multiply-class 32-bit operations (the 64 x 64-bit modular product built from
+# 32-bit multiplies) and about 8 other 32-bit operations (the add, subtract and
+# reduction), the multiplies at half rate: 10*2 + 8 = 28 issue slots, peak
+# 78.6e12 / 28 = 2.81e12 butterflies/s.  This is the reported `peak`.
+#
+# Second figure, the model of the butterfly as implemented (Shoup product with a
+# three-multiply quotient estimate): 9 multiplies (3 for the estimate, 3 each
+# for the low halves of a*w and of quotient*q) and 18 full-rate slots of 64-bit
+# adds, subtracts and the conditional subtraction: 36 slots, 2.18e12/s.
 CUS, LANES_PER_CU, CLOCK = 256, 128, 2.4e9
 VALU_LANE_OPS = CUS * LANES_PER_CU * CLOCK
-SLOTS_PER_BFLY = 9 * 2 + 18
+SLOTS_PER_BFLY = 10 * 2 + 8
 PEAK_BFLY = VALU_LANE_OPS / SLOTS_PER_BFLY
+SLOTS_PER_BFLY_IMPL = 9 * 2 + 18
+PEAK_BFLY_IMPL = VALU_LANE_OPS / SLOTS_PER_BFLY_IMPL
 HBM_PEAK = 8.0e12
 
 # HBM bytes per launch of the transform kernels, from rocprofv3 FETCH_SIZE and
@@ -110,13 +119,23 @@ def main():
     ap.add_argument("--legs", default="all",
                     help="comma-separated legs after the headline (powers, plain, autotune, ntt, c0, mixed, chain, "
                          "imputation, serving) or all")
-    ap.add_argument("--serve-seconds", type=float, default=10.0,
-                    help="length of the Poisson arrival window of the serving leg")
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
+                    help="length of the Poisson arrival window of the serving leg (200 requests/s)")
+    ap.add_argument("--saturate-rate", type=float, default=1000.0,
+                    help="offered rate of the second serving run, above the loop's capacity")
+    ap.add_argument("--saturate-seconds", type=float, default=10.0,
+                    help="arrival window of the second serving run")
     ap.add_argument("--no-calib", action="store_true",
                     help="skip the VALU / copy calibration probe (M0) run beside the roofline")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB device-to-device copy first (HBM counter scale)")
+    ap.add_argument("--cpu-oracle-only", type=float, default=None, metavar="SECONDS",
+                    help="time only the CPU oracle (no GPU use) and print its JSON record")
     args = ap.parse_args()
+    if args.cpu_oracle_only is not None:
+        from paper_2204_12201_amd import inputs
+        print(json.dumps(cpu_oracle_rate(inputs, args.cpu_oracle_only)))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported "
               "(the work shards by ciphertext across GPUs; this benchmark runs one)",
@@ -196,7 +215,11 @@ def main():
         tr = TRAFFIC.get(dom)
         traffic = tr["bytes"] if tr and tr["src"] == kernel_source_hash() and same_launch_mix(args) else None
         roofline = {"bound": "alu", "kernel": dom, "achieved": achieved / 1e12, "peak": PEAK_BFLY / 1e12,
-                    "unit": "Tbutterfly/s", "frac": achieved / PEAK_BFLY, "traffic": traffic,
+                    "unit": "Tbutterfly/s", "frac": achieved / PEAK_BFLY,
+                    "peak_basis": "10 multiply-class (half rate) + 8 other 32-bit VALU ops per butterfly "
+                                  "at 78.6 T lane-ops/s",
+                    "peak_impl_model": PEAK_BFLY_IMPL / 1e12, "frac_impl_model": achieved / PEAK_BFLY_IMPL,
+                    "traffic": traffic,
                     "traffic_unit": "bytes per launch",
                     "avg_launch_ms": avg_s * 1e3, "launches": dom_launches,
                     "butterflies_per_launch": per_launch}
@@ -257,8 +280,13 @@ def main():
         out["imputation"] = imputation_leg(fhe, inputs, torch)
         print("[bench] imputation-shaped stages done", file=sys.stderr, flush=True)
     if "serving" in legs:
-        out["serving"] = serving_leg(fhe, inputs, torch, seconds=args.serve_seconds)
+        setup = ServingSetup(fhe, inputs, torch)
+        out["serving"] = serving_leg(fhe, inputs, torch, setup, seconds=args.serve_seconds)
         print("[bench] serving loop done", file=sys.stderr, flush=True)
+        # offered load above capacity: queues build, batches fill
+        out["serving_saturated"] = serving_leg(fhe, inputs, torch, setup, seconds=args.saturate_seconds,
+                                               rate=args.saturate_rate, seed=8)
+        print("[bench] saturated serving loop done", file=sys.stderr, flush=True)
 
     if not args.no_calib:
         cal = calibration()
@@ -426,6 +454,7 @@ def ntt_rows_leg(fhe, inputs, torch, reps=4):
             bytes_s = rows_s * n * 16
             res.append({"n": n, "batch_mib": mib, "rows_per_launch": count * k, "rows_per_s": rows_s,
                         "tbutterfly_per_s": bfly_s / 1e12, "alu_frac": bfly_s / PEAK_BFLY,
+                        "alu_frac_impl_model": bfly_s / PEAK_BFLY_IMPL,
                         "gb_per_s": bytes_s / 1e9, "hbm_frac": bytes_s / HBM_PEAK})
             del polys
     return res
@@ -585,56 +614,80 @@ def imputation_leg(fhe, inputs, torch, reps=3, seed=11, subset=32):
     return res
 
 
-def serving_leg(fhe, inputs, torch, seconds=10.0, rate=200.0, seed=7):
+class ServingSetup:
+    """Contexts, resident keys and request pools of the serving legs: products
+    at n = 8192 (t = 65537); p = 17 bridge conversions at n = 16384; imputation
+    queries: one target's 3 class scores as weighted sums of 24 resident
+    genotype ciphertexts (n = 16384, t = 65537), then 3 class scores at
+    p = 17 (n = 16384, their own key) bridged to 5 bits and reduced to the
+    one-hot argmax."""
+
+    def __init__(self, fhe, inputs, torch, seed=7, pool=64):
+        c8 = inputs.CONFIGS["bfv_n8192"]
+        self.ctx8 = fhe.Context(c8["n"], c8["q"], c8["t"], "slots")
+        km8 = inputs.key_material(c8["n"], c8["q"], seed)
+        _, self.rlk8 = self.ctx8.keygen(km8["s"], km8["pk_a"], km8["pk_e"], km8["rlk_a"], km8["rlk_e"])
+        cb = inputs.CONFIGS["bridge_n16384"]
+        self.nbits = cb["nbits"]
+        self.ctxb = fhe.Context(cb["n"], cb["q"], cb["t"], "coeff")
+        kmb = inputs.key_material(cb["n"], cb["q"], seed)
+        pkb, self.rlkb = self.ctxb.keygen(kmb["s"], kmb["pk_a"], kmb["pk_e"], kmb["rlk_a"], kmb["rlk_e"])
+        self.pool = pool
+        self.a = fhe.from_numpy_u64(inputs.uniform_ciphertexts(c8["n"], c8["q"], pool, seed, "a"), "cuda")
+        self.b = fhe.from_numpy_u64(inputs.uniform_ciphertexts(c8["n"], c8["q"], pool, seed, "b"), "cuda")
+        xs = inputs.bridge_values(cb["t"], pool, seed)
+        pts = np.zeros((pool, cb["n"]), dtype=np.uint64)
+        pts[:, 0] = xs
+        r = inputs.encryption_randomness(cb["n"], pool, seed)
+        self.xb = self.ctxb.encrypt(pkb, pts, r["u"], r["e"])
+        self.ctxi = fhe.Context(cb["n"], cb["q"], 65537, "slots")
+        self.gi = fhe.from_numpy_u64(inputs.uniform_ciphertexts(cb["n"], cb["q"], 24, seed, "g"), "cuda")
+        self.wq = np.random.default_rng(seed + 1).integers(-8, 9, size=(pool, 3, 24)).astype(np.int32)
+        self.ctx2 = fhe.Context(cb["n"], cb["q"], cb["t"], "coeff")
+        km2 = inputs.key_material(cb["n"], cb["q"], seed + 2)
+        pk2, self.rlk2 = self.ctx2.keygen(km2["s"], km2["pk_a"], km2["pk_e"], km2["rlk_a"], km2["rlk_e"])
+        sv = inputs.bridge_values(cb["t"], 3 * pool, seed + 2)
+        pts = np.zeros((3 * pool, cb["n"]), dtype=np.uint64)
+        pts[:, 0] = sv
+        r = inputs.encryption_randomness(cb["n"], 3 * pool, seed + 2)
+        self.sc = self.ctx2.encrypt(pk2, pts, r["u"], r["e"]).view(pool, 3, 2, len(cb["q"]), cb["n"])
+        # warm the lanes (workspaces, kernels)
+        self.ctx8.mul_relin(self.rlk8, self.a[:64], self.b[:64])
+        self.ctxb.bridge_to_bits(self.rlkb, self.xb[:8], self.nbits)
+        self.ctxi.weighted_sum(self.gi, self.wq[:16].reshape(-1, 24))
+        bits = self.ctx2.bridge_to_bits(self.rlk2, self.sc[:4].reshape(12, 2, len(cb["q"]), cb["n"]), self.nbits)
+        self.ctx2.argmax(self.rlk2, bits.view(4, 3, self.nbits, 2, len(cb["q"]), cb["n"]).transpose(0, 1).contiguous())
+        torch.cuda.synchronize()
+
+
+def serving_leg(fhe, inputs, torch, setup, seconds=60.0, rate=200.0, seed=7):
     """Continuous batching (paper_2204_12201_amd/serving.py): Poisson arrivals at
     `rate` requests/s for `seconds`: 50 % products at n = 8192 (t = 65537), 30 %
-    p = 17 bridge conversions at n = 16384, 20 % imputation queries (one
-    target's 3 class scores: weighted sums of 24 resident ciphertexts at
-    n = 16384, t = 65537); keys and genotype ciphertexts resident, 32 GiB
-    in-flight budget.  Throughput and p50/p99 latency from arrival to
-    completion, per kind and overall."""
+    p = 17 bridge conversions at n = 16384, 20 % imputation queries (weighted
+    sums, bridge of the 3 class scores, one-hot argmax); keys and genotype
+    ciphertexts resident, 32 GiB in-flight budget.  Throughput and p50/p99
+    latency from arrival to completion, per kind and overall; the loop runs
+    until every arrived request is done (wall_s includes that drain)."""
     from paper_2204_12201_amd import serving
-    c8 = inputs.CONFIGS["bfv_n8192"]
-    ctx8 = fhe.Context(c8["n"], c8["q"], c8["t"], "slots")
-    km8 = inputs.key_material(c8["n"], c8["q"], seed)
-    _, rlk8 = ctx8.keygen(km8["s"], km8["pk_a"], km8["pk_e"], km8["rlk_a"], km8["rlk_e"])
-    cb = inputs.CONFIGS["bridge_n16384"]
-    ctxb = fhe.Context(cb["n"], cb["q"], cb["t"], "coeff")
-    kmb = inputs.key_material(cb["n"], cb["q"], seed)
-    pkb, rlkb = ctxb.keygen(kmb["s"], kmb["pk_a"], kmb["pk_e"], kmb["rlk_a"], kmb["rlk_e"])
-    pool = 64
-    a = fhe.from_numpy_u64(inputs.uniform_ciphertexts(c8["n"], c8["q"], pool, seed, "a"), "cuda")
-    b = fhe.from_numpy_u64(inputs.uniform_ciphertexts(c8["n"], c8["q"], pool, seed, "b"), "cuda")
-    xs = inputs.bridge_values(cb["t"], pool, seed)
-    pts = np.zeros((pool, cb["n"]), dtype=np.uint64)
-    pts[:, 0] = xs
-    r = inputs.encryption_randomness(cb["n"], pool, seed)
-    xb = ctxb.encrypt(pkb, pts, r["u"], r["e"])
-    ctxi = fhe.Context(cb["n"], cb["q"], 65537, "slots")
-    gi = fhe.from_numpy_u64(inputs.uniform_ciphertexts(cb["n"], cb["q"], 24, seed, "g"), "cuda")
-    wq = np.random.default_rng(seed + 1).integers(-8, 9, size=(pool, 3, 24)).astype(np.int32)
-    # warm the lanes (workspaces, kernels)
-    ctx8.mul_relin(rlk8, a[:64], b[:64])
-    ctxb.bridge_to_bits(rlkb, xb[:8], cb["nbits"])
-    ctxi.weighted_sum(gi, wq[:16].reshape(-1, 24))
-    torch.cuda.synchronize()
+    S = setup
     rng = np.random.default_rng(seed)
     t, reqs, i = 0.0, [], 0
     while True:
         t += rng.exponential(1.0 / rate)
         if t >= seconds:
             break
-        u, j = rng.random(), i % pool
+        u, j = rng.random(), i % S.pool
         if u < 0.5:
-            reqs.append(serving.Request(rid=i, kind="mul_n8192", arrival=t, x=a[j:j + 1], y=b[j:j + 1]))
+            reqs.append(serving.Request(rid=i, kind="mul_n8192", arrival=t, x=S.a[j:j + 1], y=S.b[j:j + 1]))
         elif u < 0.8:
-            reqs.append(serving.Request(rid=i, kind="bridge_n16384", arrival=t, x=xb[j:j + 1]))
+            reqs.append(serving.Request(rid=i, kind="bridge_n16384", arrival=t, x=S.xb[j:j + 1]))
         else:
-            reqs.append(serving.Request(rid=i, kind="impute_n16384", arrival=t, w=wq[j]))
+            reqs.append(serving.Request(rid=i, kind="impute_n16384", arrival=t, w=S.wq[j], s=S.sc[j]))
         i += 1
-    srv = serving.Server([serving.Lane("mul_n8192", ctx8, rlk8, "mul", max_batch=256),
-                          serving.Lane("bridge_n16384", ctxb, rlkb, "bridge", max_batch=32, nbits=cb["nbits"]),
-                          serving.Lane("impute_n16384", ctxi, None, "wsum", max_batch=64, shared=gi, rows=3)],
+    srv = serving.Server([serving.Lane("mul_n8192", S.ctx8, S.rlk8, "mul", max_batch=256),
+                          serving.Lane("bridge_n16384", S.ctxb, S.rlkb, "bridge", max_batch=32, nbits=S.nbits),
+                          serving.Lane("impute_n16384", S.ctxi, None, "impute", max_batch=64, shared=S.gi, rows=3,
+                                       nbits=S.nbits, ctx2=S.ctx2, rlk2=S.rlk2)],
                          budget_bytes=32 << 30)
     t0 = time.perf_counter()
     done = srv.run(reqs)
@@ -680,9 +733,26 @@ def calibration():
     return out
 
 
-def cpu_baseline(inputs):
+def cpu_baseline(inputs, seconds=15.0):
     """The oracle on the host: one bridge chain (4 squarings with relinearization)
-    at n = 16384, eight 55-bit primes, p = 17, repeated for about 15 s."""
+    at n = 16384, eight 55-bit primes, p = 17, repeated for about `seconds`,
+    with every host thread the oracle's OpenMP loops get; then the same in a
+    child process limited to one thread (OMP_NUM_THREADS=1)."""
+    import subprocess
+    res = cpu_oracle_rate(inputs, seconds)
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    try:
+        r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--cpu-oracle-only", str(seconds)],
+                           capture_output=True, text=True, timeout=seconds * 10 + 120, env=env)
+        one = json.loads(r.stdout.strip().splitlines()[-1]) if r.returncode == 0 else None
+    except (subprocess.TimeoutExpired, OSError, ValueError, IndexError):
+        one = None
+    if one:
+        res["one_thread"] = {k: one[k] for k in ("value", "unit", "cores", "sample", "mul_relin_per_s", "seconds")}
+    return res
+
+
+def cpu_oracle_rate(inputs, seconds=15.0):
     from oracle import bfv, clib
     cfg = inputs.CONFIGS["bridge_n16384"]
     n, qs, t = cfg["n"], cfg["q"], cfg["t"]
@@ -696,7 +766,7 @@ def cpu_baseline(inputs):
     done = 0
     t0 = time.perf_counter()
     y = bfv.sub_plain(P, ct, 3)
-    while time.perf_counter() - t0 < 15.0 or done < 2:
+    while time.perf_counter() - t0 < seconds or done < 2:
         y = bfv.mul_relin(P, y, y, rlk)
         done += 1
     el = time.perf_counter() - t0

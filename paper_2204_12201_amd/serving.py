@@ -2,7 +2,9 @@
 
 Requests of several kinds (a ciphertext product at one ring size, a p = 17
 bridge conversion at another, an imputation query: the integer-weighted sums
-of resident encrypted genotypes for one target's classes, ...) arrive over time.  The loop keeps each
+of resident encrypted genotypes for one target's classes, then the bridge of
+that target's class scores to bits and the one-hot argmax over the classes,
+...) arrive over time.  The loop keeps each
 kind's relinearization key resident, queues arrived requests per kind, and
 whenever a kind's stream is idle admits the queued requests of that kind (up to
 its batch cap) as one batch, as long as the device bytes of everything in
@@ -37,7 +39,9 @@ class Request:
     x: object = None               # device [1][2][k][n] (first operand; unused by weighted sums)
     y: object = None               # device [1][2][k][n] second operand (products)
     w: object = None               # host int32 [rows][nin] weights (weighted sums)
-    result: object = None          # device tensor once done
+    s: object = None               # device [rows][2][k][n] class scores at p (imputation queries)
+    result: object = None          # device tensor once done; for imputation queries the
+                                   # pair (weighted sums [rows], one-hot argmax [rows])
     done: float = None             # completion time on the loop's clock
     batch: int = 0                 # size of the batch it ran in
 
@@ -50,16 +54,24 @@ class Request:
 class Lane:
     """One request kind: its context, resident key, stream and batch cap.
     op: "mul" (out = x * y, relinearized), "bridge" (the p-bit conversion
-    of x, nbits bit ciphertexts) or "wsum" (rows of integer weights applied to
-    the lane's resident ciphertexts `shared`, one output per row)."""
+    of x, nbits bit ciphertexts), "wsum" (rows of integer weights applied to
+    the lane's resident ciphertexts `shared`, one output per row) or "impute"
+    (the weighted sums of "wsum", then the request's `rows` class scores at
+    the bridge modulus of `ctx2` converted to nbits bits each and reduced to
+    the one-hot argmax over the rows: the case study's query, its modular
+    stage and its bit-level comparison; BFV has no switch between the two
+    plaintext moduli, so the scores enter the bit-level stage as their own
+    p-ary ciphertexts)."""
     kind: str
     ctx: object
     rlk: object
     op: str
     max_batch: int
     nbits: int = 0
-    shared: object = None          # device [nin][2][k][n] resident inputs (wsum)
-    rows: int = 0                  # weight rows per request (wsum)
+    shared: object = None          # device [nin][2][k][n] resident inputs (wsum, impute)
+    rows: int = 0                  # weight rows per request (wsum, impute)
+    ctx2: object = None            # context of the bit-level stage (impute)
+    rlk2: object = None
     stream: object = None
     queue: collections.deque = field(default_factory=collections.deque)
     inflight: tuple = None         # (requests, event, bytes, buffers)
@@ -70,10 +82,17 @@ class Lane:
         if self.op == "mul":
             ws = fhe.lib().fhe_workspace_bytes(c._h, fhe.OP_MUL_RELIN, count)
             return ws + 3 * count * ct
-        if self.op == "wsum":
+        if self.op in ("wsum", "impute"):
             nin = self.shared.shape[0]
             ws = fhe.lib().fhe_workspace_bytes(c._h, fhe.OP_WEIGHTED_SUM, count * self.rows * nin)
-            return ws + count * self.rows * ct
+            total = ws + count * self.rows * ct
+            if self.op == "impute":
+                c2, m = self.ctx2, count * self.rows
+                ct2 = c2.ct_words * 8
+                total += max(fhe.lib().fhe_workspace_bytes(c2._h, fhe.OP_BRIDGE, m),
+                             fhe.lib().fhe_workspace_bytes(c2._h, fhe.OP_ARGMAX, count))
+                total += m * ct2 * (1 + 2 * self.nbits + 1)  # scores, bits and their class-major copy, argmax
+            return total
         ws = fhe.lib().fhe_workspace_bytes(c._h, fhe.OP_BRIDGE, count)
         return ws + count * ct * (1 + self.nbits)
 
@@ -113,6 +132,15 @@ class Server:
             if ln.op == "wsum":
                 out = ln.ctx.weighted_sum(ln.shared, np.concatenate([r.w for r in reqs]))
                 bufs = (out,)
+            elif ln.op == "impute":
+                sums = ln.ctx.weighted_sum(ln.shared, np.concatenate([r.w for r in reqs]))
+                sc = torch.cat([r.s for r in reqs]) if count > 1 else reqs[0].s  # [count * rows]
+                bits = ln.ctx2.bridge_to_bits(ln.rlk2, sc, ln.nbits)
+                k2, n2 = ln.ctx2.k, ln.ctx2.n
+                cls = bits.view(count, ln.rows, ln.nbits, 2, k2, n2).transpose(0, 1).contiguous()
+                hot = ln.ctx2.argmax(ln.rlk2, cls)  # [rows][count]
+                out = (sums, hot)
+                bufs = (sc, bits, cls, sums, hot)
             elif ln.op == "mul":
                 xs = torch.cat([r.x for r in reqs]) if count > 1 else reqs[0].x
                 ys = torch.cat([r.y for r in reqs]) if count > 1 else reqs[0].y
@@ -124,9 +152,12 @@ class Server:
                 bufs = (xs, out)
             ev = torch.cuda.Event()
             ev.record(ln.stream)
-        per = ln.rows if ln.op == "wsum" else 1
+        per = ln.rows if ln.op in ("wsum", "impute") else 1
         for j, r in enumerate(reqs):
-            r.result = out[j * per:(j + 1) * per]
+            if ln.op == "impute":
+                r.result = (out[0][j * per:(j + 1) * per], out[1][:, j])
+            else:
+                r.result = out[j * per:(j + 1) * per]
             r.batch = count
         ln.inflight = (reqs, ev, nbytes, bufs)
         self.in_flight_bytes += nbytes

@@ -239,39 +239,57 @@ def test_square_chain_graph_replays(dev):
 
 
 def test_serving_results_identical_alone_and_in_mix(dev):
-    """The continuous-batching loop: products at n = 8192 (t = 65537), p = 17
-    bridge conversions at n = 16384 and imputation queries (weighted sums of
-    24 resident ciphertexts at n = 16384) arriving interleaved; every request's
-    result equals the same request computed alone, batches formed, and kinds
-    were in flight together."""
+    """The continuous-batching loop with three kinds arriving interleaved and
+    faster than service: products at n = 8192 (five 43-bit primes, t = 65537),
+    p = 17 bridge conversions, and imputation queries (one target's 3 class
+    scores as weighted sums of 24 resident ciphertexts at t = 65537, then that
+    target's 3 class scores at p = 17 bridged to 5 bits and reduced to the
+    one-hot argmax).  The p = 17 stages run at n = 1024 (eight 55-bit primes)
+    so that the oracle can recompute whole conversions.  Every request's
+    result equals the same request computed alone; sampled requests of every
+    kind equal the oracle word for word; batches formed and kinds were in
+    flight together; the bridged bits and the argmax decrypt to the plain
+    values."""
     import torch
     from paper_2204_12201_amd import serving
     c8 = inputs.CONFIGS["bfv_n8192"]
-    ctx8 = fhe.Context(c8["n"], c8["q"], c8["t"], "slots")
-    km8 = inputs.key_material(c8["n"], c8["q"], 51)
-    _, rlk8 = ctx8.keygen(km8["s"], km8["pk_a"], km8["pk_e"], km8["rlk_a"], km8["rlk_e"])
-    cb = inputs.CONFIGS["bridge_n16384"]
-    ctxb = fhe.Context(cb["n"], cb["q"], cb["t"], "coeff")
-    kmb = inputs.key_material(cb["n"], cb["q"], 52)
-    pkb, rlkb = ctxb.keygen(kmb["s"], kmb["pk_a"], kmb["pk_e"], kmb["rlk_a"], kmb["rlk_e"])
-    nm, nb = 24, 6
-    a = up(inputs.uniform_ciphertexts(c8["n"], c8["q"], nm, 51, "a"))
-    b = up(inputs.uniform_ciphertexts(c8["n"], c8["q"], nm, 51, "b"))
-    xs = inputs.bridge_values(cb["t"], nb, 52)
-    pts = np.zeros((nb, cb["n"]), dtype=np.uint64)
+    P8, km8, pk8, rlk8_o, ctx8, rlk8 = setup(c8["n"], c8["q"], c8["t"], "slots", 51)
+    nb_n, nb_q = 1024, bfv.ntt_primes(1024, 55, 8)
+    Pb, kmb, pkb, rlkb_o, ctxb, rlkb = setup(nb_n, nb_q, 17, "coeff", 52)
+    # imputation: modular stage at t = 65537, bit-level stage at p = 17 (own
+    # contexts: a lane's workspace is its own)
+    Pi = bfv.Params(nb_n, nb_q, 65537, "slots")
+    ctxi = fhe.Context(nb_n, nb_q, 65537, "slots")
+    P2, km2, pk2, rlk2_o, ctx2, rlk2 = setup(nb_n, nb_q, 17, "coeff", 54)
+    nm, nb, ni = 24, 6, 6
+    a_h = inputs.uniform_ciphertexts(c8["n"], c8["q"], nm, 51, "a")
+    b_h = inputs.uniform_ciphertexts(c8["n"], c8["q"], nm, 51, "b")
+    a, b = up(a_h), up(b_h)
+    xs = inputs.bridge_values(17, nb, 52)
+    r = inputs.encryption_randomness(nb_n, nb, 52)
+    pts = np.zeros((nb, nb_n), dtype=np.uint64)
     pts[:, 0] = xs
-    r = inputs.encryption_randomness(cb["n"], nb, 52)
-    xb = ctxb.encrypt(pkb, pts, r["u"], r["e"])
-    ci = inputs.CONFIGS["bridge_n16384"]
-    ctxi = fhe.Context(ci["n"], ci["q"], 65537, "slots")
-    gi = up(inputs.uniform_ciphertexts(ci["n"], ci["q"], 24, 53, "g"))
+    xb_h = np.stack([bfv.encrypt(Pb, pkb, pts[j], r["u"][j], r["e"][j]) for j in range(nb)])
+    xb = up(xb_h)
+    g_h = inputs.uniform_ciphertexts(nb_n, nb_q, 24, 53, "g")
+    gi = up(g_h)
     wrng = np.random.default_rng(53)
-    ni = 6
+    W = [wrng.integers(-8, 9, size=(3, 24)).astype(np.int32) for _ in range(ni)]
+    sv = inputs.bridge_values(17, 3 * ni, 55).reshape(ni, 3)
+    sv[0] = [9, 9, 4]  # a tie at the top (ties go to the lower class)
+    r2 = inputs.encryption_randomness(nb_n, 3 * ni, 55)
+    sc_h = []
+    for q_ in range(ni):
+        for cl in range(3):
+            pt = np.zeros(nb_n, dtype=np.uint64)
+            pt[0] = sv[q_, cl]
+            sc_h.append(bfv.encrypt(P2, pk2, pt, r2["u"][3 * q_ + cl], r2["e"][3 * q_ + cl]))
+    sc_h = np.stack(sc_h).reshape(ni, 3, 2, 8, nb_n)
+    sc = up(sc_h)
     torch.cuda.synchronize()
     reqs = []
     for i in range(ni):
-        reqs.append(serving.Request(rid=200 + i, kind="impute", arrival=0.00015 * i + 0.00002,
-                                    w=wrng.integers(-8, 9, size=(3, 24)).astype(np.int32)))
+        reqs.append(serving.Request(rid=200 + i, kind="impute", arrival=0.00015 * i + 0.00002, w=W[i], s=sc[i]))
     for i in range(nm):
         reqs.append(serving.Request(rid=i, kind="mul", arrival=0.0001 * i, x=a[i:i + 1], y=b[i:i + 1]))
     for i in range(nb):  # arrivals faster than service: later requests queue and batch
@@ -279,27 +297,54 @@ def test_serving_results_identical_alone_and_in_mix(dev):
     reqs.sort(key=lambda q: q.arrival)
     srv = serving.Server([serving.Lane("mul", ctx8, rlk8, "mul", max_batch=64),
                           serving.Lane("bridge", ctxb, rlkb, "bridge", max_batch=8, nbits=5),
-                          serving.Lane("impute", ctxi, None, "wsum", max_batch=16, shared=gi, rows=3)],
+                          serving.Lane("impute", ctxi, None, "impute", max_batch=16, shared=gi, rows=3,
+                                       nbits=5, ctx2=ctx2, rlk2=rlk2)],
                          budget_bytes=32 << 30)
-    say("serving loop: 24 products n=8192 + 6 bridge conversions + 6 imputation queries n=16384")
+    say("serving loop: 24 products n=8192 + 6 bridge conversions + 6 imputation queries (sums, bridge, argmax)")
     done = srv.run(reqs)
     torch.cuda.synchronize()
     assert len(done) == nm + nb + ni
     assert max(q.batch for q in done) > 1
     assert srv.max_concurrent >= 2
-    for q in done:
+    for q in done:  # alone == in the mix
         if q.kind == "mul":
-            alone = ctx8.mul_relin(rlk8, q.x, q.y)
+            assert (down(q.result) == down(ctx8.mul_relin(rlk8, q.x, q.y))).all(), q.rid
         elif q.kind == "impute":
-            alone = ctxi.weighted_sum(gi, q.w)
+            sums = ctxi.weighted_sum(gi, q.w)
+            bits = ctx2.bridge_to_bits(rlk2, q.s, 5)
+            hot = ctx2.argmax(rlk2, bits.view(3, 1, 5, 2, 8, nb_n))
+            assert (down(q.result[0]) == down(sums)).all(), q.rid
+            assert (down(q.result[1]) == down(hot)[:, 0]).all(), q.rid
         else:
-            alone = ctxb.bridge_to_bits(rlkb, q.x, 5)
-        assert (down(q.result) == down(alone)).all(), q.rid
-    dec = ctxb.decrypt(kmb["s"], torch.cat([q.result for q in done if q.kind == "bridge"]).reshape(-1, 2, 8, cb["n"]))
-    got = dec.reshape(nb, 5, cb["n"])[:, :, 0]
+            assert (down(q.result) == down(ctxb.bridge_to_bits(rlkb, q.x, 5))).all(), q.rid
+    # sampled requests of every kind against the oracle
+    by = {q.rid: q for q in done}
+    for i in (0, 11, 23):
+        assert (down(by[i].result)[0] == bfv.mul_relin(P8, a_h[i], b_h[i], rlk8_o)).all(), i
+    for i in (0, nb - 1):
+        want, _ = bfv.bridge_to_bits(Pb, xb_h[i], rlkb_o, 5)
+        assert (down(by[100 + i].result)[0] == want).all(), i
+    for i in (0, 3):
+        q = by[200 + i]
+        assert (down(q.result[0]) == bfv.weighted_sum(Pi, g_h, W[i])).all(), i
+        bits_o = [bfv.bridge_to_bits(P2, sc_h[i, cl], rlk2_o, 5)[0] for cl in range(3)]
+        want = bfv.argmax(P2, rlk2_o, [list(bo) for bo in bits_o])
+        hot = down(q.result[1])
+        for cl in range(3):
+            assert (hot[cl] == want[cl]).all(), (i, cl)
+    # decryptions: bits of x, and the one-hot argmax of the class scores
+    dec = ctxb.decrypt(kmb["s"], torch.cat([q.result for q in done if q.kind == "bridge"]).reshape(-1, 2, 8, nb_n))
+    got = dec.reshape(nb, 5, nb_n)[:, :, 0]
     order = [q.rid - 100 for q in done if q.kind == "bridge"]
     for row, i in zip(got, order):
         assert [int(v) for v in row] == [(int(xs[i]) >> bit) & 1 for bit in range(5)], i
+    for q in done:
+        if q.kind != "impute":
+            continue
+        i = q.rid - 200
+        best = max(range(3), key=lambda cl: (int(sv[i, cl]), -cl))
+        d = ctx2.decrypt(km2["s"], q.result[1].contiguous())
+        assert [int(v) for v in d[:, 0]] == [int(cl == best) for cl in range(3)], i
 
 
 def test_exact_path_boundary_inputs(dev):
