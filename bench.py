@@ -117,8 +117,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip every leg after the headline bridge")
     ap.add_argument("--legs", default="all",
-                    help="comma-separated legs after the headline (powers, plain, autotune, ntt, c0, mixed, chain, "
-                         "imputation, serving) or all")
+                    help="comma-separated legs after the headline (powers, plain, autotune, ntt, mfma, c0, mixed, "
+                         "chain, imputation, serving) or all")
     ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="length of the Poisson arrival window of the serving leg (200 requests/s)")
     ap.add_argument("--saturate-rate", type=float, default=1000.0,
@@ -249,7 +249,7 @@ def main():
     }
 
     legs = set(args.legs.split(",")) if args.legs != "all" else {
-        "powers", "plain", "autotune", "ntt", "c0", "mixed", "chain", "imputation", "serving"}
+        "powers", "plain", "autotune", "ntt", "mfma", "c0", "mixed", "chain", "imputation", "serving"}
     if args.no_plain:
         legs = set()
 
@@ -268,6 +268,9 @@ def main():
         print("[bench] autotune done", file=sys.stderr, flush=True)
     if "ntt" in legs:
         out["ntt_rows"] = ntt_rows_leg(fhe, inputs, torch)
+    if "mfma" in legs:
+        out["mfma_pass0"] = mfma_pass0_leg(fhe, inputs, torch)
+        print("[bench] matrix-core pass comparison done", file=sys.stderr, flush=True)
     if "c0" in legs:
         out["c0_n4096"] = c0_leg(fhe, inputs, torch)
         print("[bench] transform rows and n=4096 products done", file=sys.stderr, flush=True)
@@ -457,6 +460,45 @@ def ntt_rows_leg(fhe, inputs, torch, reps=4):
                         "alu_frac_impl_model": bfly_s / PEAK_BFLY_IMPL,
                         "gb_per_s": bytes_s / 1e9, "hbm_frac": bytes_s / HBM_PEAK})
             del polys
+    return res
+
+
+def mfma_pass0_leg(fhe, inputs, torch, launches=10):
+    """The first radix-16 pass of the forward transform (butterfly levels
+    0..3) at n = 16384 with the eight 55-bit primes, on the vector ALU and as
+    an exact int8 matrix product on the matrix cores (fhe_ntt_pass0; the
+    words are equal): once per launch over 64 MiB of rows (held by the 256 MB
+    last-level cache between launches) and 512 MiB (from and to HBM), and 16
+    times per launch on register-resident data over 512 MiB (the compute rate
+    of the pass with its memory traffic amortised).  Per-launch time from HIP
+    events on the launch stream; butterflies per second count the pass's
+    4 n/2 butterflies per row and pass for both methods."""
+    cfg = inputs.CONFIGS["bridge_n16384"]
+    n, qs = cfg["n"], cfg["q"]
+    k = len(qs)
+    ctx = fhe.Context(n, qs, cfg["t"], cfg["encoding"])
+    res = []
+    for mib, reps in ((64, 1), (512, 1), (512, 16)):
+        count = mib * 131072 // n // k
+        polys = fhe.from_numpy_u64(inputs.uniform_ciphertexts(n, qs, count, 9, "p0")[:, 0], "cuda")
+        row = {"batch_mib": mib, "passes_per_launch": reps, "rows_per_launch": count * k}
+        for name, mfma in (("valu", False), ("mfma", True)):
+            ctx.ntt_pass0(polys, mfma, reps)
+            torch.cuda.synchronize()
+            ctx.reset_kernel_stats()
+            ctx.set_timing(True)
+            for _ in range(launches):
+                ctx.ntt_pass0(polys, mfma, reps)
+            torch.cuda.synchronize()
+            ctx.set_timing(False)
+            ms, nl = ctx.kernel_stats()["pass0_mfma" if mfma else "pass0_valu"]
+            per = ms / nl
+            rows_s = count * k / (per / 1e3)
+            row[name] = {"ms_per_launch": per, "rows_per_s": rows_s,
+                         "tbutterfly_per_s": rows_s * reps * 2 * n / 1e12, "gb_per_s": rows_s * n * 16 / 1e9}
+        row["mfma_over_valu_time"] = row["mfma"]["ms_per_launch"] / row["valu"]["ms_per_launch"]
+        res.append(row)
+        del polys
     return res
 
 

@@ -398,6 +398,23 @@ fhe_status fhe_bits_to_mod(fhe_ctx *ctx, const uint64_t *bits, uint32_t nbits, u
  * Inverse (inverse != 0) undoes it.  Outputs canonical. */
 fhe_status fhe_ntt(fhe_ctx *ctx, int inverse, uint64_t *polys, size_t count, hipStream_t stream);
 
+/* The first radix-16 pass of fhe_ntt's forward transform (butterfly levels
+ * 0..3), alone, in place on `count` polynomials [count][k][n] of canonical
+ * residues: every group of 16 residues a[g + e n/16] (e = 0..15) becomes
+ * y_j = sum_e M_i[j][e] a[g + e n/16] mod q_i at position g + j n/16, with
+ * M_i the 16 x 16 matrix of those four levels of the negacyclic transform
+ * (y_j = sum_e a[g + e n/16] zeta^(e (2 bitrev4(j) + 1)), zeta = psi_i^(n/16));
+ * applied `reps` times (1..1024) on the chip before the store (M_i^reps: the
+ * compute rate of the pass without its memory traffic); outputs canonical.  method 0 computes it with the vector ALU butterflies of
+ * the transforms, method 1 as an exact matrix product on the int8 matrix cores
+ * (7-bit limbs, int32 sums; same words).  A kernel-level comparison of the two
+ * ways to run a transform pass (the transforms of the product pipeline move to
+ * the matrix cores only if they are faster there); n >= 1024, and for method
+ * 1 every q_i < 2^55 (else FHE_EUNSUPPORTED).  The first method-1 call builds
+ * the context's operand tables (16 KiB per prime of q). */
+fhe_status fhe_ntt_pass0(fhe_ctx *ctx, int method, uint32_t reps, uint64_t *polys, size_t count,
+                         hipStream_t stream);
+
 /* ------------------------------------------------------------- timing ---- *
  * When enabled, every kernel launch is bracketed by HIP events on its stream
  * and its duration is accumulated per kernel kind (costs one event pair per

@@ -30,7 +30,7 @@ CFLAGS = [
     "-Wno-unused-result", "-I", INCLUDE, "-I", CSRC,
 ]
 
-SOURCES = ["host.hip", "kernels_conv.hip", "kernels_ntt.hip", "kernels_lin.hip"]
+SOURCES = ["host.hip", "kernels_conv.hip", "kernels_ntt.hip", "kernels_lin.hip", "kernels_mfma.hip"]
 
 
 def _compile(src: str) -> str:

@@ -242,6 +242,9 @@ struct fhe_ctx {
         hipEvent_t done;
     };
     std::vector<ChainGraph> graphs;
+    // operand tables of the matrix-core first transform pass (fhe_ntt_pass0),
+    // built on first use
+    void *d_p0w = nullptr;
     // device address of the static workspace of fhe_mul_relin_static on this
     // context's device (shared by every context on the device)
     void *scratch = nullptr;
@@ -259,7 +262,8 @@ constexpr size_t kMaxGraphs = 16;
 
 const char *kKernelNames[KK_COUNT] = {"lift_q2p",   "square_tensor", "scale_round", "relin_fused",
                                       "ntt_rows",   "elementwise",   "bridge",      "misc",
-                                      "mul_tensor", "fwd_ext",       "tensor_intt"};
+                                      "mul_tensor", "fwd_ext",       "tensor_intt", "pass0_valu",
+                                      "pass0_mfma"};
 
 hipEvent_t take_event(fhe_ctx *c) {
     if (!c->free_events.empty()) {
@@ -441,7 +445,7 @@ void release(fhe_ctx *c) {
     if (c->fork_ev) hipEventDestroy(c->fork_ev);
     if (c->join_ev) hipEventDestroy(c->join_ev);
     if (c->aux) hipStreamDestroy(c->aux);
-    void *ptrs[] = {c->d_pc, c->d_tw, c->d_itw, c->d_cc, c->d_mrc_q, c->d_mrc_p, c->d_counters};
+    void *ptrs[] = {c->d_pc, c->d_tw, c->d_itw, c->d_cc, c->d_mrc_q, c->d_mrc_p, c->d_counters, c->d_p0w};
     for (void *p : ptrs)
         if (p) hipFree(p);
     for (int i = 0; i < KK_COUNT; i++)
@@ -1745,6 +1749,70 @@ fhe_status fhe_ntt(fhe_ctx *c, int inverse, uint64_t *polys, size_t count, hipSt
 }
 
 // ---------------------------------------------------------------- timing ----
+
+// Operand table of the matrix-core first pass, per Q limb l: the pass's
+// 16 x 16 matrix M (the four butterfly levels applied to unit vectors, with
+// the transform's twiddles psi^bitrev(2^u + v)), then the A operands
+// W[h][v][lane][16 bytes] = 7-bit limb v of M[j][e] 2^(7u) 2^64 mod q for
+// j = lane % 16 and byte r: e = 4 (lane / 16) + 2h + r / 8, u = r % 8.
+static fhe_status ensure_pass0_tables(fhe_ctx *c) {
+    if (c->d_p0w) return FHE_OK;
+    const uint32_t k = c->k, n = c->n, L = c->L;
+    std::vector<uint8_t> W((size_t)k * 16 * 64 * 16);
+    for (uint32_t l = 0; l < k; l++) {
+        const uint64_t q = c->primes[l], psi = find_psi(q, n);
+        uint64_t M[16][16];
+        for (int col = 0; col < 16; col++) {
+            uint64_t vec[16] = {};
+            vec[col] = 1;
+            for (int u = 0; u < 4; u++) {
+                const int half = 16 >> (u + 1);
+                for (int v = 0; v < (1 << u); v++) {
+                    const uint64_t w = hpow(psi, bitrev((1u << u) + v, (int)L), q);
+                    for (int wi = 0; wi < half; wi++) {
+                        const int e0 = (v << (4 - u)) | wi;
+                        const uint64_t X = vec[e0], t = hmul(w, vec[e0 + half], q);
+                        vec[e0] = (X + t) % q;
+                        vec[e0 + half] = (X + q - t) % q;
+                    }
+                }
+            }
+            for (int j = 0; j < 16; j++) M[j][col] = vec[j];
+        }
+        const uint64_t r64 = (uint64_t)(((u128)1 << 64) % q);
+        for (int h = 0; h < 2; h++)
+            for (int v = 0; v < 8; v++)
+                for (int lane = 0; lane < 64; lane++)
+                    for (int r = 0; r < 16; r++) {
+                        const int j = lane % 16, e = 4 * (lane / 16) + 2 * h + r / 8, u = r % 8;
+                        const uint64_t val = hmul(hmul(M[j][e], hpow(2, 7 * u, q), q), r64, q);
+                        W[(((size_t)l * 16 + h * 8 + v) * 64 + lane) * 16 + r] = (uint8_t)((val >> (7 * v)) & 127);
+                    }
+    }
+    FHE_HIP(hipSetDevice(c->device));
+    fhe_status st = alloc_copy(&c->d_p0w, W.data(), W.size());
+    if (st != FHE_OK) c->d_p0w = nullptr;
+    return st;
+}
+
+fhe_status fhe_ntt_pass0(fhe_ctx *c, int method, uint32_t reps, uint64_t *polys, size_t count, hipStream_t st) {
+    if (!c) return FHE_EINVAL;
+    if (method != 0 && method != 1) return FHE_EINVAL;
+    if (reps == 0 || reps > 1024) return FHE_EINVAL;
+    if (c->n < 1024) return FHE_EUNSUPPORTED;
+    // 8 limbs of 7 bits hold residues below 2^56; primes below 2^55 keep the
+    // recombined sum below 33 * 2^64 < q 2^64 (one Montgomery reduction)
+    if (method == 1)
+        for (uint32_t i = 0; i < c->k; i++)
+            if (c->primes[i] >= (1ull << 55)) return FHE_EUNSUPPORTED;
+    if (count == 0) return FHE_OK;
+    if (!polys) return FHE_EINVAL;
+    FHE_TRY(check_canonical(c, polys, count * c->k, c->k, 0, st));
+    if (method == 1) FHE_TRY(ensure_pass0_tables(c));
+    return run(c, method ? KK_PASS0_MFMA : KK_PASS0_VALU, st, [&] {
+        return launch_pass0(c->dev, method, c->d_p0w, polys, count * c->k, c->k, 0, (int)reps, st);
+    });
+}
 
 fhe_status fhe_set_timing(fhe_ctx *c, int enable) {
     if (!c) return FHE_EINVAL;

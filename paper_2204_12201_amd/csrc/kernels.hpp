@@ -38,6 +38,8 @@ enum KernelKind {
     KK_MUL_TENSOR,
     KK_FWD_EXT,
     KK_TENSOR_INTT,
+    KK_PASS0_VALU,
+    KK_PASS0_MFMA,
     KK_COUNT
 };
 
@@ -115,6 +117,14 @@ hipError_t launch_horner(const DevCtx &c, const uint64_t *bits, int nbits, uint6
 // flag[0] |= 1 if some word of rows [nrows][n] (limb = row % kmod + off) is >= its prime
 hipError_t launch_validate(const DevCtx &c, const uint64_t *a, size_t nrows, int kmod, int off,
                            unsigned int *flag, hipStream_t s);
+
+// ---- first transform pass on the matrix cores (kernels_mfma.hip) ----
+// Levels 0..3 of the forward transform of rows [nrows][n] (limb = row % kmod +
+// limb_off), applied `reps` times, in place, canonical.  method 0: vector ALU;
+// 1: int8 matrix cores with the per-limb operand table Wt (16 KiB per limb);
+// n >= 1024.
+hipError_t launch_pass0(const DevCtx &c, int method, const void *Wt, uint64_t *data, size_t nrows, int kmod,
+                        int limb_off, int reps, hipStream_t s);
 
 // ---- integer-weighted sums (kernels_lin.hip) ----
 // Row stride (in weights) of the device weight matrix: rows padded with zeros.

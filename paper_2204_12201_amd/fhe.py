@@ -85,6 +85,7 @@ _SIGS = [
     ("fhe_mod_to_int", _I, [_P, _P, _P, _U32, _P, _Z, _P, _Z, _P]),
     ("fhe_bridge_to_bits_powers", _I, [_P, _P, _P, _U32, _P, _Z, _P, _Z, _P]),
     ("fhe_ntt", _I, [_P, _I, _P, _Z, _P]),
+    ("fhe_ntt_pass0", _I, [_P, _I, _U32, _P, _Z, _P]),
     ("fhe_set_timing", _I, [_P, _I]),
     ("fhe_kernel_kinds", _I, []),
     ("fhe_kernel_name", ctypes.c_char_p, [_I]),
@@ -430,6 +431,14 @@ class Context:
         return polys
 
     # ------------------------------------------------------------ timing ---
+    def ntt_pass0(self, polys, mfma: bool, reps: int = 1):
+        """Levels 0..3 of the forward transform, `reps` times, in place
+        ([count][k][n]); mfma: on the int8 matrix cores, else on the vector
+        ALU (same words)."""
+        _check(lib().fhe_ntt_pass0(self._h, 1 if mfma else 0, reps, _dptr(polys), polys.shape[0], _stream()),
+               "fhe_ntt_pass0")
+        return polys
+
     def set_timing(self, on: bool):
         _check(lib().fhe_set_timing(self._h, 1 if on else 0), "fhe_set_timing")
 
