@@ -527,7 +527,10 @@ def mixed_leg(fhe, inputs, torch, reps=3):
     """1024 ciphertext pairs of mixed ring sizes (342 at n=4096 with three 36-bit
     primes, 341 at n=8192 with five 43-bit, 341 at n=16384 with eight 55-bit;
     t = 65537): three per-size calls one after the other against one
-    fhe_mul_relin_multi call whose parts overlap on the device."""
+    fhe_mul_relin_multi call whose parts overlap on the device, with each
+    part's key switching on its own stream and with the key switching of all
+    parts in one persistent launch (a (ciphertext, limb, ring size) work
+    queue); words checked equal between the three."""
     parts = []
     for key, count in (("bfv_n4096", 342), ("bfv_n8192", 341), ("bfv_n16384", 341)):
         cfg = inputs.CONFIGS[key]
@@ -539,23 +542,40 @@ def mixed_leg(fhe, inputs, torch, reps=3):
         b = fhe.from_numpy_u64(inputs.uniform_ciphertexts(n, qs, count, 5, "b"), "cuda")
         parts.append((ctx, rlk, a, b, ctx.empty_ct(count)))
     total = sum(p[2].shape[0] for p in parts)
+    lead = parts[0][0]
     for ctx, rlk, a, b, out in parts:
         ctx.mul_relin(rlk, a, b, out=out)
-    fhe.mul_relin_multi(parts)
     torch.cuda.synchronize()
+    want = [fhe.to_numpy_u64(p[4]) for p in parts]
+    res = {"pairs": {"4096": 342, "8192": 341, "16384": 341}, "t": 65537}
     t0 = time.perf_counter()
     for _ in range(reps):
         for ctx, rlk, a, b, out in parts:
             ctx.mul_relin(rlk, a, b, out=out)
     torch.cuda.synchronize()
-    seq = total * reps / (time.perf_counter() - t0)
+    res["sequential_mul_relin_per_s"] = total * reps / (time.perf_counter() - t0)
+    for name, persistent in (("multi_streams", False), ("multi_persistent", True)):
+        lead.set_multi_persistent(persistent)
+        for p in parts:
+            p[4].zero_()
+        fhe.mul_relin_multi(parts)
+        torch.cuda.synchronize()
+        same = all((fhe.to_numpy_u64(p[4]) == w).all() for p, w in zip(parts, want))
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fhe.mul_relin_multi(parts)
+        torch.cuda.synchronize()
+        res[name + "_mul_relin_per_s"] = total * reps / (time.perf_counter() - t0)
+        res[name + "_words_equal_sequential"] = bool(same)
+    # the autotuner's choice between the two, kept in the leading context
+    res["autotuned_persistent"] = fhe.autotune_mul_relin_multi(parts)
     t0 = time.perf_counter()
     for _ in range(reps):
         fhe.mul_relin_multi(parts)
     torch.cuda.synchronize()
-    multi = total * reps / (time.perf_counter() - t0)
-    return {"pairs": {"4096": 342, "8192": 341, "16384": 341}, "t": 65537,
-            "sequential_mul_relin_per_s": seq, "multi_mul_relin_per_s": multi}
+    res["multi_mul_relin_per_s"] = total * reps / (time.perf_counter() - t0)
+    lead.set_multi_persistent(False)
+    return res
 
 
 def chain_leg(fhe, inputs, torch, count=64, depth=4, reps=3):

@@ -261,6 +261,29 @@ typedef struct {
 } fhe_mul_part;
 fhe_status fhe_mul_relin_multi(const fhe_mul_part *parts, size_t nparts, hipStream_t stream);
 
+/* Key switching of fhe_mul_relin_multi in one persistent launch (same words).
+ * When the call's first context allows it (enable != 0; off by default), at
+ * most 4 parts with products, of at least two of the ring sizes 4096, 8192
+ * and 16384, each fitting one chunk of its context's batch limit and all with
+ * the same key-switching variant (every configured parameter set has it): the
+ * parts run up to the third tensor component on their streams, then `stream`
+ * waits for all of them and one launch of resident workgroups takes
+ * (ciphertext, limb, ring size) tasks from a device counter (one row of
+ * 16384, two of 8192 or four of 4096 per workgroup task, the largest ring
+ * first) until every part is key-switched.  Other calls, or enable == 0,
+ * key-switch each part on its own stream. */
+fhe_status fhe_set_multi_persistent(fhe_ctx *ctx, int enable);
+
+/* Autotuner of fhe_mul_relin_multi's key switching for these parts: where the
+ * persistent launch applies, times the call (synchronously, on `stream`) with
+ * each part key-switched on its own stream and with the persistent launch,
+ * three runs each after a warm-up, and keeps the faster in parts[0].ctx (as
+ * fhe_set_multi_persistent); elsewhere it keeps the per-stream mode.  The
+ * parts' outputs are overwritten (same words either way).  *persistent (may be
+ * NULL) receives the choice. */
+fhe_status fhe_autotune_mul_relin_multi(const fhe_mul_part *parts, size_t nparts, hipStream_t stream,
+                                        int *persistent);
+
 /* Repeated squaring in place: x[j] <- x[j]^(2^depth), i.e. depth calls of
  * fhe_mul_relin(x, x, x) (same words), for j < count.  graph != 0 records the
  * launch sequence once into a HIP graph kept by the context, keyed by

@@ -2,6 +2,7 @@
 // workspace layout and the launch sequences of every entry point.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -245,6 +246,10 @@ struct fhe_ctx {
     // operand tables of the matrix-core first transform pass (fhe_ntt_pass0),
     // built on first use
     void *d_p0w = nullptr;
+    // persistent key switching of fhe_mul_relin_multi when this context leads
+    // the call: mode (1 on where it applies, 0 off) and the queue counter
+    int multi_persistent = 0;
+    void *d_persist = nullptr;
     // device address of the static workspace of fhe_mul_relin_static on this
     // context's device (shared by every context on the device)
     void *scratch = nullptr;
@@ -259,6 +264,8 @@ namespace {
 
 // Most squaring-chain graphs a context keeps (each holds its buffers' addresses).
 constexpr size_t kMaxGraphs = 16;
+// Most parts of one persistent key-switching launch.
+constexpr size_t kMaxPersistParts = kRelinQueueParts;
 
 const char *kKernelNames[KK_COUNT] = {"lift_q2p",   "square_tensor", "scale_round", "relin_fused",
                                       "ntt_rows",   "elementwise",   "bridge",      "misc",
@@ -359,7 +366,7 @@ fhe_status check_canonical(fhe_ctx *c, const uint64_t *a, size_t nrows, int kmod
 // The product pipeline on `count` items with workspace for min(count, limit).
 
 fhe_status mul_relin_impl(fhe_ctx *c, const uint64_t *rlk, const uint64_t *a, const uint64_t *b,
-                          uint64_t *out, size_t count, void *ws, hipStream_t s) {
+                          uint64_t *out, size_t count, void *ws, hipStream_t s, bool relin = true) {
     const bool square = (a == b);
     const int npoly = square ? 2 : 4;
     const size_t n = c->n, K = c->K, k = c->k, ctw = ct_words(c);
@@ -384,9 +391,16 @@ fhe_status mul_relin_impl(fhe_ctx *c, const uint64_t *rlk, const uint64_t *a, co
             FHE_TRY(run(c, KK_TENSOR_INTT, s, [&] { return launch_tensor_intt(d, E, Dt, square, items, s); }));
         }
         FHE_TRY(run(c, KK_SCALE, s, [&] { return launch_scale(d, Dt, oi, C2, items, s); }));
-        FHE_TRY(run(c, KK_RELIN_FUSED, s, [&] { return launch_relin_fused(d, C2, rlk, oi, items, s); }));
+        if (relin)
+            FHE_TRY(run(c, KK_RELIN_FUSED, s, [&] { return launch_relin_fused(d, C2, rlk, oi, items, s); }));
     }
     return FHE_OK;
+}
+
+// Where mul_relin_impl leaves C2 of a batch that fits one chunk.
+uint64_t *c2_of_single_chunk(const fhe_ctx *c, void *ws, size_t count, bool square) {
+    const size_t n = c->n, K = c->K, npoly = square ? 2 : 4;
+    return (uint64_t *)ws + count * npoly * K * n + count * 3 * K * n;
 }
 
 // Products of `count` items from transformed operands (k_lift + k_fwd_ext
@@ -445,7 +459,7 @@ void release(fhe_ctx *c) {
     if (c->fork_ev) hipEventDestroy(c->fork_ev);
     if (c->join_ev) hipEventDestroy(c->join_ev);
     if (c->aux) hipStreamDestroy(c->aux);
-    void *ptrs[] = {c->d_pc, c->d_tw, c->d_itw, c->d_cc, c->d_mrc_q, c->d_mrc_p, c->d_counters, c->d_p0w};
+    void *ptrs[] = {c->d_pc, c->d_tw, c->d_itw, c->d_cc, c->d_mrc_q, c->d_mrc_p, c->d_counters, c->d_p0w, c->d_persist};
     for (void *p : ptrs)
         if (p) hipFree(p);
     for (int i = 0; i < KK_COUNT; i++)
@@ -1195,6 +1209,40 @@ static fhe_status ensure_aux(fhe_ctx *c) {
     return FHE_OK;
 }
 
+// The persistent key switching of fhe_mul_relin_multi takes parts of ring
+// sizes 4096, 8192 and 16384 whose batch fits one chunk (its C2 stays in the
+// part's workspace until the shared launch), at most kMaxPersistParts of
+// them, when the leading context allows it and at least two ring sizes meet.
+static bool persistent_applies(const fhe_mul_part *parts, size_t nparts) {
+    if (!parts[0].ctx->multi_persistent || nparts > kMaxPersistParts) return false;
+    uint32_t sizes = 0;
+    int lazy = -1, raw = -1;
+    for (size_t i = 0; i < nparts; i++) {
+        const fhe_mul_part &p = parts[i];
+        if (p.count == 0) continue;
+        const uint32_t n = p.ctx->n;
+        if ((n != 4096 && n != 8192 && n != 16384) || p.count > p.ctx->batch_limit ||
+            p.count * p.ctx->k >= (1ull << 31))
+            return false;
+        // one key-switching variant per launch
+        const int l = p.ctx->dev.lazy_q ? 1 : 0, r = (p.ctx->dev.lazy_q && p.ctx->dev.digit_raw) ? 1 : 0;
+        if ((lazy >= 0 && l != lazy) || (raw >= 0 && r != raw)) return false;
+        lazy = l;
+        raw = r;
+        sizes |= n;
+    }
+    return (sizes & (sizes - 1)) != 0;
+}
+
+static fhe_status ensure_persist(fhe_ctx *c) {
+    if (c->d_persist) return FHE_OK;
+    if (hipMalloc(&c->d_persist, 256) != hipSuccess) {
+        c->d_persist = nullptr;
+        return FHE_ENOMEM;
+    }
+    return FHE_OK;
+}
+
 static fhe_status mul_args_ok(fhe_ctx *c, const uint64_t *rlk, const uint64_t *a, const uint64_t *b,
                               uint64_t *out, size_t count, void *ws, size_t ws_bytes) {
     if (!c) return FHE_EINVAL;
@@ -1238,7 +1286,10 @@ fhe_status fhe_mul_relin_multi(const fhe_mul_part *parts, size_t nparts, hipStre
         }
         FHE_TRY(ensure_aux(p.ctx));
     }
-    hipEvent_t fork = parts[0].ctx->fork_ev;
+    fhe_ctx *lead = parts[0].ctx;
+    const bool persist = persistent_applies(parts, nparts);
+    if (persist) FHE_TRY(ensure_persist(lead));
+    hipEvent_t fork = lead->fork_ev;
     FHE_HIP(hipEventRecord(fork, st));
     // on an error after some parts were enqueued, `st` still waits for them,
     // so the caller's stream never runs ahead of work on its buffers
@@ -1254,12 +1305,93 @@ fhe_status fhe_mul_relin_multi(const fhe_mul_part *parts, size_t nparts, hipStre
         }
         res = check_canonical(c, p.a, p.count * 2 * c->k, c->k, 0, c->aux);
         if (res == FHE_OK && p.a != p.b) res = check_canonical(c, p.b, p.count * 2 * c->k, c->k, 0, c->aux);
-        if (res == FHE_OK) res = mul_relin_impl(c, p.rlk_dev, p.a, p.b, p.out, p.count, p.ws, c->aux);
+        if (res == FHE_OK) res = mul_relin_impl(c, p.rlk_dev, p.a, p.b, p.out, p.count, p.ws, c->aux, !persist);
         if (hipEventRecord(c->join_ev, c->aux) != hipSuccess && res == FHE_OK) res = FHE_EDEVICE;
     }
     for (size_t i = 0; i < enq && i < nparts; i++)
         if (parts[i].count && hipStreamWaitEvent(st, parts[i].ctx->join_ev, 0) != hipSuccess && res == FHE_OK)
             res = FHE_EDEVICE;
+    if (res != FHE_OK || !persist) return res;
+    // every part's C2 is ready: one persistent key-switching launch over all
+    // of them, largest ring first
+    std::vector<size_t> order;
+    for (size_t i = 0; i < nparts; i++)
+        if (parts[i].count) order.push_back(i);
+    std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return parts[x].ctx->n > parts[y].ctx->n; });
+    RelinQueue Q{};
+    size_t tasks = 0;
+    for (size_t o = 0; o < order.size(); o++) {
+        const fhe_mul_part &p = parts[order[o]];
+        const fhe_ctx *c = p.ctx;
+        const size_t per = 16384 / c->n, rows = p.count * c->k;
+        RelinPart &r = Q.part[o];
+        r.c = c->dev;
+        r.C2 = c2_of_single_chunk(c, p.ws, p.count, p.a == p.b);
+        r.rlk = p.rlk_dev;
+        r.out = p.out;
+        r.items = (uint32_t)p.count;
+        r.wg_tasks = (uint32_t)((rows + per - 1) / per);
+        r.kmagic = (uint32_t)(((1ull << 32) + c->k - 1) / c->k);
+        tasks += r.wg_tasks;
+    }
+    Q.nparts = (int)order.size();
+    unsigned int *queue = (unsigned int *)lead->d_persist;
+    const DevCtx &d0 = parts[order[0]].ctx->dev;
+    const int lazy = d0.lazy_q ? 1 : 0, raw = (d0.lazy_q && d0.digit_raw) ? 1 : 0;
+    return run(lead, KK_RELIN_FUSED, st, [&] { return launch_relin_persist(Q, lazy, raw, queue, tasks, st); });
+}
+
+fhe_status fhe_set_multi_persistent(fhe_ctx *c, int enable) {
+    if (!c) return FHE_EINVAL;
+    c->multi_persistent = enable ? 1 : 0;
+    return FHE_OK;
+}
+
+fhe_status fhe_autotune_mul_relin_multi(const fhe_mul_part *parts, size_t nparts, hipStream_t st,
+                                        int *persistent) {
+    if (nparts == 0 || !parts || !parts[0].ctx) return FHE_EINVAL;
+    fhe_ctx *lead = parts[0].ctx;
+    const int saved = lead->multi_persistent;
+    // time both modes only where the persistent launch applies
+    lead->multi_persistent = 1;
+    const bool applies = persistent_applies(parts, nparts);
+    lead->multi_persistent = saved;
+    if (!applies) {
+        if (persistent) *persistent = 0;
+        lead->multi_persistent = 0;
+        return FHE_OK;
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    FHE_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return FHE_EDEVICE;
+    }
+    float best = -1.0f;
+    int best_mode = 0;
+    fhe_status res = FHE_OK;
+    for (int mode = 0; mode < 2 && res == FHE_OK; mode++) {
+        lead->multi_persistent = mode;
+        res = fhe_mul_relin_multi(parts, nparts, st);  // warm
+        float total = 0.0f;
+        for (int rep = 0; rep < 3 && res == FHE_OK; rep++) {
+            if (hipEventRecord(e0, st) != hipSuccess) res = FHE_EDEVICE;
+            if (res == FHE_OK) res = fhe_mul_relin_multi(parts, nparts, st);
+            if (res == FHE_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+                res = FHE_EDEVICE;
+            float ms = 0.0f;
+            if (res == FHE_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) res = FHE_EDEVICE;
+            total += ms;
+        }
+        if (res == FHE_OK && (best < 0.0f || total < best)) {
+            best = total;
+            best_mode = mode;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    lead->multi_persistent = res == FHE_OK ? best_mode : saved;
+    if (res == FHE_OK && persistent) *persistent = best_mode;
     return res;
 }
 

@@ -74,6 +74,26 @@ hipError_t launch_square_tensor(const DevCtx &c, const uint64_t *a, const uint64
 // Key switching: out[item][l] += sum_i [C2]_{q_i} rlk_i[l] for l = 0, 1.
 hipError_t launch_relin_fused(const DevCtx &c, const uint64_t *C2, const uint64_t *rlk, uint64_t *out,
                               size_t items, hipStream_t s);
+// One part of the persistent key switching over several ring sizes (n = 4096,
+// 8192 or 16384): `items` products of context c; wg_tasks = ceil(items k /
+// (16384 / n)) queue entries; kmagic = ceil(2^32 / k).
+struct RelinPart {
+    DevCtx c;
+    const uint64_t *C2, *rlk;
+    uint64_t *out;
+    uint32_t items, wg_tasks, kmagic;
+};
+constexpr int kRelinQueueParts = 4;
+struct RelinQueue {
+    RelinPart part[kRelinQueueParts];
+    int nparts;
+};
+// The key switching of every part of Q in one launch of persistent
+// workgroups (1024 threads; as many as the chip holds, at most `tasks`, the
+// sum of the parts' wg_tasks) taking tasks from the counter `queue` (cleared
+// on the stream first).  Every part has lazy_q == lazy and digit_raw == raw.
+hipError_t launch_relin_persist(const RelinQueue &Q, int lazy, int raw, unsigned int *queue, size_t tasks,
+                                hipStream_t s);
 
 
 // ---- base conversions and elementwise (kernels_conv.hip) ----

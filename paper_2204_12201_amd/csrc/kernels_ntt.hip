@@ -473,16 +473,16 @@ __global__ __launch_bounds__(Geo<L>::T) void k_mul_tensor_pre2(DevCtx c, const u
 // half of theirs (accumulators below 8q_j).  RAW (with LAZY): every Q prime
 // is below 4 min_j q_j, so a digit word (below q_i) is already a valid lazy
 // transform input modulo q_j and enters without the Shoup reduction by 1.
+// The body for one (item, target limb j), run by Geo<L>::T threads (tid local
+// to them) on their own LDS block of Geo<L>::lds_words words; store = false
+// runs everything but the final read-modify-write of out (a workgroup member
+// without a task of its own that must still take part in the barriers).
 template <int L, bool LAZY, bool RAW>
-__global__ __launch_bounds__(Geo<L>::T) void k_relin_fused(DevCtx c, const uint64_t *__restrict__ C2,
-                                                          const uint64_t *__restrict__ rlk,
-                                                          uint64_t *__restrict__ out) {
-    __shared__ uint64_t lds[Geo<L>::lds_words];
+__device__ __forceinline__ void relin_body(const DevCtx &c, const uint64_t *__restrict__ C2,
+                                           const uint64_t *__restrict__ rlk, uint64_t *__restrict__ out,
+                                           size_t item, int j, uint32_t tid, uint64_t *lds, bool store) {
     constexpr int n = Geo<L>::N;
     constexpr bool PREFETCH = Geo<L>::T >= 64;
-    const uint32_t tid = threadIdx.x;
-    const int j = blockIdx.x;
-    const size_t item = blockIdx.y;
     const int k = c.k;
     const PrimeConst &P = c.pc[j];
     const uint64_t q = P.q, qi = P.qinv_neg, q2 = q << 1, one_p = P.one_p;
@@ -567,6 +567,7 @@ __global__ __launch_bounds__(Geo<L>::T) void k_relin_fused(DevCtx c, const uint6
         }
     }
     ntt_inv_regs2<L, 4, LAZY>(acc0, acc1, lds, tid, c.itw + (size_t)j * n, q);
+    if (!store) return;
     const uint32_t t2 = fresh(tid);
 #pragma unroll
     for (int s = 0; s < 16; s++) {
@@ -578,6 +579,73 @@ __global__ __launch_bounds__(Geo<L>::T) void k_relin_fused(DevCtx c, const uint6
     for (int s = 0; s < 16; s++) {
         const uint32_t idx = natural_index<L>(t3, s);
         o1[idx] = add_mod(canon8(acc1[s], q), o1[idx], q);
+    }
+}
+
+template <int L, bool LAZY, bool RAW>
+__global__ __launch_bounds__(Geo<L>::T) void k_relin_fused(DevCtx c, const uint64_t *__restrict__ C2,
+                                                          const uint64_t *__restrict__ rlk,
+                                                          uint64_t *__restrict__ out) {
+    __shared__ uint64_t lds[Geo<L>::lds_words];
+    relin_body<L, LAZY, RAW>(c, C2, rlk, out, blockIdx.y, (int)blockIdx.x, threadIdx.x, lds, true);
+}
+
+// ---- key switching of several parts (ring sizes) in one persistent launch --
+// Every workgroup (1024 threads, one row of 16384 words of LDS plus padding)
+// takes tasks from a queue until it is empty.  A task is one (item, limb)
+// row of a part at n = 16384, or two (n = 8192) or four (n = 4096)
+// consecutive (item, limb) rows run side by side by 512- or 256-thread
+// sub-groups with their own LDS blocks.  Parts come in the queue in the
+// order given (largest ring first fills the chip with long tasks and leaves
+// the short ones for the end).  The queue is one counter, zero at launch.
+// Every part must have the key-switching variant (LAZY, RAW) of the launch.
+// The row's item and limb come from the task index by the part's
+// multiply-high reciprocal of k (exact for flat < 2^32 / k): an integer
+// division would leave them in vector registers and with them every constant
+// and twiddle address of the row.
+template <int L, bool LAZY, bool RAW>
+__device__ __forceinline__ void relin_persist_task(const RelinPart &P, uint32_t local, uint32_t tid, uint64_t *lds) {
+    constexpr int T = Geo<L>::T, S = 1024 / T;
+    static_assert(T % 64 == 0, "a wave lies inside one sub-group");
+    // the sub-group (and with it the row: item, limb, constants, LDS block)
+    // is the same in a whole wave: scalar values
+    const uint32_t sub = __builtin_amdgcn_readfirstlane(tid / T), lt = tid - sub * T;
+    const uint32_t k = P.c.k;
+    const uint32_t total = P.items * k;
+    uint32_t flat = local * S + sub;
+    const bool active = flat < total;
+    if (!active) flat = 0;  // a valid row to run alongside, nothing stored
+    const uint32_t item = __umulhi(flat, P.kmagic), j = flat - item * k;
+    relin_body<L, LAZY, RAW>(P.c, P.C2, P.rlk, P.out, item, (int)j, lt, lds + (size_t)sub * Geo<L>::lds_words,
+                             active);
+}
+
+// The parts travel as a kernel argument (constant memory the compiler may
+// reload at will, which keeps their fields out of the registers).
+template <bool LAZY, bool RAW>
+__global__ __launch_bounds__(1024) void k_relin_persist(const RelinQueue Q, unsigned int *__restrict__ queue) {
+    // each workgroup leaves the loop once the counter has passed the last
+    // task: every wave reads the same task index, so all of them leave
+    __shared__ uint64_t lds[Geo<14>::lds_words];
+    __shared__ uint32_t task_sh;
+    const uint32_t tid = threadIdx.x;
+    for (;;) {
+        if (tid == 0) task_sh = atomicAdd(&queue[0], 1u);
+        __syncthreads();
+        uint32_t local = __builtin_amdgcn_readfirstlane(task_sh);
+        __syncthreads();
+        int p = 0;
+        while (p < Q.nparts && local >= Q.part[p].wg_tasks) {
+            local -= Q.part[p].wg_tasks;
+            p++;
+        }
+        if (p >= Q.nparts) break;  // the same decision in every wave
+        const RelinPart &P = Q.part[p];
+        switch (P.c.L) {
+            case 12: relin_persist_task<12, LAZY, RAW>(P, local, tid, lds); break;
+            case 13: relin_persist_task<13, LAZY, RAW>(P, local, tid, lds); break;
+            default: relin_persist_task<14, LAZY, RAW>(P, local, tid, lds); break;
+        }
     }
 }
 
@@ -736,4 +804,26 @@ hipError_t launch_relin_fused(const DevCtx &c, const uint64_t *C2, const uint64_
                               size_t items, hipStream_t s) {
     if (items == 0) return hipSuccess;
     FHE_DISPATCH_L(c.L, relin_fused(c, C2, rlk, out, items, s));
+}
+
+hipError_t launch_relin_persist(const RelinQueue &Q, int lazy, int raw, unsigned int *queue, size_t tasks,
+                                hipStream_t s) {
+    if (Q.nparts <= 0 || tasks == 0) return hipSuccess;
+    auto kern = lazy ? (raw ? k_relin_persist<true, true> : k_relin_persist<true, false>)
+                     : k_relin_persist<false, false>;
+    if (!lazy && raw) return hipErrorInvalidValue;
+    static int resident = 0;  // workgroups the chip holds at once (same for every variant)
+    if (resident == 0) {
+        int nb = 0, dev = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, 1024, 0) != hipSuccess ||
+            hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || nb < 1 ||
+            cus < 1)
+            return hipErrorInvalidValue;
+        resident = nb * cus;
+    }
+    const unsigned grid = (unsigned)(tasks < (size_t)resident ? tasks : (size_t)resident);
+    if (hipMemsetAsync(queue, 0, sizeof(unsigned int), s) != hipSuccess) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(1024), 0, s, Q, queue);
+    return hipGetLastError();
 }

@@ -73,6 +73,8 @@ _SIGS = [
     ("fhe_sub_plain_const", _I, [_P, _P, _U64, _P, _Z, _P]),
     ("fhe_mul_relin", _I, [_P, _P, _P, _P, _P, _Z, _P, _Z, _P]),
     ("fhe_mul_relin_multi", _I, [ctypes.POINTER(MulPart), _Z, _P]),
+    ("fhe_set_multi_persistent", _I, [_P, _I]),
+    ("fhe_autotune_mul_relin_multi", _I, [ctypes.POINTER(MulPart), _Z, _P, ctypes.POINTER(ctypes.c_int)]),
     ("fhe_mul_relin_static", _I, [_P, _P, _P, _P, _P, _Z, _P]),
     ("fhe_square_chain", _I, [_P, _P, _P, _U32, _Z, _P, _Z, _I, _P]),
     ("fhe_bridge_to_bits", _I, [_P, _P, _P, _U32, _P, _P, _Z, _P, _Z, _P]),
@@ -309,6 +311,11 @@ class Context:
                "fhe_autotune_mul_relin")
         return chunk.value, bool(fused.value)
 
+    def set_multi_persistent(self, enable: bool):
+        """Key switching of multi-part products led by this context in one
+        persistent launch where it applies (fhe_set_multi_persistent)."""
+        _check(lib().fhe_set_multi_persistent(self._h, 1 if enable else 0), "fhe_set_multi_persistent")
+
     def set_fused_threshold(self, square: bool, min_rows: int):
         _check(lib().fhe_set_fused_threshold(self._h, 1 if square else 0, min_rows), "fhe_set_fused_threshold")
 
@@ -464,12 +471,7 @@ class Context:
         _check(lib().fhe_sync(self._h, _stream()), "fhe_sync")
 
 
-def mul_relin_multi(parts):
-    """parts: list of (Context, rlk, a, b, out) with device tensors; every part
-    gets its own workspace.  One fhe_mul_relin_multi call on the current
-    stream; returns the list of outputs.  The workspaces are released to
-    torch's allocator on return: the current stream waits for every part, and
-    the allocator hands a freed block only to later work on that stream."""
+def _multi_parts(parts):
     import torch
     arr = (MulPart * len(parts))()
     keep = []
@@ -480,5 +482,26 @@ def mul_relin_multi(parts):
         ws = torch.empty(max(need, 8), dtype=torch.uint8, device=ctx.device)
         keep.append(ws)
         arr[i] = MulPart(ctx._h, _dptr(rlk), _dptr(a), _dptr(b), _dptr(out), count, _dptr(ws), ws.numel())
+    return arr, keep
+
+
+def autotune_mul_relin_multi(parts) -> bool:
+    """fhe_autotune_mul_relin_multi on parts as for mul_relin_multi: keeps the
+    faster key-switching mode in the first part's context; returns True for the
+    persistent launch."""
+    arr, keep = _multi_parts(parts)
+    mode = ctypes.c_int(0)
+    _check(lib().fhe_autotune_mul_relin_multi(arr, len(parts), _stream(), ctypes.byref(mode)),
+           "fhe_autotune_mul_relin_multi")
+    return bool(mode.value)
+
+
+def mul_relin_multi(parts):
+    """parts: list of (Context, rlk, a, b, out) with device tensors; every part
+    gets its own workspace.  One fhe_mul_relin_multi call on the current
+    stream; returns the list of outputs.  The workspaces are released to
+    torch's allocator on return: the current stream waits for every part, and
+    the allocator hands a freed block only to later work on that stream."""
+    arr, keep = _multi_parts(parts)
     _check(lib().fhe_mul_relin_multi(arr, len(parts), _stream()), "fhe_mul_relin_multi")
     return [p[4] for p in parts]

@@ -205,6 +205,56 @@ def test_mul_relin_multi_mixed_sizes(dev):
     torch.cuda.synchronize()
 
 
+def test_mul_relin_multi_persistent_key_switching(dev):
+    """Key switching of a multi-part call in one persistent launch: parts of
+    n = 16384, 8192 and 4096 whose (item, limb) rows leave workgroup tasks with
+    idle sub-groups (5 x 3 rows at n = 4096, 3 x 5 at n = 8192), one squaring
+    part; the same words as each part's own call (and the oracle on one product
+    per ring size), on three calls in a row (the queue starts from zero each
+    time) and with the persistent launch switched off."""
+    import torch
+    specs = (("bfv_n16384", 2, 71, False), ("bfv_n8192", 3, 72, False), ("bfv_n4096", 5, 73, False),
+             ("bfv_n4096", 4, 74, True))
+    parts, single, checks = [], [], []
+    for key, count, seed, square in specs:
+        cfg = inputs.CONFIGS[key]
+        n, qs, t = cfg["n"], cfg["q"], cfg["t"]
+        P, km, pk, rlk, ctx, rlk_d = setup(n, qs, t, "slots", seed)
+        a = inputs.uniform_ciphertexts(n, qs, count, seed, "a")
+        b = a if square else inputs.uniform_ciphertexts(n, qs, count, seed, "b")
+        da = up(a)
+        db = da if square else up(b)
+        single.append(down(ctx.mul_relin(rlk_d, da, db)))
+        parts.append((ctx, rlk_d, da, db, ctx.empty_ct(count)))
+        checks.append((P, a[count - 1], b[count - 1], rlk))
+    say("mul_relin_multi with persistent key switching, n=16384/8192/4096/4096(square)")
+    lead = parts[0][0]
+    lead.set_multi_persistent(True)
+    for rep in range(3):
+        for p in parts:
+            p[4].fill_(0)
+        fhe.mul_relin_multi(parts)
+        for i, p in enumerate(parts):
+            assert (down(p[4]) == single[i]).all(), (rep, i)
+    for i, (P, a1, b1, rlk) in enumerate(checks[:3]):
+        assert (single[i][-1] == bfv.mul_relin(P, a1, b1, rlk)).all(), i
+    lead.set_multi_persistent(False)
+    for p in parts:
+        p[4].fill_(0)
+    fhe.mul_relin_multi(parts)
+    for i, p in enumerate(parts):
+        assert (down(p[4]) == single[i]).all(), ("per-stream", i)
+    # the autotuner times both modes and keeps one; the words stay the same
+    fhe.autotune_mul_relin_multi(parts)
+    for p in parts:
+        p[4].fill_(0)
+    fhe.mul_relin_multi(parts)
+    for i, p in enumerate(parts):
+        assert (down(p[4]) == single[i]).all(), ("autotuned", i)
+    lead.set_multi_persistent(False)
+    torch.cuda.synchronize()
+
+
 def test_square_chain_graph_replays(dev):
     """x^(2^3) by the graph-captured squaring chain equals three eager squarings
     (and the oracle on one ciphertext); the graph is replayed three times on
