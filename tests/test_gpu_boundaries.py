@@ -275,3 +275,32 @@ def test_multi_rejects_cross_part_overlaps(dev):
     ctx.sync()
     assert (down(o1) == down(ctx.mul_relin(rlk_d, a[:2], b[:2]))).all()
     assert (down(o2) == down(ctx.mul_relin(rlk_d, a[2:], b[2:]))).all()
+
+
+# The largest bases: k = 16 primes of q (the most the library takes) and k = 8
+# primes of 61 bits (nine auxiliary primes); the generic conversion kernels
+# (16, 20) and (8, 12) run here, and key switching sums 16 digit products
+# unreduced (the most its bound allows).
+@pytest.mark.parametrize("n,bits,k,t,enc", [(256, 55, 16, 65537, "slots"), (16, 30, 16, 17, "coeff"),
+                                            (256, 61, 8, 17, "coeff"), (16384, 55, 16, 65537, "slots")])
+def test_largest_bases_all_words(dev, n, bits, k, t, enc):
+    qs = bfv.ntt_primes(n, bits, k)
+    say(f"largest bases n={n} k={k} {bits}-bit")
+    P, km, pk, rlk, ctx, rlk_d = setup(n, qs, t, enc, 31)
+    assert ctx.aux_primes > 8
+    q = P.q
+    count = 1 if n == 16384 else 3
+    a = inputs.uniform_ciphertexts(n, qs, count, 31, "a")
+    b = inputs.uniform_ciphertexts(n, qs, count, 31, "b")
+    special = [(q - 1) // 2, (q + 1) // 2, (q - 3) // 2]
+    for j, pos in enumerate([0, n // 2, n - 1]):
+        put(P, a[0], 0, pos, special[j])
+        put(P, b[0], 1, pos, special[(j + 1) % 3])
+    before = ctx.fallback_count()
+    out = down(ctx.mul_relin(rlk_d, up(a), up(b)))
+    assert ctx.fallback_count() > before
+    da = up(a)
+    sq = down(ctx.mul_relin(rlk_d, da, da))
+    for j in range(count):
+        assert (out[j] == bfv.mul_relin(P, a[j], b[j], rlk)).all(), ("product", j)
+    assert (sq[0] == bfv.mul_relin(P, a[0], a[0], rlk)).all(), "square"
