@@ -139,6 +139,21 @@ fhe_status fhe_set_batch_limit(fhe_ctx *ctx, size_t max_items);
  * always fused; products default to 128).  Same words either way. */
 fhe_status fhe_set_fused_threshold(fhe_ctx *ctx, int square, size_t min_rows);
 
+/* Where the base conversions of `multiply` (top of this file) run: the
+ * centred lift of the inputs from q to the auxiliary basis P, and the
+ * rounding of t D / q computed in P and brought back to q: method 0 on the
+ * vector ALU (64-bit
+ * multiply-accumulates), method 1 on the int8 matrix cores, as an exact
+ * matrix product of balanced base-256 digits with int32 sums and one
+ * Montgomery reduction per output.  Both give the same words (coefficients
+ * whose floating estimate lies near a rounding boundary take the exact
+ * mixed-radix path either way).  Method 1 needs at most 8 primes in q and in
+ * P and every prime at least 2^20 (else FHE_EUNSUPPORTED); it is the default
+ * where it applies.  Drops the context's squaring-chain graphs. */
+fhe_status fhe_set_conv_method(fhe_ctx *ctx, int method);
+/* The current method of fhe_set_conv_method (0 for a NULL context). */
+int fhe_conv_method(const fhe_ctx *ctx);
+
 /* ---------------------------------------------------------------- keys --- *
  * Key generation from explicit randomness (host arrays):
  *   s      int8[n]          secret key, entries in {-1, 0, 1}

@@ -32,10 +32,16 @@ CFLAGS = [
 
 SOURCES = ["host.hip", "kernels_conv.hip", "kernels_ntt.hip", "kernels_lin.hip", "kernels_mfma.hip"]
 
+# Per-source device flags: the base conversions on the matrix cores keep
+# their int32 sums in ordinary VGPRs (no accumulator-register copies).
+EXTRA = {
+    "kernels_conv.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+}
+
 
 def _compile(src: str) -> str:
     obj = os.path.join(OBJDIR, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *CFLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *CFLAGS, *EXTRA.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr[-6000:]}")

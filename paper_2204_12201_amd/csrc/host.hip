@@ -243,6 +243,9 @@ struct fhe_ctx {
         hipEvent_t done;
     };
     std::vector<ChainGraph> graphs;
+    // operand tables of the base conversions on the matrix cores (bases of at
+    // most 8 primes each side, every prime at least 2^20), or null
+    void *d_mx = nullptr;
     // operand tables of the matrix-core first transform pass (fhe_ntt_pass0),
     // built on first use
     void *d_p0w = nullptr;
@@ -459,7 +462,8 @@ void release(fhe_ctx *c) {
     if (c->fork_ev) hipEventDestroy(c->fork_ev);
     if (c->join_ev) hipEventDestroy(c->join_ev);
     if (c->aux) hipStreamDestroy(c->aux);
-    void *ptrs[] = {c->d_pc, c->d_tw, c->d_itw, c->d_cc, c->d_mrc_q, c->d_mrc_p, c->d_counters, c->d_p0w, c->d_persist};
+    void *ptrs[] = {c->d_pc,       c->d_tw,  c->d_itw, c->d_cc,      c->d_mrc_q, c->d_mrc_p,
+                    c->d_counters, c->d_p0w, c->d_mx,  c->d_persist};
     for (void *p : ptrs)
         if (p) hipFree(p);
     for (int i = 0; i < KK_COUNT; i++)
@@ -528,6 +532,63 @@ const char *fhe_status_str(fhe_status s) {
         case FHE_EWORKSPACE: return "workspace too small";
     }
     return "unknown status";
+}
+
+// Balanced base-256 digits (each in [-128, 127]) of x < 2^63.
+void balanced_digits(uint64_t x, int8_t d[8]) {
+    const uint64_t B = 0x8080808080808080ull;
+    const uint64_t y = (x + B) ^ B;
+    for (int u = 0; u < 8; u++) d[u] = (int8_t)(uint8_t)(y >> (8 * u));
+}
+
+// Operand table of one matrix-core conversion (layout of ConvMx): weights
+// W[t][s] modulo m[t] for targets t < nt and sources s < ns (zero elsewhere).
+void mx_table(int32_t (*tab)[64][4], const uint64_t (*W)[FHE_MX_MAXB], const uint64_t *m, int nt, int ns) {
+    for (int mm = 0; mm < 4; mm++)
+        for (int lane = 0; lane < 64; lane++) {
+            const int row = lane % 16, t = 4 * (mm / 2) + row / 4, v = 4 * (mm % 2) + row % 4, g = lane / 16;
+            uint8_t bytes[16];
+            for (int b = 0; b < 16; b++) {
+                const int src = g + 4 * (b / 8), u = b % 8;
+                int8_t val = 0;
+                if (t < nt && src < ns) {
+                    int8_t d[8];
+                    balanced_digits(hmul(W[t][src], (1ull << (8 * u)) % m[t], m[t]), d);
+                    val = d[v];
+                }
+                bytes[b] = (uint8_t)val;
+            }
+            std::memcpy(tab[mm][lane], bytes, 16);
+        }
+}
+
+// The tables of the matrix-core conversions from those of the vector ALU ones.
+void build_conv_mx(const ConvConst &cc, ConvMx &mx) {
+    const int k = (int)cc.k, kp = (int)cc.kp;
+    const u128 bias = (u128)FHE_MX_BIAS * 0x0101010101010101ull;  // FHE_MX_BIAS sum_v 256^v
+    auto neg_bias = [&](uint64_t m) { return (m - (uint64_t)(bias % m)) % m; };
+    uint64_t W[FHE_MX_MAXB][FHE_MX_MAXB] = {};
+    for (int j = 0; j < kp; j++)
+        for (int i = 0; i < k; i++) W[j][i] = cc.lift_m[j][i];
+    mx_table(mx.a_lift, W, cc.p, kp, k);
+    for (int j = 0; j < kp; j++)
+        for (int i = 0; i < k; i++) W[j][i] = hmul(cc.scale_m[j][i], cc.phinv[j], cc.p[j]);
+    mx_table(mx.a_scale, W, cc.p, kp, k);
+    for (int i = 0; i < k; i++)
+        for (int j = 0; j < kp; j++) W[i][j] = cc.p2q_m[i][j];
+    mx_table(mx.a_p2q, W, cc.q, k, kp);
+    for (int j = 0; j < kp; j++) {
+        const uint64_t pj = cc.p[j];
+        mx.e_lift[j] = neg_bias(pj);
+        mx.e_scale[j] = (hmul(cc.scale_m[j][k + 2], cc.phinv[j], pj) + neg_bias(pj)) % pj;
+        mx.s_dp[j] = hmul(cc.scale_m[j][k], cc.phinv[j], pj);
+        mx.s_v[j] = hmul(cc.scale_m[j][k + 1], cc.phinv[j], pj);
+        mx.l_beta[j] = cc.lift_m[j][k];
+    }
+    for (int i = 0; i < k; i++) {
+        mx.e_p2q[i] = neg_bias(cc.q[i]);
+        mx.p_beta[i] = cc.p2q_m[i][kp];
+    }
 }
 
 fhe_status fhe_ctx_create(const fhe_params *p, int hip_device, fhe_ctx **out) {
@@ -745,6 +806,17 @@ fhe_status fhe_ctx_create(const fhe_params *p, int hip_device, fhe_ctx **out) {
     if (st == FHE_OK) st = alloc_copy(&c->d_cc, cc, sizeof(ConvConst));
     if (st == FHE_OK) st = alloc_copy(&c->d_mrc_q, mq, sizeof(MrcConst));
     if (st == FHE_OK) st = alloc_copy(&c->d_mrc_p, mp, sizeof(MrcConst));
+    // matrix-core conversions: at most 8 primes each side; primes of at least
+    // 2^20 keep the high word of every reduced sum below 2m - 1
+    bool mx_ok = k <= (uint32_t)FHE_MX_MAXB && c->kp <= (uint32_t)FHE_MX_MAXB;
+    for (uint64_t m : c->primes) mx_ok = mx_ok && m >= (1ull << 20);
+    if (st == FHE_OK && mx_ok) {
+        ConvMx *mx = new ConvMx();
+        std::memset(mx, 0, sizeof(ConvMx));
+        build_conv_mx(*cc, *mx);
+        st = alloc_copy(&c->d_mx, mx, sizeof(ConvMx));
+        delete mx;
+    }
     if (st == FHE_OK) {
         uint64_t zeros[4] = {0, 0, 0, 0};
         st = alloc_copy(&c->d_counters, zeros, sizeof(zeros));
@@ -771,6 +843,7 @@ fhe_status fhe_ctx_create(const fhe_params *p, int hip_device, fhe_ctx **out) {
     d.mrc_q = (const MrcConst *)c->d_mrc_q;
     d.mrc_p = (const MrcConst *)c->d_mrc_p;
     d.fallback = (unsigned long long *)c->d_counters;
+    d.mx = (const ConvMx *)c->d_mx;
     uint64_t qmin = c->primes[0], qmax = c->primes[0];
     for (uint32_t i = 1; i < k; i++) {
         qmin = c->primes[i] < qmin ? c->primes[i] : qmin;
@@ -871,6 +944,16 @@ fhe_status fhe_set_fused_threshold(fhe_ctx *c, int square, size_t min_rows) {
     drop_graphs(c);
     return FHE_OK;
 }
+
+fhe_status fhe_set_conv_method(fhe_ctx *c, int method) {
+    if (!c || (method != 0 && method != 1)) return FHE_EINVAL;
+    if (method == 1 && !c->d_mx) return FHE_EUNSUPPORTED;
+    c->dev.mx = method ? (const ConvMx *)c->d_mx : nullptr;
+    drop_graphs(c);
+    return FHE_OK;
+}
+
+int fhe_conv_method(const fhe_ctx *c) { return c && c->dev.mx ? 1 : 0; }
 
 fhe_status fhe_set_batch_limit(fhe_ctx *c, size_t max_items) {
     if (!c) return FHE_EINVAL;

@@ -23,6 +23,7 @@ struct DevCtx {
     int lazy_all;           // every prime of Q and P below 2^64 / (4 (L + 1)): lazy transforms
     uint64_t lazy_limbs;    // bit l: prime l (Q then P) below 2^64 / (4 (L + 1))
     int digit_raw;          // every Q prime below 4 min(Q): digits enter the lazy transforms as they are
+    const ConvMx *mx;       // matrix-core base conversion tables, or null (vector ALU conversions)
 };
 
 // Kernel kinds (timing and profiling names).

@@ -83,6 +83,28 @@ __device__ __forceinline__ uint64_t mrc_eval(const MrcConst &M, const uint64_t (
 
 // ---------------------------------------------------------------- lift ------
 
+// Exact centred lift of one coefficient (residues x in Q) by mixed-radix
+// conversion; put(j, r) receives r = x~ mod p_j.  Counts the coefficient in
+// the fallback counter.
+template <int MK, int MKP, bool EX, class Put>
+__device__ __forceinline__ void lift_exact(const DevCtx &c, const uint64_t (&x)[MK], Put put) {
+    const int kp = EX ? MKP : c.kp;
+    const ConvConst &cc = *c.cc;
+    atomicAdd(c.fallback, 1ull);
+    const MrcConst &M = *c.mrc_q;
+    uint64_t dg[MK];
+    mrc_digits<MK>(M, x, dg);
+    const bool gt = mrc_gt_half<MK>(M, dg);
+#pragma unroll 1
+    for (int j = 0; j < MKP; j++) {
+        if (j < kp) {
+            uint64_t r = mrc_eval<MK>(M, dg, j);
+            if (gt) r = sub_mod(r, M.M_mod_t[j], cc.p[j]);
+            put(j, r);
+        }
+    }
+}
+
 // Centred lift of one coefficient given by its residues x in Q:
 //   x~ = sum_i y_i qhat_i - beta q,  y_i = [x_i qhat_i^-1]_{q_i},  beta = round(sum_i y_i / q_i),
 // in (-q/2, q/2); put(j, r) receives r = x~ mod p_j for every P prime.
@@ -119,19 +141,7 @@ __device__ __forceinline__ void lift_coef(const DevCtx &c, const uint64_t (&x)[M
             }
         }
     } else {
-        atomicAdd(c.fallback, 1ull);
-        const MrcConst &M = *c.mrc_q;
-        uint64_t dg[MK];
-        mrc_digits<MK>(M, x, dg);
-        const bool gt = mrc_gt_half<MK>(M, dg);
-#pragma unroll 1
-        for (int j = 0; j < MKP; j++) {
-            if (j < kp) {
-                uint64_t r = mrc_eval<MK>(M, dg, j);
-                if (gt) r = sub_mod(r, M.M_mod_t[j], cc.p[j]);
-                put(j, r);
-            }
-        }
+        lift_exact<MK, MKP, EX>(c, x, put);
     }
 }
 
@@ -164,6 +174,48 @@ __global__ __launch_bounds__(256) void k_lift(DevCtx c, const uint64_t *__restri
 // Step 1 (in P):   C_{p_j} = [t q^-1 D_{p_j} + h q^-1 + v - sum_i y_i q_i^-1]_{p_j},
 //                  y_i = [(t D_{q_i} + h) qhat_i^-1]_{q_i}, v = floor(sum_i y_i / q_i).
 // Step 2 (P -> Q): centred conversion of C, which satisfies |C| < P/2.
+
+// Exact scale-and-round of one coefficient: Y = t D + h; [Y]_q by Garner over
+// Q; C_p = (Y_p - [Y]_q) q^-1; then the centred value of C by Garner over P.
+// Counts the coefficient in the fallback counter.
+template <int MK, int MKP, bool EX, class Put>
+__device__ __forceinline__ void scale_exact(const DevCtx &c, const uint64_t (&dq)[MK], const uint64_t (&dp)[MKP],
+                                            Put put) {
+    const int k = EX ? MK : c.k, kp = EX ? MKP : c.kp;
+    const ConvConst &cc = *c.cc;
+    atomicAdd(c.fallback, 1ull);
+    const MrcConst &MQ = *c.mrc_q;
+    const MrcConst &MP = *c.mrc_p;
+    uint64_t yq[MK], dgq[MK];
+#pragma unroll
+    for (int i = 0; i < MK; i++) {
+        yq[i] = 0;
+        if (i < k) yq[i] = add_mod(mul_shoup(dq[i], cc.t_q[i], cc.t_qs[i], cc.q[i]), cc.h_q[i], cc.q[i]);
+    }
+    mrc_digits<MK>(MQ, yq, dgq);
+    uint64_t cp[MKP], dgp[MKP];
+#pragma unroll 1
+    for (int j = 0; j < MKP; j++) {
+        cp[j] = 0;
+        if (j < kp) {
+            const uint64_t pj = cc.p[j];
+            const uint64_t ypj = add_mod(mul_shoup(dp[j], cc.t_p[j], cc.t_ps[j], pj), cc.h_p[j], pj);
+            const uint64_t xpj = mrc_eval<MK>(MQ, dgq, j);
+            cp[j] = mul_shoup(sub_mod(ypj, xpj, pj), cc.qinv_p[j], cc.qinv_ps[j], pj);
+        }
+    }
+    mrc_digits<MKP>(MP, cp, dgp);
+    const bool gt = mrc_gt_half<MKP>(MP, dgp);
+#pragma unroll 1
+    for (int i = 0; i < MK; i++) {
+        if (i < k) {
+            uint64_t r = mrc_eval<MKP>(MP, dgp, i);
+            if (gt) r = sub_mod(r, MP.M_mod_t[i], cc.q[i]);
+            put(i, r);
+        }
+    }
+}
+
 // One coefficient of round(t D / q): D given by its residues dq in Q and dp
 // in P (canonical); put(i, r) receives r = C mod q_i.
 template <int MK, int MKP, bool EX, class Put>
@@ -227,41 +279,8 @@ __device__ __forceinline__ void scale_coef(const DevCtx &c, const uint64_t (&dq)
         }
         return;
     }
-    // Exact path: Y = t D + h; [Y]_q by Garner over Q; C_p = (Y_p - [Y]_q) q^-1;
-    // then the centred value of C by Garner over P.
-    atomicAdd(c.fallback, 1ull);
-    const MrcConst &MQ = *c.mrc_q;
-    const MrcConst &MP = *c.mrc_p;
-    uint64_t yq[MK], dgq[MK];
-#pragma unroll
-    for (int i = 0; i < MK; i++) {
-        yq[i] = 0;
-        if (i < k) yq[i] = add_mod(mul_shoup(dq[i], cc.t_q[i], cc.t_qs[i], cc.q[i]), cc.h_q[i], cc.q[i]);
-    }
-    mrc_digits<MK>(MQ, yq, dgq);
-    uint64_t cp[MKP], dgp[MKP];
-#pragma unroll 1
-    for (int j = 0; j < MKP; j++) {
-        cp[j] = 0;
-        if (j < kp) {
-            const uint64_t pj = cc.p[j];
-            const uint64_t ypj = add_mod(mul_shoup(dp[j], cc.t_p[j], cc.t_ps[j], pj), cc.h_p[j], pj);
-            const uint64_t xpj = mrc_eval<MK>(MQ, dgq, j);
-            cp[j] = mul_shoup(sub_mod(ypj, xpj, pj), cc.qinv_p[j], cc.qinv_ps[j], pj);
-        }
-    }
-    mrc_digits<MKP>(MP, cp, dgp);
-    const bool gt = mrc_gt_half<MKP>(MP, dgp);
-#pragma unroll 1
-    for (int i = 0; i < MK; i++) {
-        if (i < k) {
-            uint64_t r = mrc_eval<MKP>(MP, dgp, i);
-            if (gt) r = sub_mod(r, MP.M_mod_t[i], cc.q[i]);
-            put(i, r);
-        }
-    }
+    scale_exact<MK, MKP, EX>(c, dq, dp, put);
 }
-
 
 // Component comp0 + blockIdx.y of item blockIdx.z: components 0 and 1 go to
 // out (a ciphertext), component 2 to C2.
@@ -595,6 +614,516 @@ __global__ void k_validate(DevCtx c, const uint64_t *__restrict__ a, size_t word
     }
 }
 
+// ------------------------------------------ conversions on the matrix cores --
+//
+// The base conversions of the lift and of the scale-and-round are dense
+// contractions (coefficients x sources against a sources x targets matrix of
+// constants), so for bases of at most 8 primes on each side they run on the
+// int8 matrix cores, exactly, with the operand tables of ConvMx.  Per tile of
+// 16 coefficients and per conversion: four v_mfma_i32_16x16x64_i8 give every
+// target's eight partial sums; each lane recombines the sums of its two
+// targets, adds the conversion's extra terms and reduces once (Montgomery).
+// The floating estimates are summed over the four lanes of a column.  A
+// coefficient whose estimate falls within FHE_EST_MARGIN of a decision
+// boundary is queued in LDS and converted exactly (mixed radix) by one thread
+// after the tiles; every output word is therefore the exact one, as on the
+// vector ALU path.  The operand tables and the constants of every slot (prime
+// s of the source and target bases) are staged in LDS and read per tile,
+// which keeps the register count of a wave low.
+
+typedef int mx_v4i __attribute__((ext_vector_type(4)));
+
+// Coefficients per workgroup (four waves, tiles of 16).
+constexpr int kMxSpan = 1024;
+
+// Balanced base-256 digits of x < 2^63 as eight signed bytes: the bytes of
+// x + B (B = 0x80 in every byte) are d_u + 128, and xor 0x80 turns each into
+// d_u in two's complement.
+__device__ __forceinline__ uint64_t mx_digits(uint64_t x) {
+    constexpr uint64_t B = 0x8080808080808080ull;
+    return (x + B) ^ B;
+}
+
+// B operand of a lane: the digits of its two sources (bytes 0..7, 8..15).
+__device__ __forceinline__ mx_v4i mx_operand(uint64_t x0, uint64_t x1) {
+    const uint64_t a = mx_digits(x0), b = mx_digits(x1);
+    return mx_v4i{(int)(uint32_t)a, (int)(uint32_t)(a >> 32), (int)(uint32_t)b, (int)(uint32_t)(b >> 32)};
+}
+
+// LDS of a workgroup: the operand tables of its conversions, the constants of
+// each slot on the Q side and on the P side, and the exact-path queue
+// (offsets of coefficients within the workgroup's span).
+struct MxShared {
+    mx_v4i a[2][4][64];
+    uint64_t cq[FHE_MX_MAXB][10];
+    uint64_t cp[FHE_MX_MAXB][8];
+    int item[kMxSpan];
+    int count;
+};
+
+// acc[mm] = FHE_MX_BIAS + A[mm] B, mm = 0..3 (A = table `t` of the LDS): lane
+// gets P' of target l/16 (acc[0]: digits 0..3, acc[1]: 4..7) and of target
+// l/16 + 4 (acc[2], acc[3]).
+__device__ __forceinline__ void mx_products(const MxShared &sh, int t, uint32_t lane, const mx_v4i B,
+                                            mx_v4i (&acc)[4]) {
+    const mx_v4i bias = {FHE_MX_BIAS, FHE_MX_BIAS, FHE_MX_BIAS, FHE_MX_BIAS};
+#pragma unroll
+    for (int mm = 0; mm < 4; mm++) acc[mm] = __builtin_amdgcn_mfma_i32_16x16x64_i8(sh.a[t][mm][lane], B, bias, 0, 0, 0);
+}
+
+// hi:lo = sum_v 256^v P'_v with P'_v = a[v] (v < 4), b[v - 4] (v >= 4), each in
+// [0, 2^21]: pairs within 32 bits (< 2^30), then x = a01 + a23 2^16 and
+// w = a45 + a67 2^16 (< 2^47), and the sum x + w 2^32 (< 2^79).
+__device__ __forceinline__ void mx_recombine(const mx_v4i a, const mx_v4i b, uint64_t &lo, uint64_t &hi) {
+    const uint32_t a01 = (uint32_t)a[0] + ((uint32_t)a[1] << 8);
+    const uint32_t a23 = (uint32_t)a[2] + ((uint32_t)a[3] << 8);
+    const uint32_t a45 = (uint32_t)b[0] + ((uint32_t)b[1] << 8);
+    const uint32_t a67 = (uint32_t)b[2] + ((uint32_t)b[3] << 8);
+    const uint64_t x = (uint64_t)a01 + ((uint64_t)a23 << 16);
+    const uint64_t w = (uint64_t)a45 + ((uint64_t)a67 << 16);
+    lo = x + (w << 32);
+    hi = (w >> 32) + (lo < x ? 1u : 0u);
+}
+
+__device__ __forceinline__ void mx_add(uint64_t &lo, uint64_t &hi, uint64_t alo, uint64_t ahi) {
+    lo += alo;
+    hi += ahi + (lo < alo ? 1u : 0u);
+}
+
+// Sum over the four lanes of a column (l, l ^ 16, l ^ 32, l ^ 48); every one
+// of them gets the same value (each addition pairs the same two operands).
+// a16, a32: byte addresses (l ^ 16) 4 and (l ^ 32) 4 of the lane exchange.
+__device__ __forceinline__ double mx_swap(double x, int a) {
+    const int lo = __builtin_amdgcn_ds_bpermute(a, __double2loint(x));
+    const int hi = __builtin_amdgcn_ds_bpermute(a, __double2hiint(x));
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double mx_colsum(double x, int a16, int a32) {
+    x += mx_swap(x, a16);
+    x += mx_swap(x, a32);
+    return x;
+}
+
+// Tiles w, w + 4, ... (< ntiles) of wave w with their inputs loaded one tile
+// ahead: load(R, tile) fills R, body(R, tile) uses it.
+template <class Regs, class Load, class Body>
+__device__ __forceinline__ void mx_tiles1(int wave, int ntiles, Load load, Body body) {
+    Regs r;
+    if (wave < ntiles) load(r, wave);
+    for (int tile = wave; tile < ntiles; tile += 4) {
+        asm volatile("" ::: "memory");  // read the LDS constants per tile
+        const Regs cur = r;
+        if (tile + 4 < ntiles) load(r, tile + 4);
+        body(cur, tile);
+    }
+}
+
+// The same with the inputs loaded two tiles ahead into two register sets.
+template <class Regs, class Load, class Body>
+__device__ __forceinline__ void mx_tiles(int wave, int ntiles, Load load, Body body) {
+    Regs r0, r1;
+    if (wave < ntiles) load(r0, wave);
+    if (wave + 4 < ntiles) load(r1, wave + 4);
+    for (int tile = wave; tile < ntiles; tile += 8) {
+        asm volatile("" ::: "memory");  // read the LDS constants per tile
+        {
+            const Regs cur = r0;
+            if (tile + 8 < ntiles) load(r0, tile + 8);
+            body(cur, tile);
+        }
+        if (tile + 4 < ntiles) {
+            asm volatile("" ::: "memory");
+            const Regs cur = r1;
+            if (tile + 12 < ntiles) load(r1, tile + 12);
+            body(cur, tile + 4);
+        }
+    }
+}
+
+__device__ __forceinline__ double mx_f64(uint64_t bits) { return __longlong_as_double((long long)bits); }
+
+// Table t of the LDS := operand table `src` (256 entries of 16 bytes; one per thread).
+__device__ __forceinline__ void mx_stage_table(MxShared &sh, int t, const int32_t (*src)[64][4]) {
+    const int e = (int)threadIdx.x;
+    sh.a[t][e >> 6][e & 63] = reinterpret_cast<const mx_v4i *>(&src[0][0][0])[e];
+}
+
+// Scale slot constants.  Q side of slot s: q, -q^-1 mod 2^64, [t qhat^-1]
+// (Shoup pair), [h qhat^-1], [-P] 2^64, bias removal, 1/q; P side: p,
+// -p^-1 mod 2^64, the D_p and v multipliers, bias removal plus constant, 1/p.
+// Absent primes: zeros.
+__device__ __forceinline__ void mx_stage_scale_slots(MxShared &sh, const DevCtx &c) {
+    const ConvConst &cc = *c.cc;
+    const ConvMx &mx = *c.mx;
+    const int t = (int)threadIdx.x;
+    if (t < FHE_MX_MAXB) {
+        uint64_t *w = sh.cq[t];
+        const bool ok = t < c.k;
+        w[0] = ok ? cc.q[t] : 0;
+        w[1] = ok ? cc.q_qinv[t] : 0;
+        w[2] = ok ? cc.tqhinv[t] : 0;
+        w[3] = ok ? cc.tqhinv_p[t] : 0;
+        w[4] = ok ? cc.hqhinv[t] : 0;
+        w[5] = ok ? mx.p_beta[t] : 0;
+        w[6] = ok ? mx.e_p2q[t] : 0;
+        w[7] = ok ? (uint64_t)__double_as_longlong(cc.inv_q[t]) : 0;
+    } else if (t < 2 * FHE_MX_MAXB) {
+        const int s = t - FHE_MX_MAXB;
+        uint64_t *w = sh.cp[s];
+        const bool ok = s < c.kp;
+        w[0] = ok ? cc.p[s] : 0;
+        w[1] = ok ? cc.p_qinv[s] : 0;
+        w[2] = ok ? mx.s_dp[s] : 0;
+        w[3] = ok ? mx.s_v[s] : 0;
+        w[4] = ok ? mx.e_scale[s] : 0;
+        w[5] = ok ? (uint64_t)__double_as_longlong(cc.inv_p[s]) : 0;
+    }
+}
+
+// Scale-and-round of one tile column on the matrix cores (tables 0: scale in
+// P, 1: P -> Q).  dq, dp: the lane's two Q and two P residues of D (zero for
+// absent primes); jv[h]: slot g + 4h is a P prime.  Returns false when the
+// coefficient must take the exact path, else the lane's two outputs C mod q_s
+// in out.
+__device__ __forceinline__ bool mx_scale_tile(const MxShared &sh, uint32_t lane, int a16, int a32,
+                                              const uint64_t (&dq)[2], const uint64_t (&dp)[2], const bool (&jv)[2],
+                                              uint64_t (&out)[2]) {
+    const uint32_t g = lane >> 4;
+    uint64_t y[2];
+    double e = 0.0;
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+        const uint64_t *Q = sh.cq[g + 4 * h];
+        y[h] = add_mod(mul_shoup(dq[h], Q[2], Q[3], Q[0]), Q[4], Q[0]);
+        e = fma((double)y[h], mx_f64(Q[7]), e);
+    }
+    e = mx_colsum(e, a16, a32);
+    const double fl = floor(e), d = e - fl;
+    bool exact = (d < FHE_EST_MARGIN) || (d > 1.0 - FHE_EST_MARGIN);
+    const uint64_t v = (uint32_t)fl;  // < k
+    mx_v4i acc[4];
+    mx_products(sh, 0, lane, mx_operand(y[0], y[1]), acc);
+    uint64_t z[2];
+    double e2 = 0.0;
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+        const uint64_t *Pc = sh.cp[g + 4 * h];
+        uint64_t lo, hi, plo, phi;
+        mx_recombine(acc[2 * h], acc[2 * h + 1], lo, hi);
+        mul128(dp[h], Pc[2], plo, phi);
+        mx_add(lo, hi, plo, phi);
+        mx_add(lo, hi, v * Pc[3], 0);
+        mx_add(lo, hi, Pc[4], 0);
+        // z_j = C_{p_j} phat_j^-1 mod p_j (the factor is folded into the table)
+        z[h] = jv[h] ? acc_reduce_mont_small(Acc128{lo, hi}, Pc[0], Pc[1]) : 0;
+        e2 = fma((double)z[h], mx_f64(Pc[5]), e2);
+    }
+    e2 = mx_colsum(e2, a16, a32);
+    const double fl2 = floor(e2), d2 = e2 - fl2;
+    exact = exact || (fabs(d2 - 0.5) < FHE_EST_MARGIN);
+    const uint64_t beta = (uint32_t)fl2 + (d2 > 0.5 ? 1u : 0u);  // <= k'
+    mx_products(sh, 1, lane, mx_operand(z[0], z[1]), acc);
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+        const uint64_t *Q = sh.cq[g + 4 * h];
+        uint64_t lo, hi;
+        mx_recombine(acc[2 * h], acc[2 * h + 1], lo, hi);
+        mx_add(lo, hi, beta * Q[5], 0);
+        mx_add(lo, hi, Q[6], 0);
+        out[h] = acc_reduce_mont_small(Acc128{lo, hi}, Q[0], Q[1]);
+    }
+    return !exact;
+}
+
+// Row offsets (in words) of the lane's two slots: slot s = l/16 + 4h, clamped
+// to the basis (an absent prime reads a present row; its constants are zero,
+// so the words read there do not enter any output).
+__device__ __forceinline__ uint32_t mx_row(int s, int nb, int first, int n) {
+    return (uint32_t)((first + (s < nb ? s : nb - 1)) * n);
+}
+
+// Component comp0 + blockIdx.y of item blockIdx.z, coefficients
+// [blockIdx.x span, (blockIdx.x + 1) span): the outputs of k_scale.
+__global__ __launch_bounds__(256) void k_scale_mx(DevCtx c, const uint64_t *__restrict__ Dt,
+                                                  uint64_t *__restrict__ out, uint64_t *__restrict__ C2, int comp0,
+                                                  int span) {
+    __shared__ MxShared sh;
+    const int n = c.n, k = c.k, kp = c.kp, K = c.K;
+    const int comp = comp0 + (int)blockIdx.y;
+    const size_t item = blockIdx.z;
+    const uint64_t *src = Dt + (item * 3 + comp) * (size_t)K * n;
+    uint64_t *dst = comp < 2 ? out + (item * 2 + comp) * (size_t)k * n : C2 + item * (size_t)k * n;
+    const int base = (int)blockIdx.x * span;
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6, col = lane & 15u, g = lane >> 4;
+    mx_stage_table(sh, 0, c.mx->a_scale);
+    mx_stage_table(sh, 1, c.mx->a_p2q);
+    mx_stage_scale_slots(sh, c);
+    if (threadIdx.x == 0) sh.count = 0;
+    __syncthreads();
+    const int a16 = (int)((lane ^ 16u) << 2), a32 = (int)((lane ^ 32u) << 2);
+    bool iv[2], jv[2];
+    uint32_t rq[2], rp[2];
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+        const int s = (int)g + 4 * h;
+        iv[h] = s < k;
+        jv[h] = s < kp;
+        rq[h] = mx_row(s, k, 0, n);
+        rp[h] = mx_row(s, kp, k, n);
+    }
+    struct Regs {
+        uint64_t q[2], p[2];
+    };
+    auto load = [&](Regs &R, int tile) {
+        const uint64_t *t = src + base + tile * 16 + col;
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            R.q[h] = t[rq[h]];
+            R.p[h] = t[rp[h]];
+        }
+    };
+    auto body = [&](const Regs &R, int tile) {
+        const int coef = base + tile * 16 + (int)col;
+        uint64_t r[2];
+        if (mx_scale_tile(sh, lane, a16, a32, R.q, R.p, jv, r)) {
+#pragma unroll
+            for (int h = 0; h < 2; h++)
+                if (iv[h]) dst[(size_t)(g + 4 * h) * n + coef] = r[h];
+        } else if (g == 0) {
+            sh.item[atomicAdd(&sh.count, 1)] = coef - base;
+        }
+    };
+    mx_tiles<Regs>((int)wave, span / 16, load, body);
+    __syncthreads();
+    const int cnt = sh.count;
+    for (int e = (int)threadIdx.x; e < cnt; e += 256) {
+        const int coef = base + sh.item[e];
+        uint64_t dqa[FHE_MX_MAXB], dpa[FHE_MX_MAXB];
+#pragma unroll
+        for (int i = 0; i < FHE_MX_MAXB; i++) {
+            dqa[i] = i < k ? src[(size_t)i * n + coef] : 0;
+            dpa[i] = i < kp ? src[(size_t)(k + i) * n + coef] : 0;
+        }
+        scale_exact<FHE_MX_MAXB, FHE_MX_MAXB, false>(c, dqa, dpa,
+                                                      [&](int i, uint64_t r) { dst[(size_t)i * n + coef] = r; });
+    }
+}
+
+// D of a bridge chain at one prime m (k_scale_chain): the input's tensor t
+// plus 2 gamma x~ (g1 = [2 gamma]_m 2^64, a Montgomery multiplier) and, in the
+// constant coefficient of component 0 (sq), gamma^2 (g2); canonical.
+__device__ __forceinline__ uint64_t mx_chain_d(uint64_t t, uint64_t xl, uint64_t g1, uint64_t g2, uint64_t m,
+                                               uint64_t mqi, bool sq) {
+    uint64_t v = t + mont_mul_lazy(xl, g1, m, mqi);
+    if (sq) v += g2;
+    return csub(csub(v, m << 1), m);
+}
+
+// k_scale_chain on the matrix cores: component blockIdx.y of chain blockIdx.z.
+__global__ __launch_bounds__(256) void k_scale_chain_mx(DevCtx c, const uint64_t *__restrict__ Dt,
+                                                        const uint64_t *__restrict__ x,
+                                                        const uint64_t *__restrict__ E,
+                                                        const uint64_t *__restrict__ gam,
+                                                        const uint64_t *__restrict__ R, uint64_t *__restrict__ y,
+                                                        int tcount, int span) {
+    __shared__ MxShared sh;
+    const int n = c.n, k = c.k, kp = c.kp, K = c.K;
+    const int comp = (int)blockIdx.y;
+    const size_t chain = blockIdx.z, jin = chain / tcount;
+    const ConvConst &cc = *c.cc;
+    const uint64_t *src = Dt + (jin * 3 + comp) * (size_t)K * n;
+    const uint64_t *xin = x + (jin * 2 + comp) * (size_t)k * n;
+    const uint64_t *xp = E + (jin * 2 + comp) * (size_t)K * n;
+    const uint64_t *gm = gam + chain * 2 * (size_t)K;
+    const uint64_t *rr = R + (jin * 2 + comp) * (size_t)k * n;
+    uint64_t *dst = y + (chain * 2 + comp) * (size_t)k * n;
+    const int base = (int)blockIdx.x * span;
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6, col = lane & 15u, g = lane >> 4;
+    mx_stage_table(sh, 0, c.mx->a_scale);
+    mx_stage_table(sh, 1, c.mx->a_p2q);
+    mx_stage_scale_slots(sh, c);
+    {
+        // the chain's gamma multipliers: Q side words 8, 9, P side words 6, 7
+        const int t = (int)threadIdx.x - 2 * FHE_MX_MAXB;
+        if (t >= 0 && t < FHE_MX_MAXB) {
+            sh.cq[t][8] = t < k ? gm[2 * t] : 0;
+            sh.cq[t][9] = t < k ? gm[2 * t + 1] : 0;
+        } else if (t >= FHE_MX_MAXB && t < 2 * FHE_MX_MAXB) {
+            const int s = t - FHE_MX_MAXB;
+            sh.cp[s][6] = s < kp ? gm[2 * (k + s)] : 0;
+            sh.cp[s][7] = s < kp ? gm[2 * (k + s) + 1] : 0;
+        }
+    }
+    if (threadIdx.x == 0) sh.count = 0;
+    __syncthreads();
+    const int a16 = (int)((lane ^ 16u) << 2), a32 = (int)((lane ^ 32u) << 2);
+    bool iv[2], jv[2];
+    uint32_t rq[2], rp[2];
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+        const int s = (int)g + 4 * h;
+        iv[h] = s < k;
+        jv[h] = s < kp;
+        rq[h] = mx_row(s, k, 0, n);
+        rp[h] = mx_row(s, kp, k, n);
+    }
+    struct Regs {
+        uint64_t t[2], x[2], r[2], tp[2], xp[2];
+    };
+    auto load = [&](Regs &Rg, int tile) {
+        const size_t o = (size_t)(base + tile * 16 + (int)col);
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            Rg.t[h] = src[o + rq[h]];
+            Rg.x[h] = xin[o + rq[h]];
+            Rg.r[h] = rr[o + rq[h]];
+            Rg.tp[h] = src[o + rp[h]];
+            Rg.xp[h] = xp[o + rp[h]];
+        }
+    };
+    auto body = [&](const Regs &Rg, int tile) {
+        const int coef = base + tile * 16 + (int)col;
+        const bool sq = comp == 0 && coef == 0;
+        uint64_t dq[2], dp[2];
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            const uint64_t *Q = sh.cq[g + 4 * h], *Pc = sh.cp[g + 4 * h];
+            dq[h] = mx_chain_d(Rg.t[h], Rg.x[h], Q[8], Q[9], Q[0], Q[1], sq);
+            dp[h] = mx_chain_d(Rg.tp[h], Rg.xp[h], Pc[6], Pc[7], Pc[0], Pc[1], sq);
+        }
+        uint64_t r[2];
+        if (mx_scale_tile(sh, lane, a16, a32, dq, dp, jv, r)) {
+#pragma unroll
+            for (int h = 0; h < 2; h++)
+                if (iv[h]) dst[(size_t)(g + 4 * h) * n + coef] = add_mod(r[h], Rg.r[h], sh.cq[g + 4 * h][0]);
+        } else if (g == 0) {
+            sh.item[atomicAdd(&sh.count, 1)] = coef - base;
+        }
+    };
+    mx_tiles1<Regs>((int)wave, span / 16, load, body);  // five input streams: one tile ahead
+    __syncthreads();
+    const int cnt = sh.count;
+    for (int e = (int)threadIdx.x; e < cnt; e += 256) {
+        const int coef = base + sh.item[e];
+        const bool sq = comp == 0 && coef == 0;
+        uint64_t dqa[FHE_MX_MAXB], dpa[FHE_MX_MAXB];
+#pragma unroll
+        for (int i = 0; i < FHE_MX_MAXB; i++) {
+            dqa[i] = i < k ? mx_chain_d(src[(size_t)i * n + coef], xin[(size_t)i * n + coef], gm[2 * i],
+                                        gm[2 * i + 1], cc.q[i], cc.q_qinv[i], sq)
+                           : 0;
+            dpa[i] = i < kp ? mx_chain_d(src[(size_t)(k + i) * n + coef], xp[(size_t)(k + i) * n + coef],
+                                         gm[2 * (k + i)], gm[2 * (k + i) + 1], cc.p[i], cc.p_qinv[i], sq)
+                            : 0;
+        }
+        scale_exact<FHE_MX_MAXB, FHE_MX_MAXB, false>(c, dqa, dpa, [&](int i, uint64_t r) {
+            dst[(size_t)i * n + coef] = add_mod(r, rr[(size_t)i * n + coef], cc.q[i]);
+        });
+    }
+}
+
+// k_lift on the matrix cores: poly blockIdx.y of item blockIdx.z.  Slot
+// constants: Q side q, [qhat^-1] (Shoup pair), 1/q; P side p, -p^-1 mod 2^64,
+// [-q] 2^64, bias removal.
+__global__ __launch_bounds__(256) void k_lift_mx(DevCtx c, const uint64_t *__restrict__ a,
+                                                 const uint64_t *__restrict__ b, uint64_t *__restrict__ E,
+                                                 int npoly, int span) {
+    __shared__ MxShared sh;
+    const int n = c.n, k = c.k, kp = c.kp, K = c.K;
+    const int poly = (int)blockIdx.y;
+    const size_t item = blockIdx.z;
+    const ConvConst &cc = *c.cc;
+    const ConvMx &mx = *c.mx;
+    const uint64_t *src = poly < 2 ? a + (item * 2 + poly) * (size_t)k * n
+                                   : b + (item * 2 + poly - 2) * (size_t)k * n;
+    uint64_t *dst = E + ((item * npoly + poly) * K + k) * (size_t)n;
+    const int base = (int)blockIdx.x * span;
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6, col = lane & 15u, g = lane >> 4;
+    mx_stage_table(sh, 0, mx.a_lift);
+    {
+        const int t = (int)threadIdx.x;
+        if (t < FHE_MX_MAXB) {
+            const bool ok = t < k;
+            sh.cq[t][0] = ok ? cc.q[t] : 0;
+            sh.cq[t][1] = ok ? cc.qhinv[t] : 0;
+            sh.cq[t][2] = ok ? cc.qhinv_p[t] : 0;
+            sh.cq[t][3] = ok ? (uint64_t)__double_as_longlong(cc.inv_q[t]) : 0;
+        } else if (t < 2 * FHE_MX_MAXB) {
+            const int s = t - FHE_MX_MAXB;
+            const bool ok = s < kp;
+            sh.cp[s][0] = ok ? cc.p[s] : 0;
+            sh.cp[s][1] = ok ? cc.p_qinv[s] : 0;
+            sh.cp[s][2] = ok ? mx.l_beta[s] : 0;
+            sh.cp[s][3] = ok ? mx.e_lift[s] : 0;
+        }
+    }
+    if (threadIdx.x == 0) sh.count = 0;
+    __syncthreads();
+    const int a16 = (int)((lane ^ 16u) << 2), a32 = (int)((lane ^ 32u) << 2);
+    bool jv[2];
+    uint32_t rq[2];
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+        const int s = (int)g + 4 * h;
+        jv[h] = s < kp;
+        rq[h] = mx_row(s, k, 0, n);
+    }
+    struct Regs {
+        uint64_t x[2];
+    };
+    auto load = [&](Regs &R, int tile) {
+        const uint64_t *t = src + base + tile * 16 + col;
+#pragma unroll
+        for (int h = 0; h < 2; h++) R.x[h] = t[rq[h]];
+    };
+    auto body = [&](const Regs &R, int tile) {
+        const int coef = base + tile * 16 + (int)col;
+        uint64_t yv[2];
+        double e = 0.0;
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            const uint64_t *Q = sh.cq[g + 4 * h];
+            yv[h] = mul_shoup(R.x[h], Q[1], Q[2], Q[0]);
+            e = fma((double)yv[h], mx_f64(Q[3]), e);
+        }
+        e = mx_colsum(e, a16, a32);
+        const double fl = floor(e), d = e - fl;
+        const bool exact = fabs(d - 0.5) < FHE_EST_MARGIN;
+        const uint64_t beta = (uint32_t)fl + (d > 0.5 ? 1u : 0u);  // <= k
+        mx_v4i acc[4];
+        mx_products(sh, 0, lane, mx_operand(yv[0], yv[1]), acc);
+        if (!exact) {
+#pragma unroll
+            for (int h = 0; h < 2; h++) {
+                if (jv[h]) {
+                    const uint64_t *Pc = sh.cp[g + 4 * h];
+                    uint64_t lo, hi;
+                    mx_recombine(acc[2 * h], acc[2 * h + 1], lo, hi);
+                    mx_add(lo, hi, beta * Pc[2], 0);
+                    mx_add(lo, hi, Pc[3], 0);
+                    dst[(size_t)(g + 4 * h) * n + coef] = acc_reduce_mont_small(Acc128{lo, hi}, Pc[0], Pc[1]);
+                }
+            }
+        } else if (g == 0) {
+            sh.item[atomicAdd(&sh.count, 1)] = coef - base;
+        }
+    };
+    mx_tiles<Regs>((int)wave, span / 16, load, body);
+    __syncthreads();
+    const int cnt = sh.count;
+    for (int e = (int)threadIdx.x; e < cnt; e += 256) {
+        const int coef = base + sh.item[e];
+        uint64_t xa[FHE_MX_MAXB];
+#pragma unroll
+        for (int i = 0; i < FHE_MX_MAXB; i++) xa[i] = i < k ? src[(size_t)i * n + coef] : 0;
+        lift_exact<FHE_MX_MAXB, FHE_MX_MAXB, false>(c, xa,
+                                                     [&](int j, uint64_t r) { dst[(size_t)j * n + coef] = r; });
+    }
+}
+
+inline int mx_span(int n) { return n < kMxSpan ? n : kMxSpan; }
+
 inline unsigned grid_for(size_t words, unsigned block = 256) {
     size_t g = (words + block - 1) / block;
     if (g > 65536 * 4) g = 65536 * 4;
@@ -660,12 +1189,24 @@ struct ScaleChainL {
 hipError_t launch_lift(const DevCtx &c, const uint64_t *a, const uint64_t *b, uint64_t *E, int npoly,
                        size_t items, hipStream_t s) {
     if (items == 0) return hipSuccess;
+    if (c.mx) {
+        const int span = mx_span(c.n);
+        hipLaunchKernelGGL(k_lift_mx, dim3(c.n / span, npoly, (unsigned)items), dim3(256), 0, s, c, a, b, E, npoly,
+                           span);
+        return hipGetLastError();
+    }
     return by_class<LiftL>(c.k, c.kp, c, a, b, E, npoly, items, s);
 }
 
 hipError_t launch_scale(const DevCtx &c, const uint64_t *Dt, uint64_t *out, uint64_t *C2,
                         size_t items, hipStream_t s, int comp0, int ncomp) {
     if (items == 0) return hipSuccess;
+    if (c.mx) {
+        const int span = mx_span(c.n);
+        hipLaunchKernelGGL(k_scale_mx, dim3(c.n / span, ncomp, (unsigned)items), dim3(256), 0, s, c, Dt, out, C2,
+                           comp0, span);
+        return hipGetLastError();
+    }
     return by_class<ScaleL>(c.k, c.kp, c, Dt, out, C2, items, comp0, ncomp, s);
 }
 
@@ -679,6 +1220,12 @@ hipError_t launch_scale_chain(const DevCtx &c, const uint64_t *Dt, const uint64_
                               const uint64_t *gam, const uint64_t *R, uint64_t *y, size_t chains, int tcount,
                               hipStream_t s) {
     if (chains == 0) return hipSuccess;
+    if (c.mx) {
+        const int span = mx_span(c.n);
+        hipLaunchKernelGGL(k_scale_chain_mx, dim3(c.n / span, 2, (unsigned)chains), dim3(256), 0, s, c, Dt, x, E,
+                           gam, R, y, tcount, span);
+        return hipGetLastError();
+    }
     return by_class<ScaleChainL>(c.k, c.kp, c, Dt, x, E, gam, R, y, chains, tcount, s);
 }
 

@@ -58,6 +58,8 @@ _SIGS = [
     ("fhe_workspace_bytes", _Z, [_P, _I, _Z]),
     ("fhe_set_batch_limit", _I, [_P, _Z]),
     ("fhe_set_fused_threshold", _I, [_P, _I, _Z]),
+    ("fhe_set_conv_method", _I, [_P, _I]),
+    ("fhe_conv_method", _I, [_P]),
     ("fhe_autotune_mul_relin", _I, [_P, _P, _P, _P, _P, _Z, _P, _Z, _P, ctypes.POINTER(_Z),
                                     ctypes.POINTER(ctypes.c_int)]),
     ("fhe_keygen", _I, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _Z, _P]),
@@ -315,6 +317,16 @@ class Context:
         """Key switching of multi-part products led by this context in one
         persistent launch where it applies (fhe_set_multi_persistent)."""
         _check(lib().fhe_set_multi_persistent(self._h, 1 if enable else 0), "fhe_set_multi_persistent")
+
+    def set_conv_method(self, mfma: bool):
+        """Base conversions of the product on the int8 matrix cores (True,
+        the default where the bases allow it) or on the vector ALU (False);
+        same words (fhe_set_conv_method)."""
+        _check(lib().fhe_set_conv_method(self._h, 1 if mfma else 0), "fhe_set_conv_method")
+
+    @property
+    def conv_mfma(self) -> bool:
+        return lib().fhe_conv_method(self._h) == 1
 
     def set_fused_threshold(self, square: bool, min_rows: int):
         _check(lib().fhe_set_fused_threshold(self._h, 1 if square else 0, min_rows), "fhe_set_fused_threshold")

@@ -72,13 +72,17 @@ def put(P, ct, poly, pos, value):
 FULL = [("bfv_n4096", 3), ("bfv_n8192", 5), ("bfv_n16384", 8), ("bridge_n16384", 8)]
 
 
+@pytest.mark.parametrize("mfma", [True, False], ids=["mfma", "valu"])
 @pytest.mark.parametrize("name,k", FULL)
-def test_exact_path_at_configured_sizes(dev, name, k):
+def test_exact_path_at_configured_sizes(dev, name, k, mfma):
+    """mfma: the base conversions on the matrix cores (the default at these
+    sizes), else the exact-size (k, k) vector ALU kernels."""
     cfg = inputs.CONFIGS[name]
     n, qs, t, enc = cfg["n"], cfg["q"], cfg["t"], cfg["encoding"]
-    say(f"exact paths {name}: n={n} k={k} t={t}")
+    say(f"exact paths {name}: n={n} k={k} t={t} mfma={mfma}")
     P, km, pk, rlk, ctx, rlk_d = setup(n, qs, t, enc, 21)
     assert len(qs) == k and ctx.aux_primes == k, "not the exact-size (k, k) instantiation"
+    ctx.set_conv_method(mfma)
     q = P.q
     # -- lift boundary: coefficients around q/2 in both polynomials of both
     #    operands, spread over the row (first, last and interior positions)
@@ -117,7 +121,8 @@ def test_exact_path_at_configured_sizes(dev, name, k):
     assert (out2[0] == bfv.mul_relin(P, A, B, rlk)).all(), "product on the rounding boundary"
 
 
-def test_bridge_exact_paths_at_full_size(dev):
+@pytest.mark.parametrize("mfma", [True, False], ids=["mfma", "valu"])
+def test_bridge_exact_paths_at_full_size(dev, mfma):
     """The bridge at n = 16384, eight 55-bit primes, p = 17, with two crafted
     inputs: (A) chain c* = 5 whose first rounding sits within 2^-200 of a
     half-integer (exact path of the chain-rounding kernel), (B) an input whose
@@ -127,9 +132,10 @@ def test_bridge_exact_paths_at_full_size(dev):
     equals the oracle's sum of the library's eq outputs."""
     cfg = inputs.CONFIGS["bridge_n16384"]
     n, qs, t = cfg["n"], cfg["q"], cfg["t"]
-    say("bridge exact paths n=16384 k=8")
+    say(f"bridge exact paths n=16384 k=8 mfma={mfma}")
     P, km, pk, rlk, ctx, rlk_d = setup(n, qs, t, "coeff", 23)
     assert ctx.aux_primes == 8
+    ctx.set_conv_method(mfma)
     q, D = P.q, P.delta
     cs, cb = 5, 11
     # (A) y = x - Delta c*, centred lift y~ = isqrt((2m+1) q / (2t)), m = 3:
