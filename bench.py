@@ -14,7 +14,8 @@ requested): 12,544 ciphertext squarings executed per step instead of 17,408.  In
 Prints one JSON line with the metric (bridge conversions per second), the
 executed ciphertext mul+relin per second, per-step p50/p99, the plain-vs-batched mul+relin
 comparison at n = 16384 (one pair per call vs one batched call, for several
-batch sizes), the transform kernel alone at n = 4096 / 8192 / 16384, products
+batch sizes), the headline step with the base conversions on the matrix cores and on the
+vector ALU, the transform kernel alone at n = 4096 / 8192 / 16384, products
 at n = 4096, 1024 products of mixed ring sizes (per-size calls vs one
 multi-context call), depth-4 squaring chains (eager vs HIP graph), the
 continuous-batching serving loop (Poisson arrivals, p50/p99), the roofline of the dominant kernel (timed live with HIP events on
@@ -117,8 +118,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip every leg after the headline bridge")
     ap.add_argument("--legs", default="all",
-                    help="comma-separated legs after the headline (powers, plain, autotune, ntt, mfma, c0, mixed, "
-                         "chain, imputation, serving) or all")
+                    help="comma-separated legs after the headline (conv, powers, plain, autotune, ntt, mfma, c0, "
+                         "mixed, chain, imputation, serving) or all")
     ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="length of the Poisson arrival window of the serving leg (200 requests/s)")
     ap.add_argument("--saturate-rate", type=float, default=1000.0,
@@ -129,6 +130,8 @@ def main():
                     help="skip the VALU / copy calibration probe (M0) run beside the roofline")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB device-to-device copy first (HBM counter scale)")
+    ap.add_argument("--conv", choices=("mfma", "valu"), default="mfma",
+                    help="engine of the base conversions in the headline run (the library's default is mfma)")
     ap.add_argument("--cpu-oracle-only", type=float, default=None, metavar="SECONDS",
                     help="time only the CPU oracle (no GPU use) and print its JSON record")
     args = ap.parse_args()
@@ -157,6 +160,7 @@ def main():
     n, qs, t, nbits = cfg["n"], cfg["q"], cfg["t"], cfg["nbits"]
     count = args.inputs
     ctx = fhe.Context(n, qs, t, "coeff")
+    ctx.set_conv_method(args.conv == "mfma")
     km = inputs.key_material(n, qs, 0)
     pk, rlk = ctx.keygen(km["s"], km["pk_a"], km["pk_e"], km["rlk_a"], km["rlk_e"])
     xs = inputs.bridge_values(t, count, 0)
@@ -240,6 +244,7 @@ def main():
         "config": {"workload": "bridge_p17_n16384_k8x55bit_256inputs", "n": n, "k": len(qs),
                    "q_bits": sum(int(q).bit_length() for q in qs), "p": t, "inputs": count,
                    "mul_relin_per_step": mul_per_step, "aux_primes": ctx.aux_primes,
+                   "conversions_engine": args.conv,
                    "parallelism": "single-gpu"},
         "executed_mul_relin_per_s": mul_per_step * args.steps / elapsed,
         "step_p50_ms": percentile(step_ms, 50),
@@ -249,10 +254,14 @@ def main():
     }
 
     legs = set(args.legs.split(",")) if args.legs != "all" else {
-        "powers", "plain", "autotune", "ntt", "mfma", "c0", "mixed", "chain", "imputation", "serving"}
+        "conv", "powers", "plain", "autotune", "ntt", "mfma", "c0", "mixed", "chain", "imputation", "serving"}
     if args.no_plain:
         legs = set()
 
+    if "conv" in legs:
+        out["conv_engines"] = conv_engine_leg(ctx, rlk, x_ct, nbits, torch)
+        ctx.set_conv_method(args.conv == "mfma")
+        print("[bench] conversion engines done", file=sys.stderr, flush=True)
     # the same bits from the powers of x (another circuit: t - 2 products per
     # input), on the same inputs and key; reported beside the headline
     if "powers" in legs:
@@ -420,6 +429,40 @@ def power_basis_leg(ctx, rlk, x_ct, xs, km, nbits, steps, torch):
     want = (xs[:, None].astype(np.int64) >> np.arange(nbits)) & 1
     return {"conversions_per_s": count * steps / el, "ms_per_step": el * 1e3 / steps,
             "mul_relin_per_conversion": t - 2, "decrypts_to_bits": bool((pdec.astype(np.int64) == want).all())}
+
+
+def conv_engine_leg(ctx, rlk, x_ct, nbits, torch, steps=2, rounds=2):
+    """The headline step with the base conversions (lift, scale-and-round, the
+    chains' first rounding) on the matrix cores and on the vector ALU, the two
+    engines alternating over `rounds` rounds of `steps` steps: rate, kernel
+    time per step by kind, and whether the bits are the same words."""
+    el = {True: 0.0, False: 0.0}
+    ms = {True: {}, False: {}}
+    bits = {}
+    for _ in range(rounds):
+        for mfma in (True, False):
+            ctx.set_conv_method(mfma)
+            bits[mfma] = ctx.bridge_to_bits(rlk, x_ct, nbits)  # warm-up, kept for the comparison
+            torch.cuda.synchronize()
+            ctx.reset_kernel_stats()
+            ctx.set_timing(True)
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                ctx.bridge_to_bits(rlk, x_ct, nbits)
+            torch.cuda.synchronize()
+            el[mfma] += time.perf_counter() - t0
+            ctx.set_timing(False)
+            for kind, (t, cnt) in ctx.kernel_stats().items():
+                if cnt:
+                    ms[mfma][kind] = ms[mfma].get(kind, 0.0) + t
+    ctx.set_conv_method(True)
+    res = {}
+    for mfma in (True, False):
+        res["mfma" if mfma else "valu"] = {
+            "conversions_per_s": x_ct.shape[0] * steps * rounds / el[mfma],
+            "kernel_ms_per_step": {kind: round(t / (steps * rounds), 3) for kind, t in ms[mfma].items()}}
+    res["words_equal"] = bool(torch.equal(bits[True], bits[False]))
+    return res
 
 
 def ntt_rows_leg(fhe, inputs, torch, reps=4):
