@@ -574,6 +574,9 @@ void build_conv_mx(const ConvConst &cc, ConvMx &mx) {
     for (int j = 0; j < kp; j++)
         for (int i = 0; i < k; i++) W[j][i] = hmul(cc.scale_m[j][i], cc.phinv[j], cc.p[j]);
     mx_table(mx.a_scale, W, cc.p, kp, k);
+    std::memset(W, 0, sizeof(W));
+    for (int j = 0; j < kp; j++) W[j][j] = hmul(cc.scale_m[j][k], cc.phinv[j], cc.p[j]);
+    mx_table(mx.a_sdp, W, cc.p, kp, kp);
     for (int i = 0; i < k; i++)
         for (int j = 0; j < kp; j++) W[i][j] = cc.p2q_m[i][j];
     mx_table(mx.a_p2q, W, cc.q, k, kp);
@@ -581,7 +584,6 @@ void build_conv_mx(const ConvConst &cc, ConvMx &mx) {
         const uint64_t pj = cc.p[j];
         mx.e_lift[j] = neg_bias(pj);
         mx.e_scale[j] = (hmul(cc.scale_m[j][k + 2], cc.phinv[j], pj) + neg_bias(pj)) % pj;
-        mx.s_dp[j] = hmul(cc.scale_m[j][k], cc.phinv[j], pj);
         mx.s_v[j] = hmul(cc.scale_m[j][k + 1], cc.phinv[j], pj);
         mx.l_beta[j] = cc.lift_m[j][k];
     }

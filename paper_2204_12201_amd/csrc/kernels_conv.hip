@@ -654,7 +654,7 @@ __device__ __forceinline__ mx_v4i mx_operand(uint64_t x0, uint64_t x1) {
 // each slot on the Q side and on the P side, and the exact-path queue
 // (offsets of coefficients within the workgroup's span).
 struct MxShared {
-    mx_v4i a[2][4][64];
+    mx_v4i a[3][4][64];
     uint64_t cq[FHE_MX_MAXB][10];
     uint64_t cp[FHE_MX_MAXB][8];
     int item[kMxSpan];
@@ -671,8 +671,16 @@ __device__ __forceinline__ void mx_products(const MxShared &sh, int t, uint32_t 
     for (int mm = 0; mm < 4; mm++) acc[mm] = __builtin_amdgcn_mfma_i32_16x16x64_i8(sh.a[t][mm][lane], B, bias, 0, 0, 0);
 }
 
+// acc[mm] += A[mm] B (table `t`): a second block of 64 (source, digit) pairs.
+__device__ __forceinline__ void mx_products_add(const MxShared &sh, int t, uint32_t lane, const mx_v4i B,
+                                                mx_v4i (&acc)[4]) {
+#pragma unroll
+    for (int mm = 0; mm < 4; mm++)
+        acc[mm] = __builtin_amdgcn_mfma_i32_16x16x64_i8(sh.a[t][mm][lane], B, acc[mm], 0, 0, 0);
+}
+
 // hi:lo = sum_v 256^v P'_v with P'_v = a[v] (v < 4), b[v - 4] (v >= 4), each in
-// [0, 2^21]: pairs within 32 bits (< 2^30), then x = a01 + a23 2^16 and
+// [0, 2^22]: pairs within 32 bits (< 2^31), then x = a01 + a23 2^16 and
 // w = a45 + a67 2^16 (< 2^47), and the sum x + w 2^32 (< 2^79).
 __device__ __forceinline__ void mx_recombine(const mx_v4i a, const mx_v4i b, uint64_t &lo, uint64_t &hi) {
     const uint32_t a01 = (uint32_t)a[0] + ((uint32_t)a[1] << 8);
@@ -751,8 +759,8 @@ __device__ __forceinline__ void mx_stage_table(MxShared &sh, int t, const int32_
 
 // Scale slot constants.  Q side of slot s: q, -q^-1 mod 2^64, [t qhat^-1]
 // (Shoup pair), [h qhat^-1], [-P] 2^64, bias removal, 1/q; P side: p,
-// -p^-1 mod 2^64, the D_p and v multipliers, bias removal plus constant, 1/p.
-// Absent primes: zeros.
+// -p^-1 mod 2^64, (word 2 unused), the v multiplier, bias removal plus
+// constant, 1/p.  Absent primes: zeros.
 __device__ __forceinline__ void mx_stage_scale_slots(MxShared &sh, const DevCtx &c) {
     const ConvConst &cc = *c.cc;
     const ConvMx &mx = *c.mx;
@@ -774,7 +782,6 @@ __device__ __forceinline__ void mx_stage_scale_slots(MxShared &sh, const DevCtx 
         const bool ok = s < c.kp;
         w[0] = ok ? cc.p[s] : 0;
         w[1] = ok ? cc.p_qinv[s] : 0;
-        w[2] = ok ? mx.s_dp[s] : 0;
         w[3] = ok ? mx.s_v[s] : 0;
         w[4] = ok ? mx.e_scale[s] : 0;
         w[5] = ok ? (uint64_t)__double_as_longlong(cc.inv_p[s]) : 0;
@@ -782,10 +789,11 @@ __device__ __forceinline__ void mx_stage_scale_slots(MxShared &sh, const DevCtx 
 }
 
 // Scale-and-round of one tile column on the matrix cores (tables 0: scale in
-// P, 1: P -> Q).  dq, dp: the lane's two Q and two P residues of D (zero for
-// absent primes); jv[h]: slot g + 4h is a P prime.  Returns false when the
-// coefficient must take the exact path, else the lane's two outputs C mod q_s
-// in out.
+// P from the y_i, 1: P -> Q, 2: scale in P from D_p, block-diagonal).  dq,
+// dp: the lane's two Q and two P residues of D (absent primes read a present
+// row; their constants and weights are zero); jv[h]: slot g + 4h is a P
+// prime.  Returns false when the coefficient must take the exact path, else
+// the lane's two outputs C mod q_s in out.
 __device__ __forceinline__ bool mx_scale_tile(const MxShared &sh, uint32_t lane, int a16, int a32,
                                               const uint64_t (&dq)[2], const uint64_t (&dp)[2], const bool (&jv)[2],
                                               uint64_t (&out)[2]) {
@@ -804,15 +812,14 @@ __device__ __forceinline__ bool mx_scale_tile(const MxShared &sh, uint32_t lane,
     const uint64_t v = (uint32_t)fl;  // < k
     mx_v4i acc[4];
     mx_products(sh, 0, lane, mx_operand(y[0], y[1]), acc);
+    mx_products_add(sh, 2, lane, mx_operand(dp[0], dp[1]), acc);
     uint64_t z[2];
     double e2 = 0.0;
 #pragma unroll
     for (int h = 0; h < 2; h++) {
         const uint64_t *Pc = sh.cp[g + 4 * h];
-        uint64_t lo, hi, plo, phi;
+        uint64_t lo, hi;
         mx_recombine(acc[2 * h], acc[2 * h + 1], lo, hi);
-        mul128(dp[h], Pc[2], plo, phi);
-        mx_add(lo, hi, plo, phi);
         mx_add(lo, hi, v * Pc[3], 0);
         mx_add(lo, hi, Pc[4], 0);
         // z_j = C_{p_j} phat_j^-1 mod p_j (the factor is folded into the table)
@@ -858,6 +865,7 @@ __global__ __launch_bounds__(256) void k_scale_mx(DevCtx c, const uint64_t *__re
     const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6, col = lane & 15u, g = lane >> 4;
     mx_stage_table(sh, 0, c.mx->a_scale);
     mx_stage_table(sh, 1, c.mx->a_p2q);
+    mx_stage_table(sh, 2, c.mx->a_sdp);
     mx_stage_scale_slots(sh, c);
     if (threadIdx.x == 0) sh.count = 0;
     __syncthreads();
@@ -942,6 +950,7 @@ __global__ __launch_bounds__(256) void k_scale_chain_mx(DevCtx c, const uint64_t
     const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6, col = lane & 15u, g = lane >> 4;
     mx_stage_table(sh, 0, c.mx->a_scale);
     mx_stage_table(sh, 1, c.mx->a_p2q);
+    mx_stage_table(sh, 2, c.mx->a_sdp);
     mx_stage_scale_slots(sh, c);
     {
         // the chain's gamma multipliers: Q side words 8, 9, P side words 6, 7

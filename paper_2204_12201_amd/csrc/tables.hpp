@@ -95,25 +95,26 @@ constexpr double FHE_EST_MARGIN = 9.094947017729282e-13;  // 2^-40
 // balanced base-256 digits, x_s = sum_u d_{s,u} 256^u with d in [-128, 127],
 // the weight of digit u is W[t][s] 256^u mod m_t, itself split into balanced
 // digits w_v (v = 0..7), and the products give P_{t,v} = sum_{s,u} d_{s,u}
-// w_v(W[t][s] 256^u mod m_t), exactly (|P| <= 2^20).  With the int32
-// accumulators started at FHE_MX_BIAS, r_t = (sum_v 256^v P'_{t,v} + extra
-// terms + E_t) 2^-64 mod m_t, where E_t = -FHE_MX_BIAS sum_v 256^v mod m_t
-// (plus any additive constant of the conversion) removes the bias.
+// w_v(W[t][s] 256^u mod m_t), exactly (|P| <= 2^20 per product of 64 terms,
+// 2^21 for two chained products).  With the int32 accumulators started at
+// FHE_MX_BIAS, r_t = (sum_v 256^v P'_{t,v} + extra terms + E_t) 2^-64 mod m_t,
+// where E_t = -FHE_MX_BIAS sum_v 256^v mod m_t (plus any additive constant of
+// the conversion) removes the bias.
 // Operand a_*[mm][lane] (four int32 = 16 bytes): row lane % 16 of product mm
 // is target 4 (mm / 2) + (lane % 16) / 4, digit v = 4 (mm % 2) + lane % 4;
 // byte b is source lane / 16 + 4 (b / 8), digit u = b % 8.  Lane l then
 // supplies the digits of sources l/16 and l/16 + 4 and receives P' of targets
 // l/16 and l/16 + 4 for column l % 16.
 constexpr int FHE_MX_MAXB = 8;
-constexpr int32_t FHE_MX_BIAS = 1 << 20;
+constexpr int32_t FHE_MX_BIAS = 1 << 21;
 struct ConvMx {
     int32_t a_lift[4][64][4];   // Q -> P centred lift: W[j][i] = [qhat_i]_{p_j} 2^64
     int32_t a_scale[4][64][4];  // scale in P: W[j][i] = [-q_i^-1 phat_j^-1]_{p_j} 2^64
+    int32_t a_sdp[4][64][4];    // scale in P, sources D_{p_s}: W[j][s] = [s == j] [t q^-1 phat_j^-1]_{p_j} 2^64
     int32_t a_p2q[4][64][4];    // P -> Q: W[i][j] = [phat_j]_{q_i} 2^64
     uint64_t e_lift[FHE_MX_MAXB];   // bias removal mod p_j
     uint64_t e_scale[FHE_MX_MAXB];  // bias removal plus [h q^-1 phat_j^-1]_{p_j} 2^64
     uint64_t e_p2q[FHE_MX_MAXB];    // bias removal mod q_i
-    uint64_t s_dp[FHE_MX_MAXB];     // [t q^-1 phat_j^-1]_{p_j} 2^64 (times D_{p_j})
     uint64_t s_v[FHE_MX_MAXB];      // [phat_j^-1]_{p_j} 2^64 (times v)
     uint64_t l_beta[FHE_MX_MAXB];   // [-q]_{p_j} 2^64 (times beta of the lift)
     uint64_t p_beta[FHE_MX_MAXB];   // [-P]_{q_i} 2^64 (times beta of P -> Q)
