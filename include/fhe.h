@@ -149,7 +149,9 @@ fhe_status fhe_set_fused_threshold(fhe_ctx *ctx, int square, size_t min_rows);
  * whose floating estimate lies near a rounding boundary take the exact
  * mixed-radix path either way).  Method 1 needs at most 8 primes in q and in
  * P and every prime at least 2^20 (else FHE_EUNSUPPORTED); it is the default
- * where it applies.  Drops the context's squaring-chain graphs. */
+ * where it applies.  With method 1, fhe_weighted_sum also runs on the matrix
+ * cores when every weight lies in [-127, 127] (same words).  Drops the
+ * context's squaring-chain graphs. */
 fhe_status fhe_set_conv_method(fhe_ctx *ctx, int method);
 /* The current method of fhe_set_conv_method (0 for a NULL context). */
 int fhe_conv_method(const fhe_ctx *ctx);

@@ -32,10 +32,12 @@ CFLAGS = [
 
 SOURCES = ["host.hip", "kernels_conv.hip", "kernels_ntt.hip", "kernels_lin.hip", "kernels_mfma.hip"]
 
-# Per-source device flags: the base conversions on the matrix cores keep
-# their int32 sums in ordinary VGPRs (no accumulator-register copies).
+# Per-source device flags: the base conversions and the weighted sums on the
+# matrix cores keep their int32 sums in ordinary VGPRs (no accumulator-register
+# copies).
 EXTRA = {
     "kernels_conv.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+    "kernels_lin.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
 }
 
 

@@ -686,6 +686,7 @@ fhe_status fhe_ctx_create(const fhe_params *p, int hip_device, fhe_ctx **out) {
         P.ninvm_p = shoup(P.ninvm, q);
         P.r32 = (uint64_t)(((u128)1 << 32) % q);
         P.r32_p = shoup(P.r32, q);
+        P.mx_neg_bias = (q - (uint64_t)(((u128)FHE_MX_BIAS * 0x0101010101010101ull) % q)) % q;
         P.off59 = ((1ull << 59) + q - 1) / q * q;
         P.off62 = ((1ull << 62) + q - 1) / q * q;
         const uint64_t psi = find_psi(q, n), ipsi = hinv(psi, q);
@@ -912,8 +913,11 @@ size_t fhe_workspace_bytes(const fhe_ctx *c, int op, size_t count) {
             return (k * n + 2 * count * k * n + count * n) * 8 + n + 256;
         case FHE_OP_RLK_IMPORT:
             return 0;
-        case FHE_OP_WEIGHTED_SUM:  // padded rows: at most 8 slots per weight
-            return 32 * count + 256;
+        case FHE_OP_WEIGHTED_SUM:
+            // padded int32 rows (at most 8 slots per weight), or the int8 operand
+            // table of the matrix cores: ceil(nout/16) ceil(nin/64) KiB
+            // <= 81 count + 1024 bytes for nout, nin <= count
+            return 81 * count + 1024;
         case FHE_OP_GATE:
             return 2 * count * ct_words(c) * 8 + fhe_workspace_bytes(c, FHE_OP_MUL_RELIN, count);
         case FHE_OP_COMPARE:
@@ -1606,10 +1610,9 @@ fhe_status fhe_bits_to_mod(fhe_ctx *c, const uint64_t *bits, uint32_t nbits, uin
 // Weight rows [nout][nin] padded to the kernel's row stride, staged in pinned
 // memory (the previous copy out of it must have finished), then copied
 // asynchronously to dst on st.
-static fhe_status stage_weights(fhe_ctx *c, const int32_t *w, size_t nout, size_t nin, int32_t *dst,
-                                hipStream_t st) {
-    const size_t stride = weighted_sum_row_stride(nin);
-    const size_t words = nout * stride;
+// Pinned staging buffer of at least `words` 32-bit words (the previous copy
+// out of it must have finished first).
+static fhe_status pinned_stage(fhe_ctx *c, size_t words) {
     if (!c->wpin_ev && hipEventCreateWithFlags(&c->wpin_ev, hipEventDisableTiming) != hipSuccess) {
         c->wpin_ev = nullptr;
         return FHE_EDEVICE;
@@ -1625,9 +1628,28 @@ static fhe_status stage_weights(fhe_ctx *c, const int32_t *w, size_t nout, size_
         }
         c->wpin_cap = words;
     }
+    return FHE_OK;
+}
+
+static fhe_status stage_weights(fhe_ctx *c, const int32_t *w, size_t nout, size_t nin, int32_t *dst,
+                                hipStream_t st) {
+    const size_t stride = weighted_sum_row_stride(nin);
+    const size_t words = nout * stride;
+    FHE_TRY(pinned_stage(c, words));
     std::memset(c->wpin, 0, words * 4);
     for (size_t m = 0; m < nout; m++) std::memcpy(c->wpin + m * stride, w + m * nin, nin * 4);
     FHE_HIP(hipMemcpyAsync(dst, c->wpin, words * 4, hipMemcpyHostToDevice, st));
+    FHE_HIP(hipEventRecord(c->wpin_ev, st));
+    return FHE_OK;
+}
+
+// The int8 operand table of the matrix-core weighted sum, staged like the weights.
+static fhe_status stage_weights_mx(fhe_ctx *c, const int32_t *w, size_t nout, size_t nin, void *dst,
+                                   hipStream_t st) {
+    const size_t bytes = weighted_sum_mx_bytes(nout, nin);
+    FHE_TRY(pinned_stage(c, (bytes + 3) / 4));
+    weighted_sum_mx_table(w, nout, nin, (int8_t *)c->wpin);
+    FHE_HIP(hipMemcpyAsync(dst, c->wpin, bytes, hipMemcpyHostToDevice, st));
     FHE_HIP(hipEventRecord(c->wpin_ev, st));
     return FHE_OK;
 }
@@ -1655,6 +1677,14 @@ fhe_status fhe_weighted_sum(fhe_ctx *c, const uint64_t *in, size_t nin, const in
     }
     (void)stride;
     FHE_TRY(check_canonical(c, in, nin * 2 * c->k, c->k, 0, st));
+    // the matrix cores (with the context's matrix-core conversions) for weights in [-127, 127]
+    bool mx = c->dev.mx != nullptr;
+    for (size_t i = 0; mx && i < nout * nin; i++) mx = w[i] >= -127 && w[i] <= 127;
+    if (mx) {
+        FHE_TRY(stage_weights_mx(c, w, nout, nin, ws, st));
+        return run(c, KK_ELEMENTWISE, st,
+                   [&] { return launch_weighted_sum_mx(c->dev, in, nin, ws, nout, out, st); });
+    }
     int32_t *wd = (int32_t *)ws;
     FHE_TRY(stage_weights(c, w, nout, nin, wd, st));
     return run(c, KK_ELEMENTWISE, st, [&] { return launch_weighted_sum(c->dev, in, nin, wd, nout, out, st); });

@@ -148,6 +148,13 @@ hipError_t launch_pass0(const DevCtx &c, int method, const void *Wt, uint64_t *d
                         int limb_off, int reps, hipStream_t s);
 
 // ---- integer-weighted sums (kernels_lin.hip) ----
+// Matrix-core variant for weights in [-127, 127]: the operand table (bytes
+// weighted_sum_mx_bytes) built on the host by weighted_sum_mx_table from the
+// weights [nout][nin], then out[m] = sum_j w[m][j] in[j] (in, out: [.][2][k][n]).
+size_t weighted_sum_mx_bytes(size_t nout, size_t nin);
+void weighted_sum_mx_table(const int32_t *w, size_t nout, size_t nin, int8_t *tab);
+hipError_t launch_weighted_sum_mx(const DevCtx &c, const uint64_t *in, size_t nin, const void *tab, size_t nout,
+                                  uint64_t *out, hipStream_t s);
 // Row stride (in weights) of the device weight matrix: rows padded with zeros.
 size_t weighted_sum_row_stride(size_t nin);
 // out[m] = sum_j w[m][j] in[j] for the padded device matrix w [nout][stride].

@@ -104,9 +104,135 @@ __global__ __launch_bounds__(256) void k_weighted_sum(DevCtx c, const uint64_t *
     }
 }
 
+// ------------------------------------------------ on the int8 matrix cores --
+//
+// For weights of at most 127 in absolute value the sums are a matrix product,
+// weights (outputs x inputs) times words (inputs x word positions), run on the
+// int8 matrix cores exactly.  Every input word x < 2^63 is written in
+// balanced base-256 digits d_u in [-128, 127] (the bytes of (x + B) xor B, B
+// = 0x80 in every byte), and per tile of 16 outputs x 16 word positions and
+// pass of at most 64 inputs, one v_mfma_i32_16x16x64_i8 per digit u gives
+//   P_u[m][p] = sum_j w[m][j] d_u(x_j[p]),   |P_u| <= 64 * 127 * 128 < 2^20.
+// Started at FHE_MX_BIAS (so every P'_u is positive), the eight sums
+// recombine without carries as T' = sum_u 256^u P'_u = B + A 2^32, where
+// x = P'_0 + 2^8 P'_1 + 2^16 P'_2 + 2^24 P'_3 and w = P'_4 + ... + 2^24 P'_7
+// (both below 2^47), A = floor(x / 2^32) + w and B = x mod 2^32.  With E =
+// -FHE_MX_BIAS sum_u 256^u mod q (PrimeConst::mx_neg_bias) added, T' + E is
+// the sum modulo q: (A + E_hi) r32 + (B + E_lo), two Shoup products.
+//
+// Operand layout (as for the base conversions): lane l of a wave supplies row
+// l mod 16 of A (output 16 mt + l mod 16) and column l mod 16 of B (word
+// position p0 + l mod 16), both with the 16 inputs 16 (l / 16) + b, b = 0..15,
+// in bytes b; it receives outputs 16 mt + 4 (l / 16) + i, i = 0..3, of its
+// column.
+
+typedef int ws_v4i __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint64_t ws_digits(uint64_t x) {
+    constexpr uint64_t B = 0x8080808080808080ull;
+    return (x + B) ^ B;
+}
+
+// Byte u of each of four words, packed (word i in byte i).
+__device__ __forceinline__ uint32_t ws_gather(const uint64_t *d, int u) {
+    uint32_t r = 0;
+#pragma unroll
+    for (int i = 0; i < 4; i++) r |= (uint32_t)((d[i] >> (8 * u)) & 0xFFu) << (8 * i);
+    return r;
+}
+
+// Wave w of workgroup x takes word positions p0 = 16 (4 x + w) .. p0 + 15
+// (input j at in + j in_js, output m at out + m out_ms) for the output tiles
+// blockIdx.y, blockIdx.y + gridDim.y, ... < nmt; wt: the pass's A operands
+// [nmt][64] (16 bytes each); accumulate: add into out.
+__global__ __launch_bounds__(256) void k_weighted_sum_mx(DevCtx c, const uint64_t *__restrict__ in, size_t in_js,
+                                                         int nj, const ws_v4i *__restrict__ wt, int nmt,
+                                                         size_t nout, uint64_t *__restrict__ out, size_t out_ms,
+                                                         int accumulate) {
+    const size_t W = (size_t)2 * c.k * c.n;
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6, col = lane & 15u, g = lane >> 4;
+    const size_t p0 = ((size_t)blockIdx.x * 4 + wave) * 16;
+    if (p0 >= W) return;  // whole waves
+    const size_t p = p0 + col;
+    const int limb = (int)((p0 >> c.L) % (size_t)c.k);
+    const PrimeConst &P = c.pc[limb];
+    const uint64_t q = P.q, E = P.mx_neg_bias;
+    // digits of the lane's 16 inputs, then one B operand per digit u
+    uint64_t d[16];
+#pragma unroll
+    for (int b = 0; b < 16; b++) {
+        const int j = (int)g * 16 + b;
+        d[b] = j < nj ? ws_digits(in[(size_t)j * in_js + p]) : 0;
+    }
+    ws_v4i Bu[8];
+#pragma unroll
+    for (int u = 0; u < 8; u++)
+        Bu[u] = ws_v4i{(int)ws_gather(d, u), (int)ws_gather(d + 4, u), (int)ws_gather(d + 8, u),
+                       (int)ws_gather(d + 12, u)};
+    const ws_v4i bias = {FHE_MX_BIAS, FHE_MX_BIAS, FHE_MX_BIAS, FHE_MX_BIAS};
+    for (int mt = (int)blockIdx.y; mt < nmt; mt += (int)gridDim.y) {
+        const ws_v4i A = wt[(size_t)mt * 64 + lane];
+        ws_v4i acc[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++) acc[u] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A, Bu[u], bias, 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            const size_t m = (size_t)mt * 16 + 4 * g + i;
+            if (m >= nout) continue;
+            const uint32_t a01 = (uint32_t)acc[0][i] + ((uint32_t)acc[1][i] << 8);
+            const uint32_t a23 = (uint32_t)acc[2][i] + ((uint32_t)acc[3][i] << 8);
+            const uint32_t a45 = (uint32_t)acc[4][i] + ((uint32_t)acc[5][i] << 8);
+            const uint32_t a67 = (uint32_t)acc[6][i] + ((uint32_t)acc[7][i] << 8);
+            const uint64_t x = (uint64_t)a01 + ((uint64_t)a23 << 16);
+            const uint64_t w = (uint64_t)a45 + ((uint64_t)a67 << 16);
+            const uint64_t hi = (x >> 32) + w + (E >> 32), lo = (x & 0xFFFFFFFFull) + (uint32_t)E;
+            uint64_t r = canon8w(mul_shoup_lazy4(hi, P.r32, P.r32_p, q) + mul_shoup_lazy4(lo, 1, P.one_p, q), q);
+            uint64_t *o = out + m * out_ms + p;
+            if (accumulate) r = add_mod(r, *o, q);
+            *o = r;
+        }
+    }
+}
+
 }  // namespace
 
 size_t weighted_sum_row_stride(size_t nin) { return (nin + WS_G - 1) / WS_G * WS_G; }
+
+size_t weighted_sum_mx_bytes(size_t nout, size_t nin) {
+    return ((nout + 15) / 16) * ((nin + 63) / 64) * 64 * 16;
+}
+
+void weighted_sum_mx_table(const int32_t *w, size_t nout, size_t nin, int8_t *tab) {
+    const size_t nmt = (nout + 15) / 16, npass = (nin + 63) / 64;
+    for (size_t pp = 0; pp < npass; pp++)
+        for (size_t mt = 0; mt < nmt; mt++)
+            for (int lane = 0; lane < 64; lane++)
+                for (int b = 0; b < 16; b++) {
+                    const size_t m = mt * 16 + lane % 16, j = pp * 64 + (lane / 16) * 16 + b;
+                    tab[((pp * nmt + mt) * 64 + lane) * 16 + b] =
+                        (int8_t)(m < nout && j < nin ? w[m * nin + j] : 0);
+                }
+}
+
+hipError_t launch_weighted_sum_mx(const DevCtx &c, const uint64_t *in, size_t nin, const void *tab, size_t nout,
+                                  uint64_t *out, hipStream_t s) {
+    const size_t W = (size_t)2 * c.k * c.n;
+    const size_t nmt = (nout + 15) / 16, npass = (nin + 63) / 64;
+    const size_t nbx = (W + 63) / 64;
+    size_t gy = (4096 + nbx - 1) / nbx;
+    if (gy > nmt) gy = nmt;
+    if (gy > 65535) gy = 65535;
+    if (gy < 1) gy = 1;
+    const ws_v4i *wt = (const ws_v4i *)tab;
+    for (size_t pp = 0; pp < npass; pp++) {
+        const int nj = (int)(nin - pp * 64 < 64 ? nin - pp * 64 : 64);
+        hipLaunchKernelGGL(k_weighted_sum_mx, dim3((unsigned)nbx, (unsigned)gy), dim3(256), 0, s, c,
+                           in + pp * 64 * W, W, nj, wt + pp * nmt * 64, (int)nmt, nout, out, W, pp > 0 ? 1 : 0);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
 
 hipError_t launch_weighted_sum(const DevCtx &c, const uint64_t *in, size_t nin, const int32_t *w, size_t nout,
                                uint64_t *out, hipStream_t s) {

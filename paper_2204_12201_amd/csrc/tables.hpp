@@ -20,7 +20,7 @@ struct PrimeConst {
     uint64_t ninvm, ninvm_p;   // n^-1 2^64 mod q (Shoup pair): inverse after Montgomery products
     uint64_t r32, r32_p;       // 2^32 mod q (Shoup pair)
     uint64_t off59, off62;     // smallest multiples of q at least 2^59 and 2^62
-    uint64_t pad;
+    uint64_t mx_neg_bias;      // -FHE_MX_BIAS sum_{u < 8} 256^u mod q (matrix-core weighted sums)
 };
 
 // Exact mixed-radix (Garner) conversion of a value given in basis M.

@@ -167,3 +167,30 @@ def test_bridge_both_methods(dev):
         want_bits, want_eq = bfv.bridge_to_bits(P, cts[j], rlk, 5)
         assert (eq[j] == want_eq).all(), f"eq {j}"
         assert (bits[j] == want_bits).all(), f"bits {j}"
+
+
+@pytest.mark.parametrize("n,bits,k,nin,nout", [(16, 30, 2, 1, 1), (256, 36, 3, 24, 37), (64, 55, 4, 64, 16),
+                                               (64, 61, 2, 65, 5), (1024, 55, 8, 130, 20)])
+def test_weighted_sum_both_methods(dev, n, bits, k, nin, nout):
+    """Integer-weighted sums with weights in [-127, 127]: the matrix-core path
+    (one or several passes of 64 inputs, ragged output tiles) and the vector
+    ALU path give the same words, equal to the oracle's on every output."""
+    qs = bfv.ntt_primes(n, bits, k)
+    P = bfv.Params(n, qs, 17, "coeff")
+    ctx = fhe.Context(n, qs, 17, "coeff")
+    assert ctx.conv_mfma
+    rng = np.random.default_rng(nin * 1000 + nout)
+    w = rng.integers(-127, 128, size=(nout, nin)).astype(np.int32)
+    w[0, 0] = -127
+    if nin > 1:
+        w[0, 1] = 127
+    x = inputs.uniform_ciphertexts(n, qs, nin, 37, "w")
+    xd = up(x)
+    got = {}
+    for mfma in (True, False):
+        say(f"weighted sum n={n} k={k} nin={nin} nout={nout} mfma={mfma}")
+        ctx.set_conv_method(mfma)
+        got[mfma] = down(ctx.weighted_sum(xd, w))
+    assert (got[True] == got[False]).all()
+    want = bfv.weighted_sum(P, x, w)
+    assert (got[True] == want).all()
