@@ -76,14 +76,39 @@ TRAFFIC = {
 KERNEL_SOURCES = ["paper_2204_12201_amd/csrc/kernels_ntt.hip", "paper_2204_12201_amd/csrc/ntt_core.hpp",
                   "paper_2204_12201_amd/csrc/modarith.hpp"]
 
+# HBM bytes per 512-item launch of each kernel of a squaring (same counter
+# passes and factors as TRAFFIC, taken with the matrix-core conversions), and
+# the hash of the transform and conversion sources they were taken on.
+PIPELINE = {
+    "bytes_512": {"lift_q2p": (524390.8 * 2.0 + 1048576.0) * 1024,
+                  "square_tensor": (1793942.1 * 2.0 + 4194307.0) * 1024,
+                  "scale_round": (1575209.3 * 2.0 + 1572864.0) * 1024,
+                  "relin_fused": (3097158.6 * 2.0 + 1359872.0) * 1024},
+    "src": "7bf43c2782dc991f",
+}
+PIPELINE_SOURCES = KERNEL_SOURCES + ["paper_2204_12201_amd/csrc/kernels_conv.hip"]
 
-def kernel_source_hash() -> str:
+
+def kernel_source_hash(files=None) -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in files or KERNEL_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def pipeline_bytes(ctx, squarings_per_s):
+    """HBM bytes one squaring moves through lift, tensor, scale and key
+    switching (counter figures of 512-item launches), against the 4 MiB of its
+    input and output ciphertexts, while the sources match the counter run."""
+    if kernel_source_hash(PIPELINE_SOURCES) != PIPELINE["src"]:
+        return None
+    per = {k: v / 512 for k, v in PIPELINE["bytes_512"].items()}
+    total = sum(per.values())
+    ct_bytes = 2 * ctx.k * ctx.n * 8
+    return {"bytes_per_squaring": total, "per_kernel": per, "min_bytes_per_squaring": 2 * ct_bytes,
+            "ratio_to_min": total / (2 * ct_bytes), "tb_per_s_at_measured_rate": total * squarings_per_s / 1e12}
 
 
 def percentile(xs, p):
@@ -251,6 +276,7 @@ def main():
         "step_p99_ms": percentile(step_ms, 99),
         "kernel_ms": {k: round(v[0], 3) for k, v in kern.items()},
         "roofline": roofline,
+        "pipeline_bytes": pipeline_bytes(ctx, mul_per_step * args.steps / elapsed) if args.conv == "mfma" else None,
     }
 
     legs = set(args.legs.split(",")) if args.legs != "all" else {
