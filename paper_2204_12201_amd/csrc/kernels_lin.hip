@@ -128,6 +128,9 @@ __global__ __launch_bounds__(256) void k_weighted_sum(DevCtx c, const uint64_t *
 
 typedef int ws_v4i __attribute__((ext_vector_type(4)));
 
+// Waves per workgroup of the matrix-core weighted sum (each a tile of 16 word positions).
+constexpr int WSX_WAVES = 4;
+
 __device__ __forceinline__ uint64_t ws_digits(uint64_t x) {
     constexpr uint64_t B = 0x8080808080808080ull;
     return (x + B) ^ B;
@@ -141,17 +144,17 @@ __device__ __forceinline__ uint32_t ws_gather(const uint64_t *d, int u) {
     return r;
 }
 
-// Wave w of workgroup x takes word positions p0 = 16 (4 x + w) .. p0 + 15
+// Wave w of workgroup x takes word positions p0 = 16 (WSX_WAVES x + w) .. p0 + 15
 // (input j at in + j in_js, output m at out + m out_ms) for the output tiles
 // blockIdx.y, blockIdx.y + gridDim.y, ... < nmt; wt: the pass's A operands
 // [nmt][64] (16 bytes each); accumulate: add into out.
-__global__ __launch_bounds__(256) void k_weighted_sum_mx(DevCtx c, const uint64_t *__restrict__ in, size_t in_js,
+__global__ __launch_bounds__(64 * WSX_WAVES) void k_weighted_sum_mx(DevCtx c, const uint64_t *__restrict__ in, size_t in_js,
                                                          int nj, const ws_v4i *__restrict__ wt, int nmt,
                                                          size_t nout, uint64_t *__restrict__ out, size_t out_ms,
                                                          int accumulate) {
     const size_t W = (size_t)2 * c.k * c.n;
     const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6, col = lane & 15u, g = lane >> 4;
-    const size_t p0 = ((size_t)blockIdx.x * 4 + wave) * 16;
+    const size_t p0 = ((size_t)blockIdx.x * WSX_WAVES + wave) * 16;
     if (p0 >= W) return;  // whole waves
     const size_t p = p0 + col;
     const int limb = (int)((p0 >> c.L) % (size_t)c.k);
@@ -218,15 +221,15 @@ hipError_t launch_weighted_sum_mx(const DevCtx &c, const uint64_t *in, size_t ni
                                   uint64_t *out, hipStream_t s) {
     const size_t W = (size_t)2 * c.k * c.n;
     const size_t nmt = (nout + 15) / 16, npass = (nin + 63) / 64;
-    const size_t nbx = (W + 63) / 64;
-    size_t gy = (4096 + nbx - 1) / nbx;
+    const size_t nbx = (W + 16 * WSX_WAVES - 1) / (16 * WSX_WAVES);
+    size_t gy = (16384 / WSX_WAVES + nbx - 1) / nbx;  // about 16384 waves in all
     if (gy > nmt) gy = nmt;
     if (gy > 65535) gy = 65535;
     if (gy < 1) gy = 1;
     const ws_v4i *wt = (const ws_v4i *)tab;
     for (size_t pp = 0; pp < npass; pp++) {
         const int nj = (int)(nin - pp * 64 < 64 ? nin - pp * 64 : 64);
-        hipLaunchKernelGGL(k_weighted_sum_mx, dim3((unsigned)nbx, (unsigned)gy), dim3(256), 0, s, c,
+        hipLaunchKernelGGL(k_weighted_sum_mx, dim3((unsigned)nbx, (unsigned)gy), dim3(64 * WSX_WAVES), 0, s, c,
                            in + pp * 64 * W, W, nj, wt + pp * nmt * 64, (int)nmt, nout, out, W, pp > 0 ? 1 : 0);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
