@@ -621,8 +621,10 @@ __global__ void k_validate(DevCtx c, const uint64_t *__restrict__ a, size_t word
 // constants), so for bases of at most 8 primes on each side they run on the
 // int8 matrix cores, exactly, with the operand tables of ConvMx.  Per tile of
 // 16 coefficients and per conversion: four v_mfma_i32_16x16x64_i8 give every
-// target's eight partial sums; each lane recombines the sums of its two
-// targets, adds the conversion's extra terms and reduces once (Montgomery).
+// target's eight partial sums (eight in the scale's first conversion, whose
+// D_p term is a second, block-diagonal block chained onto the first); each
+// lane recombines the sums of its two targets, adds the conversion's extra
+// terms and reduces once (Montgomery).
 // The floating estimates are summed over the four lanes of a column.  A
 // coefficient whose estimate falls within FHE_EST_MARGIN of a decision
 // boundary is queued in LDS and converted exactly (mixed radix) by one thread
