@@ -194,3 +194,34 @@ def test_weighted_sum_both_methods(dev, n, bits, k, nin, nout):
     assert (got[True] == got[False]).all()
     want = bfv.weighted_sum(P, x, w)
     assert (got[True] == want).all()
+
+
+def test_square_chain_graph_follows_conv_method(dev):
+    """A recorded squaring-chain graph holds the conversion kernels it was
+    recorded with; switching the engine drops the context's graphs, so the
+    next graph call records the other engine's kernels.  Every replay equals
+    the eager chain and the oracle."""
+    import torch
+    n = 1024
+    qs = bfv.ntt_primes(n, 55, 8)
+    P, km, pk, rlk, ctx, rlk_d = setup(n, qs, 17, "coeff", 39)
+    count, depth = 6, 2
+    x0 = inputs.uniform_ciphertexts(n, qs, count, 39, "x")
+    xe = up(x0)
+    for _ in range(depth):
+        ctx.mul_relin(rlk_d, xe, xe, out=xe)
+    want = down(xe)
+    y = x0[3]
+    for _ in range(depth):
+        y = bfv.mul_relin(P, y, y, rlk)
+    assert (want[3] == y).all()
+    src = up(x0)
+    xg = up(x0)
+    for mfma in (True, False, True):
+        say(f"square_chain graph n={n} mfma={mfma}")
+        ctx.set_conv_method(mfma)
+        for rep in range(2):
+            xg.copy_(src)
+            torch.cuda.synchronize()
+            ctx.square_chain(rlk_d, xg, depth, graph=True)
+            assert (down(xg) == want).all(), (mfma, rep)
