@@ -792,9 +792,9 @@ __device__ __forceinline__ void mx_stage_scale_slots(MxShared &sh, const DevCtx 
 
 // Scale-and-round of one tile column on the matrix cores (tables 0: scale in
 // P from the y_i, 1: P -> Q, 2: scale in P from D_p, block-diagonal).  dq,
-// dp: the lane's two Q and two P residues of D (absent primes read a present
-// row; their constants and weights are zero); jv[h]: slot g + 4h is a P
-// prime.  Returns false when the coefficient must take the exact path, else
+// dp: the lane's two Q and two P residues of D, any representatives below
+// 2^63 (absent primes read a present row; their constants and weights are
+// zero); jv[h]: slot g + 4h is a P prime.  Returns false when the coefficient must take the exact path, else
 // the lane's two outputs C mod q_s in out.
 __device__ __forceinline__ bool mx_scale_tile(const MxShared &sh, uint32_t lane, int a16, int a32,
                                               const uint64_t (&dq)[2], const uint64_t (&dp)[2], const bool (&jv)[2],
@@ -922,16 +922,25 @@ __global__ __launch_bounds__(256) void k_scale_mx(DevCtx c, const uint64_t *__re
 
 // D of a bridge chain at one prime m (k_scale_chain): the input's tensor t
 // plus 2 gamma x~ (g1 = [2 gamma]_m 2^64, a Montgomery multiplier) and, in the
-// constant coefficient of component 0 (sq), gamma^2 (g2); canonical.
-__device__ __forceinline__ uint64_t mx_chain_d(uint64_t t, uint64_t xl, uint64_t g1, uint64_t g2, uint64_t m,
-                                               uint64_t mqi, bool sq) {
+// constant coefficient of component 0 (sq), gamma^2 (g2), in [0, 4m): the
+// matrix-core scale takes any representative below 2^63 (a Shoup product
+// for the Q side, digits for the P side).
+__device__ __forceinline__ uint64_t mx_chain_dl(uint64_t t, uint64_t xl, uint64_t g1, uint64_t g2, uint64_t m,
+                                                uint64_t mqi, bool sq) {
     uint64_t v = t + mont_mul_lazy(xl, g1, m, mqi);
     if (sq) v += g2;
-    return csub(csub(v, m << 1), m);
+    return v;
 }
 
-// k_scale_chain on the matrix cores: component blockIdx.y of chain blockIdx.z.
-__global__ __launch_bounds__(256) void k_scale_chain_mx(DevCtx c, const uint64_t *__restrict__ Dt,
+// The same, canonical (the exact path).
+__device__ __forceinline__ uint64_t mx_chain_d(uint64_t t, uint64_t xl, uint64_t g1, uint64_t g2, uint64_t m,
+                                               uint64_t mqi, bool sq) {
+    return csub(csub(mx_chain_dl(t, xl, g1, g2, m, mqi, sq), m << 1), m);
+}
+
+// k_scale_chain on the matrix cores: component blockIdx.y of chain blockIdx.z
+// (register budget of four waves per SIMD).
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_scale_chain_mx(DevCtx c, const uint64_t *__restrict__ Dt,
                                                         const uint64_t *__restrict__ x,
                                                         const uint64_t *__restrict__ E,
                                                         const uint64_t *__restrict__ gam,
@@ -1000,8 +1009,8 @@ __global__ __launch_bounds__(256) void k_scale_chain_mx(DevCtx c, const uint64_t
 #pragma unroll
         for (int h = 0; h < 2; h++) {
             const uint64_t *Q = sh.cq[g + 4 * h], *Pc = sh.cp[g + 4 * h];
-            dq[h] = mx_chain_d(Rg.t[h], Rg.x[h], Q[8], Q[9], Q[0], Q[1], sq);
-            dp[h] = mx_chain_d(Rg.tp[h], Rg.xp[h], Pc[6], Pc[7], Pc[0], Pc[1], sq);
+            dq[h] = mx_chain_dl(Rg.t[h], Rg.x[h], Q[8], Q[9], Q[0], Q[1], sq);
+            dp[h] = mx_chain_dl(Rg.tp[h], Rg.xp[h], Pc[6], Pc[7], Pc[0], Pc[1], sq);
         }
         uint64_t r[2];
         if (mx_scale_tile(sh, lane, a16, a32, dq, dp, jv, r)) {
