@@ -84,7 +84,7 @@ PIPELINE = {
                   "square_tensor": (1793942.1 * 2.0 + 4194307.0) * 1024,
                   "scale_round": (1575209.3 * 2.0 + 1572864.0) * 1024,
                   "relin_fused": (3097158.6 * 2.0 + 1359872.0) * 1024},
-    "src": "d9214ee11921a204",
+    "src": "812c16121d858bd2",
 }
 PIPELINE_SOURCES = KERNEL_SOURCES + ["paper_2204_12201_amd/csrc/kernels_conv.hip"]
 

@@ -534,7 +534,8 @@ const char *fhe_status_str(fhe_status s) {
     return "unknown status";
 }
 
-// Balanced base-256 digits (each in [-128, 127]) of x < 2^63.
+// Balanced base-256 digits (each in [-128, 127]) of x < 2^62 (any x with
+// x + 0x8080808080808080 < 2^64).
 void balanced_digits(uint64_t x, int8_t d[8]) {
     const uint64_t B = 0x8080808080808080ull;
     const uint64_t y = (x + B) ^ B;

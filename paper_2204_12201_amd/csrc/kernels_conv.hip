@@ -638,9 +638,10 @@ typedef int mx_v4i __attribute__((ext_vector_type(4)));
 // Coefficients per workgroup (four waves, tiles of 16).
 constexpr int kMxSpan = 1024;
 
-// Balanced base-256 digits of x < 2^63 as eight signed bytes: the bytes of
-// x + B (B = 0x80 in every byte) are d_u + 128, and xor 0x80 turns each into
-// d_u in two's complement.
+// Balanced base-256 digits of x as eight signed bytes: the bytes of x + B
+// (B = 0x80 in every byte) are d_u + 128, and xor 0x80 turns each into d_u in
+// two's complement.  Valid while x + B < 2^64 (x <= 0x7F7F7F7F7F7F7F7F, about
+// 2^63 - 2^55); every value decomposed here is below 2^62.
 __device__ __forceinline__ uint64_t mx_digits(uint64_t x) {
     constexpr uint64_t B = 0x8080808080808080ull;
     return (x + B) ^ B;
@@ -793,7 +794,7 @@ __device__ __forceinline__ void mx_stage_scale_slots(MxShared &sh, const DevCtx 
 // Scale-and-round of one tile column on the matrix cores (tables 0: scale in
 // P from the y_i, 1: P -> Q, 2: scale in P from D_p, block-diagonal).  dq,
 // dp: the lane's two Q and two P residues of D, any representatives below
-// 2^63 (absent primes read a present row; their constants and weights are
+// 2^62 (absent primes read a present row; their constants and weights are
 // zero); jv[h]: slot g + 4h is a P prime.  Returns false when the coefficient must take the exact path, else
 // the lane's two outputs C mod q_s in out.
 __device__ __forceinline__ bool mx_scale_tile(const MxShared &sh, uint32_t lane, int a16, int a32,
@@ -922,20 +923,21 @@ __global__ __launch_bounds__(256) void k_scale_mx(DevCtx c, const uint64_t *__re
 
 // D of a bridge chain at one prime m (k_scale_chain): the input's tensor t
 // plus 2 gamma x~ (g1 = [2 gamma]_m 2^64, a Montgomery multiplier) and, in the
-// constant coefficient of component 0 (sq), gamma^2 (g2), in [0, 4m): the
-// matrix-core scale takes any representative below 2^63 (a Shoup product
-// for the Q side, digits for the P side).
+// constant coefficient of component 0 (sq), gamma^2 (g2), in [0, 2m) (one
+// conditional subtraction from [0, 4m)): the matrix-core scale takes any
+// representative below 2^62 (a Shoup product for the Q side, digits for the
+// P side).
 __device__ __forceinline__ uint64_t mx_chain_dl(uint64_t t, uint64_t xl, uint64_t g1, uint64_t g2, uint64_t m,
                                                 uint64_t mqi, bool sq) {
     uint64_t v = t + mont_mul_lazy(xl, g1, m, mqi);
     if (sq) v += g2;
-    return v;
+    return csub(v, m << 1);
 }
 
 // The same, canonical (the exact path).
 __device__ __forceinline__ uint64_t mx_chain_d(uint64_t t, uint64_t xl, uint64_t g1, uint64_t g2, uint64_t m,
                                                uint64_t mqi, bool sq) {
-    return csub(csub(mx_chain_dl(t, xl, g1, g2, m, mqi, sq), m << 1), m);
+    return csub(mx_chain_dl(t, xl, g1, g2, m, mqi, sq), m);
 }
 
 // k_scale_chain on the matrix cores: component blockIdx.y of chain blockIdx.z

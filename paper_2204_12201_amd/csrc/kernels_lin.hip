@@ -108,7 +108,7 @@ __global__ __launch_bounds__(256) void k_weighted_sum(DevCtx c, const uint64_t *
 //
 // For weights of at most 127 in absolute value the sums are a matrix product,
 // weights (outputs x inputs) times words (inputs x word positions), run on the
-// int8 matrix cores exactly.  Every input word x < 2^63 is written in
+// int8 matrix cores exactly.  Every input word x (< q < 2^61) is written in
 // balanced base-256 digits d_u in [-128, 127] (the bytes of (x + B) xor B, B
 // = 0x80 in every byte), and per tile of 16 outputs x 16 word positions and
 // pass of at most 64 inputs, one v_mfma_i32_16x16x64_i8 per digit u gives

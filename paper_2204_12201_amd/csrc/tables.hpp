@@ -91,7 +91,7 @@ constexpr double FHE_EST_MARGIN = 9.094947017729282e-13;  // 2^-40
 // Operand tables of the base conversions on the int8 matrix cores, for bases
 // of at most 8 primes on each side.  A conversion r_t = sum_s x_s W[t][s] mod
 // m_t (sources s, targets t, weights in Montgomery form) runs as four products
-// v_mfma_i32_16x16x64_i8 per 16 coefficients: every x_s < 2^63 is written in
+// v_mfma_i32_16x16x64_i8 per 16 coefficients: every x_s < 2^62 is written in
 // balanced base-256 digits, x_s = sum_u d_{s,u} 256^u with d in [-128, 127],
 // the weight of digit u is W[t][s] 256^u mod m_t, itself split into balanced
 // digits w_v (v = 0..7), and the products give P_{t,v} = sum_{s,u} d_{s,u}
