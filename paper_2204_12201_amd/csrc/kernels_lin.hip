@@ -28,9 +28,21 @@ __device__ __forceinline__ uint64_t canon8w(uint64_t x, uint64_t q) {  // [0, 8q
     return csub(csub(csub(x, q << 2), q << 1), q);
 }
 
+// The constants of a word's prime that the final reduction uses, held in
+// registers: read through the table after a store to out, the compiler would
+// reload them, and the wait for the reload would also wait for every store
+// before it.
+struct LinPrime {
+    uint64_t q, off59, off62, r32, r32_p, one_p;
+};
+
+__device__ __forceinline__ LinPrime lin_prime(const PrimeConst &P) {
+    return LinPrime{P.q, P.off59, P.off62, P.r32, P.r32_p, P.one_p};
+}
+
 // S = S_hi 2^32 + S_lo mod q from the two signed sums (S_lo still without
 // its 2^31 sum(w) correction), written or added to *o.
-__device__ __forceinline__ void finish(int64_t sl, int64_t sh, int32_t ws, const PrimeConst &P, uint64_t *o,
+__device__ __forceinline__ void finish(int64_t sl, int64_t sh, int32_t ws, const LinPrime &P, uint64_t *o,
                                        int accumulate) {
     const uint64_t q = P.q;
     sl += (int64_t)ws * ((int64_t)1 << 31);
@@ -56,8 +68,7 @@ __global__ __launch_bounds__(256) void k_weighted_sum(DevCtx c, const uint64_t *
     const size_t p = (size_t)blockIdx.x * 256 + threadIdx.x;
     if (p >= W) return;
     const int limb = (int)((p >> c.L) % (size_t)c.k);
-    const PrimeConst &P = c.pc[limb];
-    const uint64_t q = P.q;
+    const LinPrime P = lin_prime(c.pc[limb]);
     in += blockIdx.z * in_is;
     out += blockIdx.z * out_is;
     // the constant coefficient of the first polynomial carries Delta in the encryption of 1
@@ -158,8 +169,10 @@ __global__ __launch_bounds__(64 * WSX_WAVES) void k_weighted_sum_mx(DevCtx c, co
     if (p0 >= W) return;  // whole waves
     const size_t p = p0 + col;
     const int limb = (int)((p0 >> c.L) % (size_t)c.k);
+    // the prime's constants in registers (a store to out could alias the
+    // table for the compiler, which would reload them, and wait, per output)
     const PrimeConst &P = c.pc[limb];
-    const uint64_t q = P.q, E = P.mx_neg_bias;
+    const uint64_t q = P.q, E = P.mx_neg_bias, r32 = P.r32, r32p = P.r32_p, onep = P.one_p;
     // digits of the lane's 16 inputs, then one B operand per digit u
     uint64_t d[16];
 #pragma unroll
@@ -189,7 +202,7 @@ __global__ __launch_bounds__(64 * WSX_WAVES) void k_weighted_sum_mx(DevCtx c, co
             const uint64_t x = (uint64_t)a01 + ((uint64_t)a23 << 16);
             const uint64_t w = (uint64_t)a45 + ((uint64_t)a67 << 16);
             const uint64_t hi = (x >> 32) + w + (E >> 32), lo = (x & 0xFFFFFFFFull) + (uint32_t)E;
-            uint64_t r = canon8w(mul_shoup_lazy4(hi, P.r32, P.r32_p, q) + mul_shoup_lazy4(lo, 1, P.one_p, q), q);
+            uint64_t r = canon8w(mul_shoup_lazy4(hi, r32, r32p, q) + mul_shoup_lazy4(lo, 1, onep, q), q);
             uint64_t *o = out + m * out_ms + p;
             if (accumulate) r = add_mod(r, *o, q);
             *o = r;
