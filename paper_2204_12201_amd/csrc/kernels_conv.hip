@@ -696,6 +696,14 @@ __device__ __forceinline__ void mx_recombine(const mx_v4i a, const mx_v4i b, uin
     hi = (w >> 32) + (lo < x ? 1u : 0u);
 }
 
+// (hi:lo) 2^-64 mod m in [0, m) for the sums of the matrix-core tiles: below
+// 2^79 plus two 64-bit constants, so hi < 2^16 < m - 1 (every prime here is at
+// least 2^20) and the Montgomery reduction hi + floor(m' m / 2^64) + [lo != 0]
+// (m' = lo (-m^-1) mod 2^64) is already below 2m: one conditional subtraction.
+__device__ __forceinline__ uint64_t mx_reduce(uint64_t lo, uint64_t hi, uint64_t m, uint64_t minv_neg) {
+    return csub(redc_lazy(hi, lo, m, minv_neg), m);
+}
+
 __device__ __forceinline__ void mx_add(uint64_t &lo, uint64_t &hi, uint64_t alo, uint64_t ahi) {
     lo += alo;
     hi += ahi + (lo < alo ? 1u : 0u);
@@ -826,7 +834,7 @@ __device__ __forceinline__ bool mx_scale_tile(const MxShared &sh, uint32_t lane,
         mx_add(lo, hi, v * Pc[3], 0);
         mx_add(lo, hi, Pc[4], 0);
         // z_j = C_{p_j} phat_j^-1 mod p_j (the factor is folded into the table)
-        z[h] = jv[h] ? acc_reduce_mont_small(Acc128{lo, hi}, Pc[0], Pc[1]) : 0;
+        z[h] = jv[h] ? mx_reduce(lo, hi, Pc[0], Pc[1]) : 0;
         e2 = fma((double)z[h], mx_f64(Pc[5]), e2);
     }
     e2 = mx_colsum(e2, a16, a32);
@@ -841,7 +849,7 @@ __device__ __forceinline__ bool mx_scale_tile(const MxShared &sh, uint32_t lane,
         mx_recombine(acc[2 * h], acc[2 * h + 1], lo, hi);
         mx_add(lo, hi, beta * Q[5], 0);
         mx_add(lo, hi, Q[6], 0);
-        out[h] = acc_reduce_mont_small(Acc128{lo, hi}, Q[0], Q[1]);
+        out[h] = mx_reduce(lo, hi, Q[0], Q[1]);
     }
     return !exact;
 }
@@ -1124,7 +1132,7 @@ __global__ __launch_bounds__(256) void k_lift_mx(DevCtx c, const uint64_t *__res
                     mx_recombine(acc[2 * h], acc[2 * h + 1], lo, hi);
                     mx_add(lo, hi, beta * Pc[2], 0);
                     mx_add(lo, hi, Pc[3], 0);
-                    dst[(size_t)(g + 4 * h) * n + coef] = acc_reduce_mont_small(Acc128{lo, hi}, Pc[0], Pc[1]);
+                    dst[(size_t)(g + 4 * h) * n + coef] = mx_reduce(lo, hi, Pc[0], Pc[1]);
                 }
             }
         } else if (g == 0) {

@@ -42,6 +42,19 @@ def recombine(P):
     return sum(p << (8 * v) for v, p in enumerate(P))
 
 
+def mx_reduce(T, m):
+    """The kernels' reduction of a tile sum T: one Montgomery step (hi +
+    floor(m' m / 2^64) + [lo != 0], m' = lo (-m^-1) mod 2^64) and a single
+    conditional subtraction, valid because hi = floor(T / 2^64) stays below
+    2^16 (sums below 2^79 plus two 64-bit constants) while m >= 2^20."""
+    lo, hi = T % R, T >> 64
+    assert hi < (1 << 16)
+    mp = lo * ((-pow(m, -1, R)) % R) % R
+    r = hi + (mp * m >> 64) + (1 if lo else 0)
+    assert r < 2 * m
+    return r - m if r >= m else r
+
+
 def test_balanced_digits_recompose():
     rnd = random.Random(1)
     top = (1 << 64) - 1 - B8  # 0x7F7F7F7F7F7F7F7F, the largest word the form covers
@@ -95,6 +108,7 @@ def test_scale_with_digit_products_is_exact_rounding():
             assert T < pj * R
             zj = T * pow(R, -1, pj) % pj
             assert zj == (C % pj) * phinv % pj
+            assert mx_reduce(T, pj) == zj
             z.append(zj)
         beta = round(sum(Fraction(z[j], ps[j]) for j in range(8)))
         for i, qi in enumerate(qs):
@@ -102,6 +116,7 @@ def test_scale_with_digit_products_is_exact_rounding():
             Pv = [BIAS + a for a in digit_products(z, W2, qi)]
             T = recombine(Pv) + beta * ((-P) % qi * R % qi) + ((-bias_total) % qi)
             assert T * pow(R, -1, qi) % qi == C % qi
+            assert mx_reduce(T, qi) == C % qi
 
 
 def test_lift_with_digit_products_is_centred_lift():
@@ -117,6 +132,7 @@ def test_lift_with_digit_products_is_centred_lift():
             Pv = [BIAS + a for a in digit_products(y, W, pj)]
             T = recombine(Pv) + beta * ((-q) % pj * R % pj) + ((-bias_total) % pj)
             assert T * pow(R, -1, pj) % pj == xc % pj
+            assert mx_reduce(T, pj) == xc % pj
 
 
 def test_weighted_sum_recombination_is_exact():
