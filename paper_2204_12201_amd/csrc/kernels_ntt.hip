@@ -177,20 +177,20 @@ __global__ __launch_bounds__(Geo<L>::T) void k_tensor_intt(DevCtx c, const uint6
         if (SQ) {
             const uint64_t a0 = base[idx], a1 = base[rs + idx];
             if (comp == 0) {
-                v = mont_mul_lazy(a0, a0, q, qi);
+                v = mont_mul_lazy_u(a0, a0, q, qi);
             } else if (comp == 1) {
-                const uint64_t m = mont_mul_lazy(a0, a1, q, qi);  // d1 = 2 a0 a1
+                const uint64_t m = mont_mul_lazy_u(a0, a1, q, qi);  // d1 = 2 a0 a1
                 v = csub(m + m, q2);
             } else {
-                v = mont_mul_lazy(a1, a1, q, qi);
+                v = mont_mul_lazy_u(a1, a1, q, qi);
             }
         } else {
             const uint64_t a0 = base[idx], a1 = base[rs + idx];
             const uint64_t b0 = base[2 * rs + idx], b1 = base[3 * rs + idx];
-            if (comp == 0) v = mont_mul_lazy(a0, b0, q, qi);
+            if (comp == 0) v = mont_mul_lazy_u(a0, b0, q, qi);
             else if (comp == 1)
-                v = csub(mont_mul_lazy(a0, b1, q, qi) + mont_mul_lazy(a1, b0, q, qi), q2);
-            else v = mont_mul_lazy(a1, b1, q, qi);
+                v = csub(mont_mul_lazy_u(a0, b1, q, qi) + mont_mul_lazy_u(a1, b0, q, qi), q2);
+            else v = mont_mul_lazy_u(a1, b1, q, qi);
         }
         x[s] = csub(v, q2);  // [0, 2q)
     }
@@ -264,7 +264,7 @@ __global__ __launch_bounds__(Geo<L>::T) void k_mul_tensor(DevCtx c, const uint64
         const uint64_t a1 = fwd_operand<LZ>(x[s], q, one_p);
         y[s] = fwd_operand<LZ>(y[s], q, one_p);
         d1[idx] = a1;
-        d2[idx] = mont_mul_lazy(a1, y[s], q, qi);
+        d2[idx] = mont_mul_lazy_u(a1, y[s], q, qi);
     }
     asm volatile("" ::: "memory");
     // A0
@@ -286,7 +286,7 @@ __global__ __launch_bounds__(Geo<L>::T) void k_mul_tensor(DevCtx c, const uint64
 #pragma unroll
     for (int s = 0; s < 16; s++) {
         x[s] = fwd_operand<LZ>(x[s], q, one_p);
-        d0[bitrev_layout_index<L>(t3, s)] = mont_mul_lazy(x[s], y[s], q, qi);
+        d0[bitrev_layout_index<L>(t3, s)] = mont_mul_lazy_u(x[s], y[s], q, qi);
     }
     asm volatile("" ::: "memory");
     // B0
@@ -307,8 +307,8 @@ __global__ __launch_bounds__(Geo<L>::T) void k_mul_tensor(DevCtx c, const uint64
     for (int s = 0; s < 16; s++) {
         const uint32_t idx = bitrev_layout_index<L>(t5, s);
         const uint64_t b0 = fwd_operand<LZ>(y[s], q, one_p);
-        y[s] = mont_mul_lazy(d1[idx], b0, q, qi) + d0[idx];  // < 4q
-        x[s] = mont_mul_lazy(x[s], b0, q, qi);
+        y[s] = mont_mul_lazy_u(d1[idx], b0, q, qi) + d0[idx];  // < 4q
+        x[s] = mont_mul_lazy_u(x[s], b0, q, qi);
     }
     asm volatile("" ::: "memory");
     ntt_inv_regs<L, 4, LZ>(x, lds, tid, itw, q);
@@ -376,10 +376,10 @@ __global__ __launch_bounds__(Geo<L>::T) void k_square_tensor(DevCtx c, const uin
     for (int s = 0; s < 16; s++) {
         const uint64_t a1 = fwd_operand<LZ>(x[s], q, one_p);
         const uint64_t a0 = fwd_operand<LZ>(y[s], q, one_p);
-        const uint64_t m = mont_mul_lazy(a0, a1, q, qi);
+        const uint64_t m = mont_mul_lazy_u(a0, a1, q, qi);
         d1[bitrev_layout_index<L>(t2, s)] = m + m;
-        y[s] = mont_mul_lazy(a0, a0, q, qi);
-        x[s] = mont_mul_lazy(a1, a1, q, qi);
+        y[s] = mont_mul_lazy_u(a0, a0, q, qi);
+        x[s] = mont_mul_lazy_u(a1, a1, q, qi);
     }
     asm volatile("" ::: "memory");
     ntt_inv_regs2<L, 4, LZ>(y, x, lds, tid, itw, q);
@@ -434,9 +434,9 @@ __global__ __launch_bounds__(Geo<L>::T) void k_mul_tensor_pre2(DevCtx c, const u
     for (int s = 0; s < 16; s++) {
         const uint32_t idx = bitrev_layout_index<L>(t2, s);
         const uint64_t a0 = a0h[idx], a1 = a1h[idx], b0 = b0h[idx], b1 = b1h[idx];
-        d2[idx] = mont_mul_lazy(a1, b1, q, qi);
-        x[s] = mont_mul_lazy(a0, b1, q, qi) + mont_mul_lazy(a1, b0, q, qi);  // below 4q
-        y[s] = mont_mul_lazy(a0, b0, q, qi);
+        d2[idx] = mont_mul_lazy_u(a1, b1, q, qi);
+        x[s] = mont_mul_lazy_u(a0, b1, q, qi) + mont_mul_lazy_u(a1, b0, q, qi);  // below 4q
+        y[s] = mont_mul_lazy_u(a0, b0, q, qi);
     }
     asm volatile("" ::: "memory");
     ntt_inv_regs2<L, 4, LZ>(y, x, lds, tid, itw, q);

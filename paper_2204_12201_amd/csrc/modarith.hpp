@@ -157,6 +157,59 @@ __device__ __forceinline__ void acc3_mac(Acc3 &A, uint64_t a, uint64_t b) {
         : [a0] "v"(a0), [a1] "v"(a1), [b0] "s"(b0), [b1] "s"(b1));
 }
 
+// a b 2^-64 mod q in [0, 2q) (the value of mont_mul_lazy) for a wave-uniform
+// q, when a b < q 2^64 and hi(a) + hi(b) + hi(q) < 2^32 (32-bit halves).  The
+// product T = a b and m q (m = T (-q^-1) mod 2^64) are summed by columns of
+// 32-bit halves with multiply-adds whose 64-bit addends are the previous
+// partial sums: L = lo(a) lo(b) + m0 q0 (carry cL), Mid = lo(a) hi(b) +
+// hi(a) lo(b) + m0 hi(q) + m1 lo(q) (below 2^64 until the last term, whose
+// carry is cM; the bound on the high halves keeps the first three below
+// 2^64) and H = hi(a) hi(b) + m1 hi(q).  T + m q vanishes modulo 2^64, so its
+// bits 32..63 are zero: lo(Mid) + hi(L) is 0 or 2^32, the latter exactly when
+// lo(Mid) is nonzero, and (T + m q) / 2^64 = H + hi(Mid) + cL + [lo(Mid) != 0]
+// + cM 2^32.  No partial product is zero-extended into a 64-bit addend, which
+// would cost register moves.  The carry masks written by the multiply-adds
+// are read as carry-ins only two or more instructions later.
+__device__ __forceinline__ uint64_t mont_mul_lazy_u(uint64_t a, uint64_t b, uint64_t q, uint64_t qinv_neg) {
+    const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32);
+    const uint32_t b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
+    const uint32_t q0 = (uint32_t)q, q1 = (uint32_t)(q >> 32);
+    const uint32_t qi0 = (uint32_t)qinv_neg, qi1 = (uint32_t)(qinv_neg >> 32);
+    uint64_t P00, Mid, P11, j0;
+    asm("v_mad_u64_u32 %[p00], %[j], %[a0], %[b0], 0\n\t"
+        "v_mad_u64_u32 %[mid], %[j], %[a0], %[b1], 0\n\t"
+        "v_mad_u64_u32 %[p11], %[j], %[a1], %[b1], 0\n\t"
+        "v_mad_u64_u32 %[mid], %[j], %[a1], %[b0], %[mid]"
+        : [p00] "=&v"(P00), [mid] "=&v"(Mid), [p11] "=&v"(P11), [j] "=&s"(j0)
+        : [a0] "v"(a0), [a1] "v"(a1), [b0] "v"(b0), [b1] "v"(b1));
+    // m = lo(T) (-q^-1) mod 2^64, lo(T) = (lo P00, hi P00 + lo Mid)
+    const uint32_t t0 = (uint32_t)P00, t1 = (uint32_t)(P00 >> 32) + (uint32_t)Mid;
+    const uint64_t M = (uint64_t)t0 * qi0;
+    const uint32_t m0 = (uint32_t)M, m1 = (uint32_t)(M >> 32) + t0 * qi1 + t1 * qi0;
+    uint64_t L, H, cL, cM, j1;
+    asm("v_mad_u64_u32 %[l], %[cl], %[m0], %[q0], %[p00]\n\t"
+        "v_mad_u64_u32 %[mid], %[j], %[m0], %[q1], %[mid]\n\t"
+        "v_mad_u64_u32 %[h], %[j], %[m1], %[q1], %[p11]\n\t"
+        "v_mad_u64_u32 %[mid], %[cm], %[m1], %[q0], %[mid]"
+        : [l] "=&v"(L), [h] "=&v"(H), [mid] "+v"(Mid), [cl] "=&s"(cL), [cm] "=&s"(cM), [j] "=&s"(j1)
+        : [m0] "v"(m0), [m1] "v"(m1), [q0] "s"(q0), [q1] "s"(q1), [p00] "v"(P00), [p11] "v"(P11));
+    (void)L;
+    const uint32_t h0 = (uint32_t)H, h1 = (uint32_t)(H >> 32), ml = (uint32_t)Mid, mh = (uint32_t)(Mid >> 32);
+    uint32_t r0, r1;
+    uint64_t e1, e2, e3, nz;
+    asm("v_add_co_u32_e64 %[r0], %[e1], %[h0], %[mh]\n\t"
+        "v_cmp_ne_u32_e64 %[nz], 0, %[ml]\n\t"
+        "v_addc_co_u32_e64 %[r0], %[e2], %[r0], 0, %[cl]\n\t"
+        "v_addc_co_u32_e64 %[r1], %[e1], %[h1], 0, %[e1]\n\t"
+        "v_addc_co_u32_e64 %[r0], %[e3], %[r0], 0, %[nz]\n\t"
+        "v_addc_co_u32_e64 %[r1], %[e2], %[r1], 0, %[e2]\n\t"
+        "v_addc_co_u32_e64 %[r1], %[e1], %[r1], 0, %[cm]\n\t"
+        "v_addc_co_u32_e64 %[r1], %[e1], %[r1], 0, %[e3]"
+        : [r0] "=&v"(r0), [r1] "=&v"(r1), [e1] "=&s"(e1), [e2] "=&s"(e2), [e3] "=&s"(e3), [nz] "=&s"(nz)
+        : [h0] "v"(h0), [h1] "v"(h1), [ml] "v"(ml), [mh] "v"(mh), [cl] "s"(cL), [cm] "s"(cM));
+    return ((uint64_t)r1 << 32) | r0;
+}
+
 // A += c for a constant c < 2^64.
 __device__ __forceinline__ void acc3_add(Acc3 &A, uint64_t c) {
     const uint64_t s = A.lo + c;
