@@ -330,74 +330,117 @@ __global__ __launch_bounds__(Geo<L>::T) void k_mul_tensor(DevCtx c, const uint64
     for (int s = 0; s < 16; s++) d2[natural_index<L>(t9, s)] = mul_shoup_s(x[s], P.ninvm, P.ninvm_p, q);
 }
 
-// Squaring, transform phase fused: grid (K limbs, items).  For limb l of item
-// it transforms a0 and a1 (Q limbs straight from the ciphertext, P limbs from
-// the lift in E), then forms d0 = a0^2, d1 = 2 a0 a1, d2 = a1^2 (Montgomery
-// products) and inverse transforms each into Dt[item][comp][l].  Two rows
-// live in registers: a0 and a1 are transformed side by side (one twiddle load
-// for both); d1 (transform domain) is parked in its own output row, which this
-// workgroup alone touches, and read back while d2 is inverse transformed.
-template <int L, bool LZ>
+// Squaring, transform phase fused: one task per (item, limb l), task = l + K
+// item.  For limb l of item it transforms a0 and a1 (Q limbs straight from the
+// ciphertext, P limbs from the lift in E), then forms d0 = a0^2, d1 = 2 a0 a1,
+// d2 = a1^2 (Montgomery products) and inverse transforms each into
+// Dt[item][comp][l].  Two rows live in registers: a0 and a1 are transformed
+// side by side (one twiddle load for both); d1 (transform domain) is parked in
+// its own output row, which this task alone touches, and read back while d2 is
+// inverse transformed.  PERSIST: a resident grid of workgroups takes the tasks
+// blockIdx.x, blockIdx.x + gridDim.x, ...; the next task's a1 row is loaded
+// into the free registers of x during the last inverse transform of the
+// current task (after its last vector-memory twiddle load), so that it
+// arrives while that transform finishes and its output is stored, and its a0
+// row right after that store.  Otherwise grid (K, items), one task per
+// workgroup.
+template <int L, bool LZ, bool PERSIST>
 __global__ __launch_bounds__(Geo<L>::T) void k_square_tensor(DevCtx c, const uint64_t *__restrict__ a,
                                                             const uint64_t *__restrict__ E,
-                                                            uint64_t *__restrict__ Dt) {
+                                                            uint64_t *__restrict__ Dt, uint32_t tasks) {
+    static_assert(!PERSIST || Geo<L>::NPASS >= 3, "the next task's rows load from the pass-2 exchange hook");
     __shared__ uint64_t lds[Geo<L>::lds_words];
     constexpr int n = Geo<L>::N;
     const uint32_t tid = threadIdx.x;
-    const int limb = blockIdx.x;
-    const size_t item = blockIdx.y;
     const int k = c.k, K = c.K;
-    const PrimeConst &P = c.pc[limb];
-    const uint64_t q = P.q, qi = P.qinv_neg, one_p = P.one_p;
-    const Tw *tw = c.tw + (size_t)limb * n;
-    const Tw *itw = c.itw + (size_t)limb * n;
-    const uint64_t *src0, *src1;
-    if (limb < k) {
-        src0 = a + ((item * 2 + 0) * k + limb) * (size_t)n;
-        src1 = a + ((item * 2 + 1) * k + limb) * (size_t)n;
-    } else {
-        src0 = E + ((item * 2 + 0) * K + limb) * (size_t)n;
-        src1 = E + ((item * 2 + 1) * K + limb) * (size_t)n;
-    }
-    uint64_t *d0 = Dt + ((item * 3 + 0) * K + limb) * (size_t)n;
-    uint64_t *d1 = Dt + ((item * 3 + 1) * K + limb) * (size_t)n;
-    uint64_t *d2 = Dt + ((item * 3 + 2) * K + limb) * (size_t)n;
+    uint32_t task = PERSIST ? blockIdx.x : blockIdx.x + blockIdx.y * (uint32_t)K;
+    // rows a0 and a1 of a task (uniform: the task is the same in the whole workgroup)
+    auto rows_of = [&](uint32_t t, const uint64_t *&s0, const uint64_t *&s1) {
+        const int limb = (int)(t % (uint32_t)K);
+        const size_t item = t / (uint32_t)K;
+        if (limb < k) {
+            s0 = a + ((item * 2 + 0) * k + limb) * (size_t)n;
+            s1 = a + ((item * 2 + 1) * k + limb) * (size_t)n;
+        } else {
+            s0 = E + ((item * 2 + 0) * K + limb) * (size_t)n;
+            s1 = E + ((item * 2 + 1) * K + limb) * (size_t)n;
+        }
+    };
     uint64_t x[16], y[16];
-    const uint32_t t1 = fresh(tid);
+    {
+        const uint64_t *src0, *src1;
+        rows_of(task, src0, src1);
+        const uint32_t t1 = fresh(tid);
 #pragma unroll
-    for (int s = 0; s < 16; s++) x[s] = src1[natural_index<L>(t1, s)];
+        for (int s = 0; s < 16; s++) x[s] = src1[natural_index<L>(t1, s)];
 #pragma unroll
-    for (int s = 0; s < 16; s++) y[s] = src0[natural_index<L>(t1, s)];
-    asm volatile("" ::: "memory");
-    ntt_fwd_regs2<L, 4, !LZ>(x, y, lds, tid, tw, q);  // A1, A0
-    // d1 = 2 A0 A1 parked in d1; d0 = A0^2 in y, d2 = A1^2 in x (all below 4q)
-    const uint32_t t2 = fresh(tid);
-#pragma unroll
-    for (int s = 0; s < 16; s++) {
-        const uint64_t a1 = fwd_operand<LZ>(x[s], q, one_p);
-        const uint64_t a0 = fwd_operand<LZ>(y[s], q, one_p);
-        const uint64_t m = mont_mul_lazy_u(a0, a1, q, qi);
-        d1[bitrev_layout_index<L>(t2, s)] = m + m;
-        y[s] = mont_mul_lazy_u(a0, a0, q, qi);
-        x[s] = mont_mul_lazy_u(a1, a1, q, qi);
+        for (int s = 0; s < 16; s++) y[s] = src0[natural_index<L>(t1, s)];
     }
-    asm volatile("" ::: "memory");
-    ntt_inv_regs2<L, 4, LZ>(y, x, lds, tid, itw, q);
-    const uint32_t t3 = fresh(tid);
+    for (;;) {
+        const int limb = (int)(task % (uint32_t)K);
+        const size_t item = task / (uint32_t)K;
+        const PrimeConst &P = c.pc[limb];
+        const uint64_t q = P.q, qi = P.qinv_neg, one_p = P.one_p;
+        const Tw *tw = c.tw + (size_t)limb * n;
+        const Tw *itw = c.itw + (size_t)limb * n;
+        uint64_t *d0 = Dt + ((item * 3 + 0) * K + limb) * (size_t)n;
+        uint64_t *d1 = Dt + ((item * 3 + 1) * K + limb) * (size_t)n;
+        uint64_t *d2 = Dt + ((item * 3 + 2) * K + limb) * (size_t)n;
+        asm volatile("" ::: "memory");
+        ntt_fwd_regs2<L, 4, !LZ>(x, y, lds, tid, tw, q);  // A1, A0
+        // d1 = 2 A0 A1 parked in d1; d0 = A0^2 in y, d2 = A1^2 in x (all below 4q)
+        const uint32_t t2 = fresh(tid);
 #pragma unroll
-    for (int s = 0; s < 16; s++) d0[natural_index<L>(t3, s)] = mul_shoup_s(y[s], P.ninvm, P.ninvm_p, q);
-    // every thread rereads only the positions it parked
-    const uint32_t t4 = fresh(tid);
+        for (int s = 0; s < 16; s++) {
+            const uint64_t a1 = fwd_operand<LZ>(x[s], q, one_p);
+            const uint64_t a0 = fwd_operand<LZ>(y[s], q, one_p);
+            const uint64_t m = mont_mul_lazy_u(a0, a1, q, qi);
+            d1[bitrev_layout_index<L>(t2, s)] = m + m;
+            y[s] = mont_mul_lazy_u(a0, a0, q, qi);
+            x[s] = mont_mul_lazy_u(a1, a1, q, qi);
+        }
+        asm volatile("" ::: "memory");
+        ntt_inv_regs2<L, 4, LZ>(y, x, lds, tid, itw, q);
+        const uint32_t t3 = fresh(tid);
 #pragma unroll
-    for (int s = 0; s < 16; s++) y[s] = d1[bitrev_layout_index<L>(t4, s)];
-    const uint32_t t5 = fresh(tid);
+        for (int s = 0; s < 16; s++) d0[natural_index<L>(t3, s)] = mul_shoup_s(y[s], P.ninvm, P.ninvm_p, q);
+        // every thread rereads only the positions it parked
+        const uint32_t t4 = fresh(tid);
 #pragma unroll
-    for (int s = 0; s < 16; s++) d2[natural_index<L>(t5, s)] = mul_shoup_s(x[s], P.ninvm, P.ninvm_p, q);
-    asm volatile("" ::: "memory");
-    ntt_inv_regs<L, 4, LZ>(y, lds, tid, itw, q);
-    const uint32_t t6 = fresh(tid);
+        for (int s = 0; s < 16; s++) y[s] = d1[bitrev_layout_index<L>(t4, s)];
+        const uint32_t t5 = fresh(tid);
 #pragma unroll
-    for (int s = 0; s < 16; s++) d1[natural_index<L>(t6, s)] = mul_shoup_s(y[s], P.ninvm, P.ninvm_p, q);
+        for (int s = 0; s < 16; s++) d2[natural_index<L>(t5, s)] = mul_shoup_s(x[s], P.ninvm, P.ninvm_p, q);
+        asm volatile("" ::: "memory");
+        // x is free (d2 stored): the next task's a1 goes there; its a0 is
+        // loaded into y once y's row is stored
+        const uint32_t next = task + gridDim.x;
+        const bool more = PERSIST && next < tasks;
+        auto pre_next = [&]() {
+            if constexpr (PERSIST) {
+                if (more) {
+                    const uint64_t *src0, *src1;
+                    rows_of(next, src0, src1);
+                    const uint32_t tn = fresh(tid);
+#pragma unroll
+                    for (int s = 0; s < 16; s++) x[s] = src1[natural_index<L>(tn, s)];
+                }
+            }
+        };
+        ntt_inv_regs<L, 4, LZ>(y, lds, tid, itw, q, pre_next);
+        const uint32_t t6 = fresh(tid);
+#pragma unroll
+        for (int s = 0; s < 16; s++) d1[natural_index<L>(t6, s)] = mul_shoup_s(y[s], P.ninvm, P.ninvm_p, q);
+        if (!more) break;
+        {
+            const uint64_t *src0, *src1;
+            rows_of(next, src0, src1);
+            const uint32_t tn = fresh(tid);
+#pragma unroll
+            for (int s = 0; s < 16; s++) y[s] = src0[natural_index<L>(tn, s)];
+        }
+        task = next;
+    }
 }
 
 // Product of two operands both already transformed: grid (K limbs, items).
@@ -724,14 +767,37 @@ struct NttL {
                                Bhat, Dt);
         return hipGetLastError();
     }
+    template <bool LZ>
+    static hipError_t square_tensor_lz(const DevCtx &c, const uint64_t *a, const uint64_t *E, uint64_t *Dt,
+                                       size_t items, hipStream_t s) {
+        const uint32_t tasks = (uint32_t)(c.K * items);
+        if constexpr (Geo<L>::NPASS >= 3) {
+            // resident workgroups of the persistent kernel (same for both variants)
+            static int resident = 0;
+            if (resident == 0) {
+                int nb = 0, dev = 0, cus = 0;
+                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_square_tensor<L, LZ, true>, Geo<L>::T, 0) !=
+                        hipSuccess ||
+                    hipGetDevice(&dev) != hipSuccess ||
+                    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+                    nb < 1 || cus < 1)
+                    return hipErrorInvalidValue;
+                resident = nb * cus;
+            }
+            if (tasks > (uint32_t)resident) {
+                hipLaunchKernelGGL((k_square_tensor<L, LZ, true>), dim3((unsigned)resident), dim3(Geo<L>::T), 0, s,
+                                   c, a, E, Dt, tasks);
+                return hipGetLastError();
+            }
+        }
+        hipLaunchKernelGGL((k_square_tensor<L, LZ, false>), dim3(c.K, (unsigned)items), dim3(Geo<L>::T), 0, s, c, a,
+                           E, Dt, tasks);
+        return hipGetLastError();
+    }
     static hipError_t square_tensor(const DevCtx &c, const uint64_t *a, const uint64_t *E, uint64_t *Dt,
                                     size_t items, hipStream_t s) {
-        const dim3 grid(c.K, (unsigned)items);
-        if (c.lazy_all)
-            hipLaunchKernelGGL((k_square_tensor<L, true>), grid, dim3(Geo<L>::T), 0, s, c, a, E, Dt);
-        else
-            hipLaunchKernelGGL((k_square_tensor<L, false>), grid, dim3(Geo<L>::T), 0, s, c, a, E, Dt);
-        return hipGetLastError();
+        return c.lazy_all ? square_tensor_lz<true>(c, a, E, Dt, items, s)
+                          : square_tensor_lz<false>(c, a, E, Dt, items, s);
     }
     static hipError_t relin_fused(const DevCtx &c, const uint64_t *C2, const uint64_t *rlk, uint64_t *out,
                                   size_t items, hipStream_t s) {

@@ -266,13 +266,17 @@ __device__ __forceinline__ void fwd_from(uint64_t (&x)[1 << LE], uint64_t *lds, 
     }
 }
 
-template <int L, int LE, int P, bool SEMI>
+// Passes P..0 of the inverse transform.  hook() runs once, right after the
+// exchange into pass 1 (from there on, at n = 2^14, every twiddle is
+// wave-uniform: no vector-memory wait follows until the transform ends).
+template <int L, int LE, int P, bool SEMI, class Hook>
 __device__ __forceinline__ void inv_from(uint64_t (&x)[1 << LE], uint64_t *lds, int tid,
-                                         const Tw *__restrict__ tw, uint64_t q) {
+                                         const Tw *__restrict__ tw, uint64_t q, const Hook &hook) {
     inv_pass<L, LE, P, SEMI>(x, tid, tw, q);
     if constexpr (P > 0) {
         exchange<L, LE, P, P - 1>(lds, x, tid);
-        inv_from<L, LE, P - 1, SEMI>(x, lds, tid, tw, q);
+        if constexpr (P == 2) hook();
+        inv_from<L, LE, P - 1, SEMI>(x, lds, tid, tw, q, hook);
     }
 }
 
@@ -289,10 +293,11 @@ __device__ __forceinline__ void ntt_fwd_regs(uint64_t (&x)[1 << LE], uint64_t *l
 // Inverse transform (without the 1/n factor) of a row held in last-pass
 // layout, values < 4q.  Leaves natural order in pass-0 layout, values < 4q,
 // or < 8q with SEMI (for q < 2^60).
-template <int L, int LE = 4, bool SEMI = false>
+template <int L, int LE = 4, bool SEMI = false, class Hook = NoHook>
 __device__ __forceinline__ void ntt_inv_regs(uint64_t (&x)[1 << LE], uint64_t *lds, int tid,
-                                             const Tw *__restrict__ tw, uint64_t q) {
-    inv_from<L, LE, Geo<L, LE>::NPASS - 1, SEMI>(x, lds, (int)fresh(tid), tw, q);
+                                             const Tw *__restrict__ tw, uint64_t q,
+                                             const Hook &hook = Hook()) {
+    inv_from<L, LE, Geo<L, LE>::NPASS - 1, SEMI>(x, lds, (int)fresh(tid), tw, q, hook);
 }
 
 // ---- two rows of the same prime at once --------------------------------
