@@ -480,6 +480,29 @@ def test_mul_relin_n16384_batched_equals_single(dev):
     assert (down(ctx.mul_relin(rlk_d, da, db)) == batched).all()
 
 
+@pytest.mark.parametrize("cfg_name,count", [("bfv_n16384", 17), ("bfv_n8192", 57), ("bfv_n4096", 181)])
+def test_squaring_resident_grid_ragged(dev, cfg_name, count):
+    """Squarings whose (item, limb) tasks outnumber the workgroups the chip
+    holds, by a count that is not a multiple of them: the squaring kernel's
+    resident grid, where some workgroups take one task more than others and
+    load each next task's rows during the previous one.  Every word of the
+    batched call equals the same squaring done one ciphertext per call (one
+    task per workgroup), and the first and last items equal the oracle."""
+    cfg = inputs.CONFIGS[cfg_name]
+    n, qs, t = cfg["n"], cfg["q"], cfg["t"]
+    P, km, pk, rlk, ctx, rlk_d = setup(n, qs, t, "slots", 5)
+    K = len(qs) + ctx.aux_primes
+    say(f"squaring resident grid n={n} K={K} x{count} ({K * count} tasks)")
+    a = inputs.uniform_ciphertexts(n, qs, count, 5, "a")
+    da = up(a)
+    batched = down(ctx.mul_relin(rlk_d, da, da))
+    for j in range(count):
+        dj = up(a[j:j + 1])
+        assert (down(ctx.mul_relin(rlk_d, dj, dj))[0] == batched[j]).all(), f"item {j}"
+    for j in (0, count - 1):
+        assert (batched[j] == bfv.mul_relin(P, a[j], a[j], rlk)).all(), f"oracle item {j}"
+
+
 # ----------------------------------------------------------- elementwise ----
 
 def test_elementwise_ops(dev):
