@@ -210,124 +210,160 @@ __device__ __forceinline__ uint64_t fwd_operand(uint64_t v, uint64_t q, uint64_t
     else return csub(csub(v, q << 2), q << 1);
 }
 
-// Product of two ciphertexts, transform phase fused: grid (K limbs, items).
-// For limb l of item it transforms a0, a1, b0, b1 (Q limbs from the inputs, P
-// limbs from the lift in E), forms d0 = a0 b0, d1 = a0 b1 + a1 b0, d2 = a1 b1
-// (Montgomery products) and inverse transforms each into Dt[item][comp][l].
-// Two rows live in registers; A1, a1 b1 and a0 b1 are parked (transform
-// domain) in the item's own output rows, which this workgroup alone touches.
-// With whole waves, each of a0 and b0 is copied into LDS while the transform
-// before it finishes (prefetch_row_lds).
-template <int L, bool LZ>
+// Product of two ciphertexts, transform phase fused: one task per (item,
+// limb l), task = l + K item.  For limb l of item it transforms a0, a1, b0, b1
+// (Q limbs from the inputs, P limbs from the lift in E), forms d0 = a0 b0, d1 =
+// a0 b1 + a1 b0, d2 = a1 b1 (Montgomery products) and inverse transforms each
+// into Dt[item][comp][l].  Two rows live in registers; A1, a1 b1 and a0 b1 are
+// parked (transform domain) in the item's own output rows, which this task
+// alone touches.  With whole waves, each of a0 and b0 is copied into LDS while
+// the transform before it finishes (prefetch_row_lds).  PERSIST: a resident
+// grid takes the tasks blockIdx.x, blockIdx.x + gridDim.x, ... and loads the
+// next task's b1 row into the free registers of y during the last inverse
+// transform (after its last vector-memory twiddle load), its a1 row right
+// after the last store.  Otherwise grid (K, items), one task per workgroup.
+template <int L, bool LZ, bool PERSIST>
 __global__ __launch_bounds__(Geo<L>::T) void k_mul_tensor(DevCtx c, const uint64_t *__restrict__ a,
                                                          const uint64_t *__restrict__ b,
                                                          const uint64_t *__restrict__ E,
-                                                         uint64_t *__restrict__ Dt) {
+                                                         uint64_t *__restrict__ Dt, uint32_t tasks) {
+    static_assert(!PERSIST || Geo<L>::NPASS >= 3, "the next task's rows load from the pass-2 exchange hook");
     __shared__ uint64_t lds[Geo<L>::lds_words];
     constexpr int n = Geo<L>::N;
     constexpr bool PREFETCH = Geo<L>::T >= 64;
     const uint32_t tid = threadIdx.x;
-    const int limb = blockIdx.x;
-    const size_t item = blockIdx.y;
     const int k = c.k, K = c.K;
-    const PrimeConst &P = c.pc[limb];
-    const uint64_t q = P.q, qi = P.qinv_neg, one_p = P.one_p;
-    const Tw *tw = c.tw + (size_t)limb * n;
-    const Tw *itw = c.itw + (size_t)limb * n;
-    const uint64_t *src[4];
-#pragma unroll
-    for (int poly = 0; poly < 4; poly++)
-        src[poly] = limb < k ? (poly < 2 ? a + ((item * 2 + poly) * k + limb) * (size_t)n
-                                         : b + ((item * 2 + poly - 2) * k + limb) * (size_t)n)
-                             : E + ((item * 4 + poly) * K + limb) * (size_t)n;
-    uint64_t *d0 = Dt + ((item * 3 + 0) * K + limb) * (size_t)n;
-    uint64_t *d1 = Dt + ((item * 3 + 1) * K + limb) * (size_t)n;
-    uint64_t *d2 = Dt + ((item * 3 + 2) * K + limb) * (size_t)n;
+    uint32_t task = PERSIST ? blockIdx.x : blockIdx.x + blockIdx.y * (uint32_t)K;
+    // row poly of a task: a0, a1 (Q limbs from a), b0, b1 (from b); P limbs from E
+    auto row_of = [&](uint32_t t, int poly) {
+        const int limb = (int)(t % (uint32_t)K);
+        const size_t item = t / (uint32_t)K;
+        return limb < k ? (poly < 2 ? a + ((item * 2 + poly) * k + limb) * (size_t)n
+                                    : b + ((item * 2 + poly - 2) * k + limb) * (size_t)n)
+                        : E + ((item * 4 + poly) * K + limb) * (size_t)n;
+    };
     uint64_t x[16], y[16];
-    // A1 and B1
-    const uint32_t t0 = fresh(tid);
+    {  // A1 and B1 of the first task
+        const uint64_t *s1 = row_of(task, 1), *s3 = row_of(task, 3);
+        const uint32_t t0 = fresh(tid);
 #pragma unroll
-    for (int s = 0; s < 16; s++) x[s] = src[1][natural_index<L>(t0, s)];
+        for (int s = 0; s < 16; s++) x[s] = s1[natural_index<L>(t0, s)];
 #pragma unroll
-    for (int s = 0; s < 16; s++) y[s] = src[3][natural_index<L>(t0, s)];
-    asm volatile("" ::: "memory");
-    ntt_fwd_regs<L, 4, !LZ>(x, lds, tid, tw, q);
-    auto pre_a0 = [&]() {
-        if constexpr (PREFETCH) prefetch_row_lds<L>(lds, src[0], fresh(tid));
-    };
-    ntt_fwd_regs<L, 4, !LZ>(y, lds, tid, tw, q, pre_a0);
-    // park A1 in d1 and a1 b1 in d2; B1 stays in y
-    const uint32_t t1 = fresh(tid);
-#pragma unroll
-    for (int s = 0; s < 16; s++) {
-        const uint32_t idx = bitrev_layout_index<L>(t1, s);
-        const uint64_t a1 = fwd_operand<LZ>(x[s], q, one_p);
-        y[s] = fwd_operand<LZ>(y[s], q, one_p);
-        d1[idx] = a1;
-        d2[idx] = mont_mul_lazy_u(a1, y[s], q, qi);
+        for (int s = 0; s < 16; s++) y[s] = s3[natural_index<L>(t0, s)];
     }
-    asm volatile("" ::: "memory");
-    // A0
-    const uint32_t t2 = fresh(tid);
-    if (PREFETCH) {
-        prefetch_wait();
+    for (;;) {
+        const int limb = (int)(task % (uint32_t)K);
+        const size_t item = task / (uint32_t)K;
+        const PrimeConst &P = c.pc[limb];
+        const uint64_t q = P.q, qi = P.qinv_neg, one_p = P.one_p;
+        const Tw *tw = c.tw + (size_t)limb * n;
+        const Tw *itw = c.itw + (size_t)limb * n;
+        const uint64_t *src[4];
 #pragma unroll
-        for (int s = 0; s < 16; s++) x[s] = prefetched(lds, t2, s);
-    } else {
+        for (int poly = 0; poly < 4; poly++) src[poly] = row_of(task, poly);
+        uint64_t *d0 = Dt + ((item * 3 + 0) * K + limb) * (size_t)n;
+        uint64_t *d1 = Dt + ((item * 3 + 1) * K + limb) * (size_t)n;
+        uint64_t *d2 = Dt + ((item * 3 + 2) * K + limb) * (size_t)n;
+        asm volatile("" ::: "memory");
+        ntt_fwd_regs<L, 4, !LZ>(x, lds, tid, tw, q);
+        auto pre_a0 = [&]() {
+            if constexpr (PREFETCH) prefetch_row_lds<L>(lds, src[0], fresh(tid));
+        };
+        ntt_fwd_regs<L, 4, !LZ>(y, lds, tid, tw, q, pre_a0);
+        // park A1 in d1 and a1 b1 in d2; B1 stays in y
+        const uint32_t t1 = fresh(tid);
 #pragma unroll
-        for (int s = 0; s < 16; s++) x[s] = src[0][natural_index<L>(t2, s)];
+        for (int s = 0; s < 16; s++) {
+            const uint32_t idx = bitrev_layout_index<L>(t1, s);
+            const uint64_t a1 = fwd_operand<LZ>(x[s], q, one_p);
+            y[s] = fwd_operand<LZ>(y[s], q, one_p);
+            d1[idx] = a1;
+            d2[idx] = mont_mul_lazy_u(a1, y[s], q, qi);
+        }
+        asm volatile("" ::: "memory");
+        // A0
+        const uint32_t t2 = fresh(tid);
+        if (PREFETCH) {
+            prefetch_wait();
+#pragma unroll
+            for (int s = 0; s < 16; s++) x[s] = prefetched(lds, t2, s);
+        } else {
+#pragma unroll
+            for (int s = 0; s < 16; s++) x[s] = src[0][natural_index<L>(t2, s)];
+        }
+        auto pre_b0 = [&]() {
+            if constexpr (PREFETCH) prefetch_row_lds<L>(lds, src[2], fresh(tid));
+        };
+        ntt_fwd_regs<L, 4, !LZ>(x, lds, tid, tw, q, pre_b0);
+        // park a0 b1 in d0; A0 stays in x
+        const uint32_t t3 = fresh(tid);
+#pragma unroll
+        for (int s = 0; s < 16; s++) {
+            x[s] = fwd_operand<LZ>(x[s], q, one_p);
+            d0[bitrev_layout_index<L>(t3, s)] = mont_mul_lazy_u(x[s], y[s], q, qi);
+        }
+        asm volatile("" ::: "memory");
+        // B0
+        const uint32_t t4 = fresh(tid);
+        if (PREFETCH) {
+            prefetch_wait();
+#pragma unroll
+            for (int s = 0; s < 16; s++) y[s] = prefetched(lds, t4, s);
+        } else {
+#pragma unroll
+            for (int s = 0; s < 16; s++) y[s] = src[2][natural_index<L>(t4, s)];
+        }
+        ntt_fwd_regs<L, 4, !LZ>(y, lds, tid, tw, q);
+        // d0 = a0 b0 in x, d1 = a1 b0 + a0 b1 in y (every thread rereads only the
+        // positions it parked)
+        const uint32_t t5 = fresh(tid);
+#pragma unroll
+        for (int s = 0; s < 16; s++) {
+            const uint32_t idx = bitrev_layout_index<L>(t5, s);
+            const uint64_t b0 = fwd_operand<LZ>(y[s], q, one_p);
+            y[s] = mont_mul_lazy_u(d1[idx], b0, q, qi) + d0[idx];  // < 4q
+            x[s] = mont_mul_lazy_u(x[s], b0, q, qi);
+        }
+        asm volatile("" ::: "memory");
+        ntt_inv_regs<L, 4, LZ>(x, lds, tid, itw, q);
+        const uint32_t t6 = fresh(tid);
+#pragma unroll
+        for (int s = 0; s < 16; s++) d0[natural_index<L>(t6, s)] = mul_shoup_s(x[s], P.ninvm, P.ninvm_p, q);
+        // d2's parked product, read while d1 is transformed
+        const uint32_t t7 = fresh(tid);
+#pragma unroll
+        for (int s = 0; s < 16; s++) x[s] = d2[bitrev_layout_index<L>(t7, s)];
+        asm volatile("" ::: "memory");
+        ntt_inv_regs<L, 4, LZ>(y, lds, tid, itw, q);
+        const uint32_t t8 = fresh(tid);
+#pragma unroll
+        for (int s = 0; s < 16; s++) d1[natural_index<L>(t8, s)] = mul_shoup_s(y[s], P.ninvm, P.ninvm_p, q);
+        // y is free (d1 stored): the next task's b1 goes there
+        const uint32_t next = task + gridDim.x;
+        const bool more = PERSIST && next < tasks;
+        auto pre_next = [&]() {
+            if constexpr (PERSIST) {
+                if (more) {
+                    const uint64_t *s3 = row_of(next, 3);
+                    const uint32_t tn = fresh(tid);
+#pragma unroll
+                    for (int s = 0; s < 16; s++) y[s] = s3[natural_index<L>(tn, s)];
+                }
+            }
+        };
+        ntt_inv_regs<L, 4, LZ>(x, lds, tid, itw, q, pre_next);
+        const uint32_t t9 = fresh(tid);
+#pragma unroll
+        for (int s = 0; s < 16; s++) d2[natural_index<L>(t9, s)] = mul_shoup_s(x[s], P.ninvm, P.ninvm_p, q);
+        if (!more) break;
+        {
+            const uint64_t *s1 = row_of(next, 1);
+            const uint32_t tn = fresh(tid);
+#pragma unroll
+            for (int s = 0; s < 16; s++) x[s] = s1[natural_index<L>(tn, s)];
+        }
+        task = next;
     }
-    auto pre_b0 = [&]() {
-        if constexpr (PREFETCH) prefetch_row_lds<L>(lds, src[2], fresh(tid));
-    };
-    ntt_fwd_regs<L, 4, !LZ>(x, lds, tid, tw, q, pre_b0);
-    // park a0 b1 in d0; A0 stays in x
-    const uint32_t t3 = fresh(tid);
-#pragma unroll
-    for (int s = 0; s < 16; s++) {
-        x[s] = fwd_operand<LZ>(x[s], q, one_p);
-        d0[bitrev_layout_index<L>(t3, s)] = mont_mul_lazy_u(x[s], y[s], q, qi);
-    }
-    asm volatile("" ::: "memory");
-    // B0
-    const uint32_t t4 = fresh(tid);
-    if (PREFETCH) {
-        prefetch_wait();
-#pragma unroll
-        for (int s = 0; s < 16; s++) y[s] = prefetched(lds, t4, s);
-    } else {
-#pragma unroll
-        for (int s = 0; s < 16; s++) y[s] = src[2][natural_index<L>(t4, s)];
-    }
-    ntt_fwd_regs<L, 4, !LZ>(y, lds, tid, tw, q);
-    // d0 = a0 b0 in x, d1 = a1 b0 + a0 b1 in y (every thread rereads only the
-    // positions it parked)
-    const uint32_t t5 = fresh(tid);
-#pragma unroll
-    for (int s = 0; s < 16; s++) {
-        const uint32_t idx = bitrev_layout_index<L>(t5, s);
-        const uint64_t b0 = fwd_operand<LZ>(y[s], q, one_p);
-        y[s] = mont_mul_lazy_u(d1[idx], b0, q, qi) + d0[idx];  // < 4q
-        x[s] = mont_mul_lazy_u(x[s], b0, q, qi);
-    }
-    asm volatile("" ::: "memory");
-    ntt_inv_regs<L, 4, LZ>(x, lds, tid, itw, q);
-    const uint32_t t6 = fresh(tid);
-#pragma unroll
-    for (int s = 0; s < 16; s++) d0[natural_index<L>(t6, s)] = mul_shoup_s(x[s], P.ninvm, P.ninvm_p, q);
-    // d2's parked product, read while d1 is transformed
-    const uint32_t t7 = fresh(tid);
-#pragma unroll
-    for (int s = 0; s < 16; s++) x[s] = d2[bitrev_layout_index<L>(t7, s)];
-    asm volatile("" ::: "memory");
-    ntt_inv_regs<L, 4, LZ>(y, lds, tid, itw, q);
-    const uint32_t t8 = fresh(tid);
-#pragma unroll
-    for (int s = 0; s < 16; s++) d1[natural_index<L>(t8, s)] = mul_shoup_s(y[s], P.ninvm, P.ninvm_p, q);
-    ntt_inv_regs<L, 4, LZ>(x, lds, tid, itw, q);
-    const uint32_t t9 = fresh(tid);
-#pragma unroll
-    for (int s = 0; s < 16; s++) d2[natural_index<L>(t9, s)] = mul_shoup_s(x[s], P.ninvm, P.ninvm_p, q);
 }
 
 // Squaring, transform phase fused: one task per (item, limb l), task = l + K
@@ -747,14 +783,36 @@ struct NttL {
         else tensor_sq<false>(c, E, Dt, items, s);
         return hipGetLastError();
     }
+    template <bool LZ>
+    static hipError_t mul_tensor_lz(const DevCtx &c, const uint64_t *a, const uint64_t *b, const uint64_t *E,
+                                    uint64_t *Dt, size_t items, hipStream_t s) {
+        const uint32_t tasks = (uint32_t)(c.K * items);
+        if constexpr (Geo<L>::NPASS >= 3) {
+            static int resident = 0;  // workgroups of the resident grid the chip holds
+            if (resident == 0) {
+                int nb = 0, dev = 0, cus = 0;
+                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_mul_tensor<L, LZ, true>, Geo<L>::T, 0) !=
+                        hipSuccess ||
+                    hipGetDevice(&dev) != hipSuccess ||
+                    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+                    nb < 1 || cus < 1)
+                    return hipErrorInvalidValue;
+                resident = nb * cus;
+            }
+            if (tasks > (uint32_t)resident) {
+                hipLaunchKernelGGL((k_mul_tensor<L, LZ, true>), dim3((unsigned)resident), dim3(Geo<L>::T), 0, s, c,
+                                   a, b, E, Dt, tasks);
+                return hipGetLastError();
+            }
+        }
+        hipLaunchKernelGGL((k_mul_tensor<L, LZ, false>), dim3(c.K, (unsigned)items), dim3(Geo<L>::T), 0, s, c, a, b,
+                           E, Dt, tasks);
+        return hipGetLastError();
+    }
     static hipError_t mul_tensor(const DevCtx &c, const uint64_t *a, const uint64_t *b, const uint64_t *E,
                                  uint64_t *Dt, size_t items, hipStream_t s) {
-        const dim3 grid(c.K, (unsigned)items);
-        if (c.lazy_all)
-            hipLaunchKernelGGL((k_mul_tensor<L, true>), grid, dim3(Geo<L>::T), 0, s, c, a, b, E, Dt);
-        else
-            hipLaunchKernelGGL((k_mul_tensor<L, false>), grid, dim3(Geo<L>::T), 0, s, c, a, b, E, Dt);
-        return hipGetLastError();
+        return c.lazy_all ? mul_tensor_lz<true>(c, a, b, E, Dt, items, s)
+                          : mul_tensor_lz<false>(c, a, b, E, Dt, items, s);
     }
     static hipError_t mul_tensor_pre2(const DevCtx &c, const uint64_t *Ahat, int na, size_t item0,
                                       const uint64_t *Bhat, uint64_t *Dt, size_t items, hipStream_t s) {

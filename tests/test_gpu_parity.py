@@ -481,26 +481,31 @@ def test_mul_relin_n16384_batched_equals_single(dev):
 
 
 @pytest.mark.parametrize("cfg_name,count", [("bfv_n16384", 17), ("bfv_n8192", 57), ("bfv_n4096", 181)])
-def test_squaring_resident_grid_ragged(dev, cfg_name, count):
-    """Squarings whose (item, limb) tasks outnumber the workgroups the chip
-    holds, by a count that is not a multiple of them: the squaring kernel's
-    resident grid, where some workgroups take one task more than others and
-    load each next task's rows during the previous one.  Every word of the
-    batched call equals the same squaring done one ciphertext per call (one
-    task per workgroup), and the first and last items equal the oracle."""
+def test_products_resident_grid_ragged(dev, cfg_name, count):
+    """Squarings and products whose (item, limb) tasks outnumber the
+    workgroups the chip holds, by a count that is not a multiple of them: the
+    resident grids of the squaring and product kernels, where some workgroups
+    take one task more than others and load each next task's rows during the
+    previous one.  Every word of the batched calls equals the same squaring or
+    product done one ciphertext per call (one task per workgroup, or the
+    unfused kernels), and the first and last items equal the oracle."""
     cfg = inputs.CONFIGS[cfg_name]
     n, qs, t = cfg["n"], cfg["q"], cfg["t"]
     P, km, pk, rlk, ctx, rlk_d = setup(n, qs, t, "slots", 5)
     K = len(qs) + ctx.aux_primes
-    say(f"squaring resident grid n={n} K={K} x{count} ({K * count} tasks)")
+    say(f"resident grids n={n} K={K} x{count} ({K * count} tasks)")
     a = inputs.uniform_ciphertexts(n, qs, count, 5, "a")
-    da = up(a)
-    batched = down(ctx.mul_relin(rlk_d, da, da))
+    b = inputs.uniform_ciphertexts(n, qs, count, 5, "b")
+    da, db = up(a), up(b)
+    sq = down(ctx.mul_relin(rlk_d, da, da))
+    pr = down(ctx.mul_relin(rlk_d, da, db))
     for j in range(count):
-        dj = up(a[j:j + 1])
-        assert (down(ctx.mul_relin(rlk_d, dj, dj))[0] == batched[j]).all(), f"item {j}"
+        dj, ej = up(a[j:j + 1]), up(b[j:j + 1])
+        assert (down(ctx.mul_relin(rlk_d, dj, dj))[0] == sq[j]).all(), f"square {j}"
+        assert (down(ctx.mul_relin(rlk_d, dj, ej))[0] == pr[j]).all(), f"product {j}"
     for j in (0, count - 1):
-        assert (batched[j] == bfv.mul_relin(P, a[j], a[j], rlk)).all(), f"oracle item {j}"
+        assert (sq[j] == bfv.mul_relin(P, a[j], a[j], rlk)).all(), f"oracle square {j}"
+        assert (pr[j] == bfv.mul_relin(P, a[j], b[j], rlk)).all(), f"oracle product {j}"
 
 
 # ----------------------------------------------------------- elementwise ----
